@@ -1,0 +1,405 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the passage it pins. None of them re-types an oracle formula: they check the
+oracle against closed forms (Poiseuille, Hartmann, Gold), exact identities (mass, momentum
+bookkeeping, symmetry), textbook definitions (Lagrange interpolation, Fourier symbols) and fixed
+points written with independent numpy finite-difference operators.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import gold
+from tests import fdops
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _threads():
+    oracle.set_threads(8)
+    yield
+
+
+# --------------------------------------------------------------------------------------------
+# Immersed boundary kernel and row sums (Sec. 5.2, Sec. 5.3)
+# --------------------------------------------------------------------------------------------
+
+def lagrange_basis(X):
+    """Textbook quadratic Lagrange basis on the three nodes nearest to X."""
+    n0 = math.floor(X + 0.5)
+    nodes = [n0 - 1, n0, n0 + 1]
+    w = []
+    for t, nt in enumerate(nodes):
+        v = 1.0
+        for s, ns in enumerate(nodes):
+            if s != t:
+                v *= (X - ns) / (nt - ns)
+        w.append(v)
+    return n0 - 1, np.array(w)
+
+
+@pytest.mark.parametrize("X", [3.0, 3.3, 3.49, 2.5, 7.77, 0.5, 10.25, 5.999])
+def test_lagrange_kernel_is_quadratic_lagrange_interpolation(X):
+    base, w = oracle.lagrange3(X)
+    base_ref, w_ref = lagrange_basis(X)
+    assert base == base_ref
+    np.testing.assert_allclose(w, w_ref, rtol=0, atol=1e-15)
+    nodes = base + np.arange(3)
+    # exact on polynomials of degree <= 2
+    for coef in ([1, 0, 0], [0.3, -1.7, 0], [2.0, 0.5, -0.25]):
+        f = lambda x: coef[0] + coef[1] * x + coef[2] * x * x
+        assert abs(np.dot(w, f(nodes.astype(float))) - f(X)) < 1e-12
+
+
+def test_lagrange_kernel_on_a_node_is_a_delta():
+    base, w = oracle.lagrange3(6.0)
+    assert base == 5 and list(w) == [0.0, 1.0, 0.0]
+
+
+def _dense_D(nx, ny, nz, X):
+    """Dense interpolation matrix D (M x N) from the textbook basis (periodic indexing)."""
+    M = X.shape[1]
+    D = np.zeros((M, nx * ny * nz))
+    for j in range(M):
+        bx, wx = lagrange_basis(X[0, j])
+        by, wy = lagrange_basis(X[1, j])
+        bz, wz = lagrange_basis(X[2, j])
+        for c in range(3):
+            for b in range(3):
+                for a in range(3):
+                    k = ((bx + a) % nx) + nx * (((by + b) % ny) + ny * ((bz + c) % nz))
+                    D[j, k] += wx[a] * wy[b] * wz[c]
+    return D
+
+
+def test_rowsums_match_dense_DDt():
+    nx, ny, nz = 3, 14, 14
+    p = oracle.make_params(nx, ny, nz)
+    X = W.pipe_markers(nx, 4.3, 7.0, 7.0, m_slice=27)
+    X[0] += np.array([0.0, 0.25, 0.5])[np.arange(X.shape[1]) % 3]  # some off-plane markers too
+    D = _dense_D(nx, ny, nz, X)
+    d_ref = (D @ D.T).sum(axis=1)
+    np.testing.assert_allclose(oracle.ib_rowsums(p, X), d_ref, rtol=1e-13)
+
+
+def test_isolated_markers_enforce_wall_value_exactly():
+    # For a marker whose support meets no other marker, A = D D^T is diagonal, the explicit
+    # correction with lambda = 1 is the exact least-squares solve and D u = U_b afterwards.
+    nx, ny, nz = 12, 12, 12
+    p = oracle.make_params(nx, ny, nz)
+    X = np.array([[2.3, 8.1], [3.7, 8.6], [4.45, 2.2]])
+    g = W.rng_for(100)
+    phi = g.normal(size=(3, nz, ny, nx))
+    wall = g.normal(size=(3, 2))
+    d = oracle.ib_rowsums(p, X)
+    out = oracle.ib_correct(p, X, d, 1.0, phi, wall)
+    D = _dense_D(nx, ny, nz, X)
+    np.testing.assert_allclose(D @ out.reshape(3, -1).T, wall.T, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.7, 36.0])
+def test_markers_on_nodes_are_exact_for_any_lambda(lam):
+    nx, ny, nz = 4, 10, 3
+    p = oracle.make_params(nx, ny, nz)
+    X = W.plane_wall_markers(nx, nz, 6.0)
+    d = oracle.ib_rowsums(p, X)
+    np.testing.assert_array_equal(d, np.ones(X.shape[1]))
+    phi = W.rng_for(101).normal(size=(3, nz, ny, nx))
+    out = oracle.ib_correct(p, X, d, lam, phi)
+    np.testing.assert_array_equal(out[:, :, 6, :], 0.0)
+    keep = np.ones(ny, bool)
+    keep[6] = False
+    np.testing.assert_array_equal(out[:, :, keep, :], phi[:, :, keep, :])
+
+
+# --------------------------------------------------------------------------------------------
+# Magnetic iteration (Sec. 5.7)
+# --------------------------------------------------------------------------------------------
+
+def test_magnetic_sweep_symbol_is_the_lattice_average():
+    # u = 0: one tau_m = 1 sweep multiplies a lattice Fourier mode by sum_i w_i cos(k.e_i),
+    # the D3Q19 averaging symbol, whose minimum 1/9 makes the plain sweep a contraction.
+    n = 8
+    p = oracle.make_params(n, n, n, eta=3.0)
+    x = np.arange(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = np.zeros((3, n, n, n))
+    for (kx, ky, kz) in [(1, 0, 0), (2, 3, 0), (4, 4, 0), (1, 2, 3), (4, 4, 4), (0, 4, 4)]:
+        k = 2 * np.pi * np.array([kx, ky, kz]) / n
+        mode = np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+        b = np.stack([mode, 0.5 * mode, -mode])
+        out = oracle.mag_sweep(p, u, b)
+        cx, cy, cz = np.cos(k)
+        symbol = 1 / 3 + (cx + cy + cz) / 9 + (cx * cy + cx * cz + cy * cz) / 9
+        np.testing.assert_allclose(out, symbol * b, atol=1e-14)
+        assert symbol >= 1 / 9 - 1e-15
+
+
+def test_magnetic_fixed_point_solves_qs_poisson_equation():
+    # The iteration's steady state satisfies eta lap b = div(u B - B u), B = B_ext + b
+    # (asymptotic limit stated in Sec. 5.7), with the isotropic operators.
+    n = 8
+    eta = 2.0
+    p = oracle.make_params(n, n, n, eta=eta, bext_kind=W.BEXT_UNIFORM_Y, B0=1.0)
+    x = 2 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = 0.05 * np.stack([np.sin(Y) * np.cos(Z), np.cos(X + 2 * Z), np.sin(X - Y)])
+    b = np.zeros((3, n, n, n))
+    for _ in range(600):
+        b = oracle.mag_sweep(p, u, b)
+    B = b.copy()
+    B[1] += 1.0
+    res = eta * np.stack([fdops.lap(b[a]) for a in range(3)]) - fdops.div_flux(u, B)
+    scale = np.abs(fdops.div_flux(u, B)).max()
+    assert np.abs(res).max() <= 1e-10 * scale
+
+
+def test_magnetic_sweep_conserves_the_mean_field():
+    n = 6
+    p = oracle.make_params(n, n, n, eta=1.5, bext_kind=W.BEXT_UNIFORM_Y, B0=0.7)
+    g = W.rng_for(102)
+    u = 0.05 * g.normal(size=(3, n, n, n))
+    b = 0.01 * g.normal(size=(3, n, n, n))
+    out = oracle.mag_sweep(p, u, b)
+    np.testing.assert_allclose(out.sum(axis=(1, 2, 3)), b.sum(axis=(1, 2, 3)), atol=1e-14)
+
+
+# --------------------------------------------------------------------------------------------
+# Fluid update (Sec. 3.3, Sec. 5.1): conservation and the discrete-effect term
+# --------------------------------------------------------------------------------------------
+
+def _random_state(n, key, F_mean=1e-4):
+    g = W.rng_for(key)
+    rho = 1.0 + 0.01 * g.uniform(-1, 1, size=(n, n, n))
+    u = 0.05 * g.uniform(-1, 1, size=(3, n, n, n))
+    F = F_mean * (1.0 + g.uniform(-1, 1, size=(3, n, n, n)))
+    return rho, u, F
+
+
+def test_density_update_conserves_mass_exactly():
+    rho, u, F = _random_state(7, 103)
+    p = oracle.make_params(7, 7, 7, nu=0.05)
+    r2, _ = oracle.fluid(p, rho, u, F)
+    assert abs(r2.sum() - rho.sum()) <= 1e-13 * rho.sum()
+
+
+def test_momentum_update_adds_exactly_the_body_force():
+    # Without walls every gathered term telescopes on the periodic grid:
+    # sum rho' u* - sum rho u = sum F.
+    rho, u, F = _random_state(7, 104)
+    for nu in (0.01, 0.1, 0.15):
+        p = oracle.make_params(7, 7, 7, nu=nu)
+        r2, u2 = oracle.fluid(p, rho, u, F)
+        lhs = (r2 * u2).sum(axis=(1, 2, 3)) - (rho * u).sum(axis=(1, 2, 3))
+        np.testing.assert_allclose(lhs, F.sum(axis=(1, 2, 3)), rtol=1e-12)
+
+
+def test_discrete_effect_term_converges_to_its_continuum_form():
+    # -(tau/2) sum_i e_i [F_i(x+e_i) - F_i(x-e_i)] -> -(tau - 1/2) div(u F + F u), second order.
+    nu = 0.05
+    tau = 3 * nu + 0.5
+    errs = []
+    for n in (16, 32, 64):
+        h = 2 * np.pi / n
+        x = h * np.arange(n)
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        u = 0.05 * np.stack([np.sin(Y + Z), np.cos(X) * np.sin(Z), np.sin(X + Y)])
+        F = 1e-3 * np.stack([np.cos(Z), np.sin(X), np.cos(Y + X)])
+        rho = np.ones((n, n, n))
+        p = oracle.make_params(n, n, n, nu=nu)
+        r_F, u_F = oracle.fluid(p, rho, u, F)
+        r_0, u_0 = oracle.fluid(p, rho, u, np.zeros_like(F))
+        term = r_F * u_F - r_0 * u_0 - F
+        # continuum value with spectral derivatives of the smooth products
+        k = np.fft.fftfreq(n, d=1.0 / n)
+        def d(f, axis):
+            # spectral derivative, converted to lattice units (dx = 1 <-> physical h)
+            shape = [1, 1, 1]
+            shape[axis] = n
+            return np.real(np.fft.ifftn(1j * k.reshape(shape) * np.fft.fftn(f))) * h
+        axes = {0: 2, 1: 1, 2: 0}  # component index -> array axis
+        cont = np.zeros_like(u)
+        for a in range(3):
+            for c in range(3):
+                cont[a] += d(u[a] * F[c] + F[a] * u[c], axes[c])
+        cont *= -(tau - 0.5)
+        errs.append(np.abs(term - cont).max() / np.abs(cont).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) >= 1.9, (errs, orders)
+
+
+# --------------------------------------------------------------------------------------------
+# Closed forms: plane Poiseuille (B = 0) and plane Hartmann (uniform B normal to the walls)
+# --------------------------------------------------------------------------------------------
+
+def _plane_channel(ny, yc, a, **kw):
+    X = np.concatenate([W.plane_wall_markers(1, 1, yc - a), W.plane_wall_markers(1, 1, yc + a)], 1)
+    p = oracle.make_params(1, ny, 1, yc=float(yc), zc=0.0, radius=float(a), **kw)
+    return p, X
+
+
+def test_plane_poiseuille_is_exact():
+    # Walls on lattice nodes (D = delta, d = 1): the steady discrete state is the parabola
+    # G (a^2 - y^2) / (2 nu), exactly.
+    oracle.set_threads(1)
+    ny, yc, a, nu, G = 24, 12, 8, 0.1, 1e-5
+    p, X = _plane_channel(ny, yc, a, nu=nu, eta=1.0, n_mag=1, G0=G)
+    y = np.arange(ny) - yc
+    u0 = np.zeros((3, 1, ny, 1))
+    u0[0, 0, :, 0] = gold.plane_poiseuille_u(y, a, nu, G) * 0.9
+    o = oracle.Oracle(p, X, u=u0)
+    o.step(6000)
+    inside = np.abs(y) <= a
+    ref = gold.plane_poiseuille_u(y[inside], a, nu, G)
+    got = o.u[0, 0, inside, 0]
+    assert np.abs(got - ref).max() <= 1e-10 * ref.max()
+    assert np.abs(o.u[1:]).max() <= 1e-14
+    assert np.abs(o.rho - 1.0).max() <= 1e-12  # 6000 steps of round-off
+    oracle.set_threads(8)
+
+
+def _hartmann_fd(a, nu, eta, B0, G):
+    """Steady 3-point finite-difference system nu u'' + B0 b' + G = 0, eta b'' + B0 u' = 0,
+    u = b = 0 at y = +-a (central differences)."""
+    n = 2 * a - 1
+    A = np.zeros((2 * n, 2 * n))
+    rhs = np.zeros(2 * n)
+    for i in range(n):
+        for (off, cu, cb) in ((-1, nu, -0.5 * B0), (0, -2 * nu, 0.0), (1, nu, 0.5 * B0)):
+            j = i + off
+            if 0 <= j < n:
+                A[i, j] += cu
+                A[i, n + j] += cb
+        for (off, cb, cu) in ((-1, eta, -0.5 * B0), (0, -2 * eta, 0.0), (1, eta, 0.5 * B0)):
+            j = i + off
+            if 0 <= j < n:
+                A[n + i, n + j] += cb
+                A[n + i, j] += cu
+        rhs[i] = -G
+    sol = np.linalg.solve(A, rhs)
+    return sol[:n], sol[n:]
+
+
+def _hartmann_run(a, Ha, steps):
+    ny = 2 * a + 8
+    yc = ny // 2
+    nu, eta, G = 0.1, 4.0, 1e-5
+    B0 = Ha * math.sqrt(eta * nu) / a
+    p, X = _plane_channel(ny, yc, a, nu=nu, eta=eta, n_mag=24, G0=G,
+                          bext_kind=W.BEXT_UNIFORM_Y, B0=B0)
+    y = (np.arange(ny) - yc).astype(float)
+    uc, bc = gold.plane_hartmann(np.clip(y, -a, a), a, nu, eta, B0, G)
+    u0 = np.zeros((3, 1, ny, 1))
+    b0 = np.zeros((3, 1, ny, 1))
+    inside = np.abs(y) < a
+    u0[0, 0, inside, 0] = uc[inside]
+    b0[0, 0, inside, 0] = bc[inside]
+    o = oracle.Oracle(p, X, u=u0, b=b0)
+    o.step(steps)
+    prev = o.u.copy()
+    o.step(200)
+    assert np.abs(o.u - prev).max() <= 1e-9 * np.abs(o.u).max(), "not converged"
+    return o, y, inside, (nu, eta, B0, G)
+
+
+def test_plane_hartmann_matches_fd_system_and_closed_form():
+    oracle.set_threads(1)
+    errs = []
+    for a in (8, 16):
+        o, y, inside, (nu, eta, B0, G) = _hartmann_run(a, 4.0, 3000 if a == 8 else 8000)
+        uf, bf = _hartmann_fd(a, nu, eta, B0, G)
+        u = o.u[0, 0, inside, 0]
+        b = o.b[0, 0, inside, 0]
+        assert np.abs(u - uf).max() <= 1e-4 * np.abs(uf).max()
+        assert np.abs(b - bf).max() <= 1e-4 * np.abs(bf).max()
+        uc, bc = gold.plane_hartmann(y[inside], a, nu, eta, B0, G)
+        errs.append(np.abs(u - uc).max() / np.abs(uc).max())
+    order = math.log2(errs[0] / errs[1])
+    assert order >= 1.9, (errs, order)
+    oracle.set_threads(8)
+
+
+# --------------------------------------------------------------------------------------------
+# Pipe: conservation and symmetry of the whole step
+# --------------------------------------------------------------------------------------------
+
+def test_pipe_step_conserves_mass_to_roundoff():
+    w = W.small_pipe(rho_amp=1e-3)
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params, n_mag=40)
+    o = oracle.Oracle(p, w.markers, w.rho, w.u, w.b)
+    m0 = o.rho.sum()
+    o.step(20)
+    assert abs(o.rho.sum() - m0) <= 1e-13 * m0
+
+
+def test_pipe_step_keeps_the_mirror_symmetries():
+    # Uniform field along y, 88 markers per plane (a multiple of 4), integer centre:
+    # u_x is even in y and z, b_x is odd in y and even in z.
+    w = W.small_pipe(noise=0.0)
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params, n_mag=60)
+    o = oracle.Oracle(p, w.markers, w.rho, w.u, w.b)
+    o.step(4)
+    yc, zc, n = int(w.params.yc), int(w.params.zc), w.ny
+    iy = (2 * yc - np.arange(n)) % n
+    iz = (2 * zc - np.arange(w.nz)) % w.nz
+    ux, bx = o.u[0], o.b[0]
+    assert np.abs(ux).max() > 0 and np.abs(bx).max() > 0
+    assert np.abs(ux - ux[:, iy, :]).max() <= 1e-12 * np.abs(ux).max()
+    assert np.abs(ux - ux[iz, :, :]).max() <= 1e-12 * np.abs(ux).max()
+    assert np.abs(bx + bx[:, iy, :]).max() <= 1e-12 * np.abs(bx).max()
+    assert np.abs(bx - bx[iz, :, :]).max() <= 1e-12 * np.abs(bx).max()
+
+
+# --------------------------------------------------------------------------------------------
+# Gold's solution itself (Sec. 4)
+# --------------------------------------------------------------------------------------------
+
+def test_gold_series_solves_the_pipe_equations():
+    R, nu, eta, G, Ha = 1.0, 1.0, 1.0, 1.0, 6.0
+    B0 = Ha * math.sqrt(eta * nu) / R
+    h = 2e-3
+    pts = [(0.3, 0.2), (-0.5, 0.1), (0.1, -0.6), (0.0, 0.0), (0.55, 0.55)]
+    for (yy, zz) in pts:
+        def U(y, z):
+            return gold.gold_u(np.hypot(y, z) / R, np.arctan2(z, y), Ha, R, nu, G)
+
+        def Bx(y, z):
+            return gold.gold_b(np.hypot(y, z) / R, np.arctan2(z, y), Ha, R, nu, eta, G)
+
+        def lap(f):
+            return (f(yy + h, zz) + f(yy - h, zz) + f(yy, zz + h) + f(yy, zz - h) - 4 * f(yy, zz)) / h**2
+
+        def dy(f):
+            return (f(yy + h, zz) - f(yy - h, zz)) / (2 * h)
+
+        r1 = nu * lap(U) + B0 * dy(Bx) + G
+        r2 = eta * lap(Bx) + B0 * dy(U)
+        assert abs(r1) < 1e-4 * G and abs(r2) < 1e-4 * G * R * R / math.sqrt(eta * nu)
+    th = np.linspace(0, 2 * np.pi, 37)
+    umax = gold.gold_u(0.0, 0.0, Ha, R, nu, G)
+    assert np.abs(gold.gold_u(1.0, th, Ha, R, nu, G)).max() < 1e-10 * umax
+    assert np.abs(gold.gold_b(1.0, th, Ha, R, nu, eta, G)).max() < 1e-10 * umax
+
+
+def test_gold_series_tends_to_poiseuille():
+    r = np.linspace(0, 1, 7)
+    for th in (0.0, 0.7, np.pi / 2):
+        u = gold.gold_u(r, th, 0.05, 1.0, 1.0, 1.0)
+        np.testing.assert_allclose(u, gold.poiseuille_pipe_u(r, 1.0, 1.0, 1.0), rtol=2e-4, atol=1e-9)
+
+
+def test_plane_hartmann_closed_form_solves_its_ode():
+    a, nu, eta, B0, G = 1.0, 0.3, 2.0, 3.0, 0.7
+    y = np.linspace(-0.9, 0.9, 13)
+    h = 1e-4
+    u = lambda s: gold.plane_hartmann(s, a, nu, eta, B0, G)[0]
+    b = lambda s: gold.plane_hartmann(s, a, nu, eta, B0, G)[1]
+    d2 = lambda f: (f(y + h) - 2 * f(y) + f(y - h)) / h**2
+    d1 = lambda f: (f(y + h) - f(y - h)) / (2 * h)
+    np.testing.assert_allclose(nu * d2(u) + B0 * d1(b) + G, 0.0, atol=1e-5)
+    np.testing.assert_allclose(eta * d2(b) + B0 * d1(u), 0.0, atol=1e-5)
+    ua, ba = gold.plane_hartmann(np.array([-a, a]), a, nu, eta, B0, G)
+    np.testing.assert_allclose(ua, 0.0, atol=1e-12)
+    np.testing.assert_allclose(ba, 0.0, atol=1e-12)

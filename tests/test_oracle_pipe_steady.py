@@ -1,0 +1,102 @@
+"""Steady pipe flow of the oracle against Poiseuille (Ha = 0) and Gold's series (uniform field),
+and the steady power balance of the energy budgets (Sec. 4, Sec. 5.7 validations).
+
+The wall is the explicit immersed boundary of Sec. 5.3 - 5.6 on 88 markers per plane (R = 14),
+so agreement is limited by the IB's first-order wall representation, not by round-off.
+The steady state does not depend on the number of magnetic sweeps per step (it is the fixed
+point of the warm-started iteration), so these runs use 24 sweeps to reach it sooner.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import gold
+
+NY = NZ = 32
+R = 14.0
+YC = ZC = 16
+
+
+def _grid_polar():
+    y = np.arange(NY) - YC
+    z = np.arange(NZ) - ZC
+    Zg, Yg = np.meshgrid(z, y, indexing="ij")  # arrays (nz, ny)
+    r = np.hypot(Yg, Zg)
+    th = np.arctan2(Zg, Yg)  # from +y towards +z
+    return r, th
+
+
+def _steady(Ha, tol=2e-7, max_steps=12000):
+    nu, eta = 0.07, 700.0
+    B0 = Ha * math.sqrt(eta * nu) / R
+    G = W.poiseuille_G(nu, R)
+    X = W.pipe_markers(1, R, YC, ZC)
+    p = oracle.make_params(1, NY, NZ, nu=nu, eta=eta, n_mag=24, G0=G,
+                           bext_kind=W.BEXT_UNIFORM_Y if Ha > 0 else W.BEXT_NONE, B0=B0,
+                           yc=YC, zc=ZC, radius=R)
+    r, th = _grid_polar()
+    inside = r < R
+    u0 = np.zeros((3, NZ, NY, 1))
+    if Ha > 0:
+        u0[0, :, :, 0] = np.where(inside, gold.gold_u(np.minimum(r / R, 1.0), th, Ha, R, nu, G), 0.0)
+    else:
+        u0[0, :, :, 0] = np.where(inside, gold.poiseuille_pipe_u(r, R, nu, G), 0.0)
+    o = oracle.Oracle(p, X, u=u0)
+    steps = 0
+    while steps < max_steps:
+        prev = o.u.copy()
+        o.step(250)
+        steps += 250
+        if np.abs(o.u - prev).max() <= tol * np.abs(o.u).max():
+            break
+    assert steps < max_steps, "no steady state"
+    return o, (nu, eta, B0, G), r, th
+
+
+@pytest.fixture(scope="module")
+def hartmann5():
+    oracle.set_threads(8)
+    return _steady(5.0)
+
+
+def test_pipe_poiseuille_at_zero_field():
+    o, (nu, eta, B0, G), r, th = _steady(0.0)
+    ux = o.u[0, :, :, 0]
+    ref = gold.poiseuille_pipe_u(r, R, nu, G)
+    band = r <= R - 1.5
+    err = np.abs(ux - ref)[band].max() / ref.max()
+    assert err <= 0.03, err
+
+
+def test_pipe_gold_profiles_and_flow_rate(hartmann5):
+    o, (nu, eta, B0, G), r, th = hartmann5
+    Ha = 5.0
+    ux = o.u[0, :, :, 0]
+    bx = o.b[0, :, :, 0]
+    ug = gold.gold_u(np.minimum(r / R, 1.0), th, Ha, R, nu, G)
+    bg = gold.gold_b(np.minimum(r / R, 1.0), th, Ha, R, nu, eta, G)
+    on_y = (np.arange(NZ)[:, None] == ZC) & (r <= R - 1.0)   # theta = 0, pi (along B)
+    on_z = (np.arange(NY)[None, :] == YC) & (r <= R - 1.0)   # theta = +-pi/2
+    umax = ug.max()
+    for line in (on_y, on_z):
+        assert np.abs(ux - ug)[line].max() <= 0.05 * umax
+    bmax = np.abs(bg[on_y]).max()
+    assert np.abs(bx - bg)[on_y].max() <= 0.10 * bmax
+    q_num = ux[r <= R].sum()
+    q_ref = ug[r <= R].sum()
+    assert abs(q_num / q_ref - 1.0) <= 0.03
+
+
+def test_pipe_steady_power_balance(hartmann5):
+    # Steady unidirectional flow: u . (G x - grad p + nu lap u + J x B) = 0 at every cell, so the
+    # kinetic budget closes over any region; the QS magnetic budget closes at the fixed point.
+    o, *_ = hartmann5
+    bud = o.budgets()
+    kin = bud["P_in"] + bud["P_p"] + bud["P_nu"] + bud["P_L"]
+    assert abs(kin) <= 0.01 * bud["P_in"], bud
+    assert bud["P_L"] < 0 and bud["P_nu"] < 0
+    mag = bud["M_eta"] + bud["M_adv"]
+    assert abs(mag) <= 0.01 * abs(bud["M_eta"]), bud

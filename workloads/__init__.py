@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs for the QS-MHD pipe-flow step (geometry, parameters, initial fields).
+
+This module holds no arithmetic of the lattice method itself: it only produces the inputs that
+both the HIP path and the FP64 oracle consume (marker positions, lattice-unit parameters, initial
+density/velocity/induced-field arrays). Everything is generated in float64 from numpy's
+SeedSequence, keyed by a workload id, so every caller sees the same bytes.
+
+Conventions (lattice units, dx = dt = 1):
+  * box nx * ny * nz, periodic on every face, pipe axis along x;
+  * fields are component-major, x fastest: u has shape (3, nz, ny, nx);
+  * wall markers sit on integer x planes, on a circle of radius R around (yc, zc),
+    m_slice = round(2 pi R) markers per plane (element size close to dx^2, Sec. 5.3 remark on
+    element area), angle theta_j = 2 pi j / m_slice measured from +y towards +z.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+SEED = 221109370
+U0 = 0.05  # reference (bulk) velocity in lattice units
+
+# bext_kind values shared by the C ABI, the oracle and the workloads
+BEXT_NONE = 0
+BEXT_UNIFORM_Y = 1
+BEXT_TANH_FRINGE_Y = 2
+
+
+@dataclasses.dataclass
+class Params:
+    """Physical parameters in lattice units (mirrors the C `mhd_params` struct field by field)."""
+    nu: float
+    eta: float
+    n_mag: int
+    lambda_u: float = 1.0
+    lambda_b: float = 0.0  # <= 0 selects the default eta/eta_ref with eta_ref = 1/6
+    G0: float = 0.0
+    G1: float = 0.0
+    period: float = 0.0
+    bext_kind: int = BEXT_NONE
+    B0: float = 0.0
+    fringe_x0: float = 0.0
+    fringe_w: float = 1.0
+    yc: float = 0.0
+    zc: float = 0.0
+    avg_radius: float = 0.0
+    flow_control: int = 0
+    u_bulk_target: float = 0.0
+    k_c: float = 0.1
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    R: float
+    params: Params
+    markers: np.ndarray          # (3, M) float64
+    rho: np.ndarray              # (nz, ny, nx)
+    u: np.ndarray                # (3, nz, ny, nx)
+    b: np.ndarray                # (3, nz, ny, nx)
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def rng_for(key: int) -> np.random.Generator:
+    """numpy Generator from SeedSequence(SEED) spawned child `key`."""
+    ss = np.random.SeedSequence(SEED)
+    child = ss.spawn(key + 1)[key]
+    return np.random.default_rng(child)
+
+
+def n_mag_for(eta: float, cap: int = 270) -> int:
+    """Sweeps per fluid step: ceil(1/dt) with dt = 1/(6 eta), capped at the effective count."""
+    return int(max(1, min(math.ceil(6.0 * eta - 1e-9), cap)))
+
+
+def map_params(Re: float, Ha: float, Rm: float, R: float, U0: float = U0):
+    """(Re, Ha, Rm) -> (nu, eta, B0) with L = R and U = U0 (Ha = B0 R / sqrt(eta nu))."""
+    nu = U0 * R / Re
+    eta = U0 * R / Rm
+    B0 = Ha * math.sqrt(eta * nu) / R
+    return nu, eta, B0
+
+
+def poiseuille_G(nu: float, R: float, U0: float = U0) -> float:
+    """Body force giving bulk velocity U0 in a Poiseuille pipe of radius R: 8 nu U0 / R^2."""
+    return 8.0 * nu * U0 / (R * R)
+
+
+def pipe_markers(nx: int, R: float, yc: float, zc: float, m_slice: Optional[int] = None,
+                 x_planes: Optional[np.ndarray] = None) -> np.ndarray:
+    """Circle of markers of radius R on each integer x plane; returns (3, M) float64."""
+    if m_slice is None:
+        m_slice = int(round(2.0 * math.pi * R))
+    if x_planes is None:
+        x_planes = np.arange(nx, dtype=np.float64)
+    th = 2.0 * math.pi * np.arange(m_slice, dtype=np.float64) / m_slice
+    ys = yc + R * np.cos(th)
+    zs = zc + R * np.sin(th)
+    X = np.empty((3, len(x_planes) * m_slice), dtype=np.float64)
+    for p, x in enumerate(x_planes):
+        sl = slice(p * m_slice, (p + 1) * m_slice)
+        X[0, sl] = x
+        X[1, sl] = ys
+        X[2, sl] = zs
+    return X
+
+
+def plane_wall_markers(nx: int, nz: int, y_wall: float) -> np.ndarray:
+    """One marker on every (x, z) node of the plane y = y_wall; returns (3, nx*nz)."""
+    xs, zs = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(nz, dtype=np.float64),
+                         indexing="xy")
+    X = np.empty((3, nx * nz), dtype=np.float64)
+    X[0] = xs.ravel()
+    X[1] = y_wall
+    X[2] = zs.ravel()
+    return X
+
+
+def noise_fields(nx, ny, nz, key, amp=1e-4, rho_amp=0.0, b_amp=0.0):
+    """rho = 1 (+ optional noise), u ~ U(-amp, amp) per cell and component, b (default 0)."""
+    g = rng_for(key)
+    u = g.uniform(-amp, amp, size=(3, nz, ny, nx))
+    rho = np.ones((nz, ny, nx))
+    if rho_amp:
+        rho = rho + g.uniform(-rho_amp, rho_amp, size=(nz, ny, nx))
+    b = np.zeros((3, nz, ny, nx))
+    if b_amp:
+        b = g.uniform(-b_amp, b_amp, size=(3, nz, ny, nx))
+    return rho, u, b
+
+
+def pipe_workload(name, key, nx, ny, nz, R, Re, Ha, Rm, *, bext_kind=BEXT_UNIFORM_Y,
+                  fringe_x0=0.0, fringe_w=8.0, n_mag_cap=270, n_mag=None, noise=1e-4,
+                  rho_amp=0.0, b_amp=0.0, G=None) -> Workload:
+    nu, eta, B0 = map_params(Re, Ha, Rm, R)
+    yc, zc = ny // 2, nz // 2
+    p = Params(nu=nu, eta=eta, n_mag=n_mag if n_mag is not None else n_mag_for(eta, n_mag_cap),
+               G0=poiseuille_G(nu, R) if G is None else G, bext_kind=bext_kind, B0=B0,
+               fringe_x0=fringe_x0, fringe_w=fringe_w, yc=float(yc), zc=float(zc),
+               avg_radius=float(R), u_bulk_target=U0)
+    X = pipe_markers(nx, R, yc, zc)
+    rho, u, b = noise_fields(nx, ny, nz, key, amp=noise, rho_amp=rho_amp, b_amp=b_amp)
+    return Workload(name, nx, ny, nz, float(R), p, X, rho, u, b)
+
+
+def small_pipe(**kw) -> Workload:
+    """8 x 32 x 32 box, R = 14, 88 markers per plane, uniform B0 along y,
+    Ha = 5, Re = 10, Rm = 1e-3 (nu = 0.07, eta = 700, B0 = 2.5, 270 sweeps per step)."""
+    return pipe_workload("pipe8x32x32_R14_Ha5", 1, 8, 32, 32, 14.0, 10.0, 5.0, 1e-3, **kw)
+
+
+def fringe_pipe(**kw) -> Workload:
+    """128^3 box, R = 60, 377 markers per plane, fringe field B0 (1 + tanh((x - 64)/8))/2 along y,
+    Ha = 20, Re = 500, Rm = 1e-2 (nu = 0.006, eta = 300, 270 sweeps per step)."""
+    return pipe_workload("pipe128x128x128_R60_fringe_Ha20", 2, 128, 128, 128, 60.0, 500.0, 20.0,
+                         1e-2, bext_kind=BEXT_TANH_FRINGE_Y, fringe_x0=64.0, fringe_w=8.0, **kw)
+
+
+def quarter_fringe_pipe(**kw) -> Workload:
+    """1/4 linear scale of the 128^3 fringe pipe: 32^3 box, R = 15 (94 markers per plane)."""
+    return pipe_workload("pipe32x32x32_R15_fringe_Ha20", 3, 32, 32, 32, 15.0, 500.0, 20.0, 1e-2,
+                         bext_kind=BEXT_TANH_FRINGE_Y, fringe_x0=16.0, fringe_w=2.0, **kw)
+
+
+def large_pipe(Rm=1e-2, **kw) -> Workload:
+    """512 x 256 x 256 box, R = 120, 754 markers per plane, uniform B0, Ha = 30, Re = 5000."""
+    return pipe_workload(f"pipe512x256x256_R120_Ha30_Rm{Rm:g}", 5, 512, 256, 256, 120.0, 5000.0,
+                         30.0, Rm, **kw)

@@ -1,0 +1,174 @@
+/*
+ * mhdlbm — C ABI of the MI355X (gfx950) single-step simplified lattice Boltzmann solver for
+ * quasi-static MHD pipe flow with an explicit immersed-boundary wall
+ * (Tavares, Magacho, Moriconi, Loureiro, arXiv:2211.09370).
+ *
+ * Problem statement followed by the calls (Sec. 4 and Sec. 5): a box of nx*ny*nz lattice cells,
+ * periodic on every face, holds a conducting fluid driven along x by a body force G(t) (the
+ * pressure gradient, dp/dx = -G, Sec. 4 variable-force form G(t) = G0 + G1 cos(2 pi t / T)).
+ * An imposed field B_ext (uniform along y, or a tanh fringe along y that varies with x) acts on
+ * it; the induced field b is iterated in the quasi-static limit (Sec. 5.7). An insulating pipe
+ * wall is represented by Lagrangian markers at which u = u_wall and b = b_wall (default 0) are
+ * imposed with the explicit immersed boundary of Sec. 5.3 - 5.6.
+ *
+ * Units are lattice units (dx = dt = 1, Sec. 4). Every field crosses the ABI as float64,
+ * component-major, x fastest: element (a, x, y, z) of a vector field is at
+ * a*nx*ny*nz + x + nx*(y + ny*z).
+ *
+ * Errors: every call returns an mhd_status; on failure mhd_last_error() gives a message
+ * (thread-local, valid until the next call on the same thread). No call aborts the process.
+ * Threading: one mhd_sim must not be used by two threads at once.
+ */
+#ifndef MHDLBM_H
+#define MHDLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mhd_status;
+#define MHD_OK 0
+#define MHD_ERR_INVALID_ARG (-1) /* argument out of range or inconsistent                   */
+#define MHD_ERR_OOM (-2)         /* workspace too small / host allocation failed            */
+#define MHD_ERR_HIP (-3)         /* a HIP runtime call failed (message names it)            */
+#define MHD_ERR_UNSTABLE (-4)    /* non-finite state or |u| >= c_s found by a budget pass    */
+#define MHD_ERR_STATE (-5)       /* call out of order (e.g. step before params/markers)     */
+#define MHD_ERR_UNSUPPORTED (-6) /* valid request outside this build (e.g. tau >= 1)        */
+
+/* Storage kind of a field in device memory. Arithmetic is always float32. 16-bit kinds store
+ * offsets: rho as rho - 1, u as u / u_scale, b as b / b_scale. */
+typedef enum { MHD_STORE_F32 = 0, MHD_STORE_F16 = 1, MHD_STORE_BF16 = 2 } mhd_storage;
+
+typedef struct {
+    int32_t nx, ny, nz;    /* box size in cells; nx, ny, nz >= 1                         */
+    int32_t rho_storage;   /* mhd_storage of the density offset rho - 1                  */
+    int32_t u_storage;     /* mhd_storage of the velocity                               */
+    int32_t b_storage;     /* mhd_storage of the induced field                          */
+    double u_scale;        /* velocity scale of 16-bit storage (> 0; ignored for F32)    */
+    double b_scale;        /* induced-field scale of 16-bit storage (> 0; ignored for F32) */
+} mhd_grid_desc;
+
+typedef enum {
+    MHD_BEXT_NONE = 0,
+    MHD_BEXT_UNIFORM_Y = 1,     /* B_ext = (0, B0, 0)                                    */
+    MHD_BEXT_TANH_FRINGE_Y = 2  /* B_ext = (0, B0 (1 + tanh((x - fringe_x0)/fringe_w))/2, 0) */
+} mhd_bext_kind;
+
+/* Physical parameters (lattice units). */
+typedef struct {
+    double nu;            /* kinematic viscosity; tau = 3 nu + 1/2 must lie in (1/2, 1)     */
+    double eta;           /* magnetic resistivity (> 0); particle speed of the b iteration
+                             c = 6 eta, kappa = 1/(2 eta) (Sec. 5.7)                      */
+    int32_t n_mag;        /* magnetic sweeps per fluid step (>= 1), usually
+                             min(ceil(6 eta), 270) (Sec. 5.7 iteration count and cap)       */
+    int32_t bext_kind;    /* mhd_bext_kind                                                 */
+    double lambda_u;      /* viscosity ratio of the u correction (Sec. 5.5); <= 0 -> 1      */
+    double lambda_b;      /* resistivity ratio of the b correction (Sec. 5.6); <= 0 -> 6 eta
+                             (reference resistivity 1/6)                                   */
+    double G0, G1, period;/* G(t) = G0 + G1 cos(2 pi t / period); period <= 0 -> G = G0     */
+    double B0;            /* imposed field amplitude                                       */
+    double fringe_x0, fringe_w; /* tanh fringe centre and width (cells), fringe_w > 0       */
+    double yc, zc;        /* pipe axis position in the cross-section (cells)               */
+    double avg_radius;    /* pipe radius R used by the budgets (r < R - 2) and flow rate   */
+    int32_t flow_control; /* 1: integral control of G towards u_bulk_target               */
+    int32_t reserved0;
+    double u_bulk_target; /* target bulk velocity over r <= R                               */
+    double k_c;           /* control gain: G += k_c (8 nu / R^2) (target - U_b) per step    */
+} mhd_params;
+
+typedef enum { MHD_FIELD_RHO = 0, MHD_FIELD_U = 1, MHD_FIELD_B_INDUCED = 2 } mhd_field;
+
+/* One budget record (Sec. 4 energy balance): averages over Omega = {(y-yc)^2 + (z-zc)^2 <
+ * (R-2)^2} of E_k = <rho |u|^2 / 2>, E_m = <|B|^2 / 2> (B = B_ext + b), E_b = <|b|^2 / 2>,
+ * P_in = G <u_x>, P_p = -<u . grad(rho/3)>, P_nu = nu <u . lap u>, P_L = <u . (J x B)>,
+ * M_eta = eta <B . lap b>, M_adv = -<B . div(u B - B u)>, joule = eta <|J|^2>; plus
+ * mass = sum of rho over the box, Q = (1/nx) sum over r <= R of u_x, u_max = max |u|.
+ * Derivatives are the D3Q19 isotropic differences; all sums are float64 in a fixed order. */
+typedef struct {
+    int64_t step;   /* steps completed when the record was taken                          */
+    double G;       /* body force used by that step                                       */
+    double E_k, E_m, E_b, P_in, P_p, P_nu, P_L, M_eta, M_adv, joule, mass, Q, u_max;
+    double n_omega; /* number of cells in Omega                                            */
+} mhd_budget;
+
+typedef struct mhd_sim mhd_sim;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *mhd_last_error(void);
+
+/* Bytes of device workspace needed for a box g with at most n_markers markers
+ * (host-only; no GPU needed). */
+mhd_status mhd_workspace_size(const mhd_grid_desc *g, int64_t n_markers, size_t *bytes);
+
+/* Create a solver on the current HIP device.
+ * dev_workspace: device memory of at least mhd_workspace_size(g, n_markers) bytes, 256-byte
+ *   aligned, owned by the caller and kept alive until mhd_destroy.
+ * hip_stream: the hipStream_t every kernel and copy is issued on (NULL = default stream).
+ * Fields start at rho = 1, u = 0, b = 0, t = 0. */
+mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_workspace, size_t bytes,
+                      void *hip_stream, mhd_sim **out);
+
+/* Wall markers X_j (host, SoA: x[0..M), y[0..M), z[0..M)) and the imposed wall values
+ * u_wall, b_wall (host, 3*M component-major, NULL -> 0). Copied; caller keeps ownership.
+ * Each coordinate must lie in [0, n) of its axis (the stencil wraps periodically).
+ * Computes the Lagrange taps (Sec. 5.2), the row sums d_j of D D^T (Sec. 5.3) and the
+ * gather lists of the spreading step. M = 0 removes the wall. */
+mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const double *u_wall,
+                           const double *b_wall);
+
+/* Parameters (copied). INVALID_ARG if tau = 3 nu + 1/2 <= 1/2, eta <= 0, n_mag < 1, a fringe
+ * width <= 0, or (with markers set) 1 + d_j (lambda - 1) <= 0 for some marker (the scaling
+ * of Sec. 5.5 / 5.6 would be singular or negative). UNSUPPORTED if tau >= 1. */
+mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p);
+
+/* Copy a field in / out (host float64, layout above; rho has 1 component, u and b 3).
+ * Synchronous with respect to the host buffer. mhd_get_field also reports a deferred
+ * MHD_ERR_UNSTABLE (the data is still copied). */
+mhd_status mhd_set_field(mhd_sim *s, mhd_field f, const double *host);
+mhd_status mhd_get_field(mhd_sim *s, mhd_field f, double *host);
+
+/* Step counter and current body force (checkpoint / resume). */
+mhd_status mhd_get_time(mhd_sim *s, int64_t *t, double *G);
+mhd_status mhd_set_time(mhd_sim *s, int64_t t, double G);
+
+/* Advance n_steps fluid steps (each: n_mag magnetic sweeps with the b correction after each,
+ * Lorentz force, fluid predictor, u correction). Asynchronous on the stream: returns after
+ * the launches. If budget_every > 0 a budget record is taken after every step whose new step
+ * count is a multiple of budget_every. */
+mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every);
+
+/* Synchronise the stream and move the budget records taken since the last call (oldest first,
+ * at most cap) to out. Returns MHD_ERR_UNSTABLE if a record found non-finite values or
+ * |u| >= 1/sqrt(3) (the records are still returned). */
+mhd_status mhd_get_budgets(mhd_sim *s, mhd_budget *out, int64_t cap, int64_t *n_out);
+
+/* Take one budget record of the current state now (asynchronous). */
+mhd_status mhd_record_budget(mhd_sim *s);
+
+/* Kernel timing with HIP events on the solver's stream: when enabled, mhd_step brackets every
+ * launch of the kernels with events; mhd_kernel_stats synchronises and returns the number of
+ * timed launches and their summed duration for one kernel id, then forgets them. */
+typedef enum {
+    MHD_K_MAG_SWEEP = 0,
+    MHD_K_IB_INTERP = 1,
+    MHD_K_IB_SPREAD = 2,
+    MHD_K_LORENTZ = 3,
+    MHD_K_FLUID = 4,
+    MHD_K_BUDGET = 5,
+    MHD_K_CONTROL = 6,
+    MHD_K_COUNT = 7
+} mhd_kernel_id;
+mhd_status mhd_set_profiling(mhd_sim *s, int32_t enable);
+mhd_status mhd_kernel_stats(mhd_sim *s, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Free library host state (events included). Device workspace stays the caller's. */
+mhd_status mhd_destroy(mhd_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHDLBM_H */

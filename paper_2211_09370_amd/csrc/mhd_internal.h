@@ -1,0 +1,74 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels of mhdlbm.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mhdlbm.h"
+
+namespace mhd {
+
+// Device-side control block: step counter, body force, status and budget-ring bookkeeping.
+struct DevCtrl {
+    double G;          // controlled body force (state of the integral law)
+    double G_step;     // body force used by the step in flight
+    int64_t t;         // steps completed
+    int32_t status;    // bit 0: unstable
+    int32_t n_records; // budget records written since the host last drained the ring
+    int32_t overflow;  // records dropped because the ring was full
+    int32_t pad[9];
+};
+
+// Scalar parameters the step kernels read (copied by value into every launch).
+struct StepConst {
+    int nx, ny, nz;
+    float kappa;       // 1 / (2 eta)
+    float tau;         // 3 nu + 1/2
+    float u_scale, inv_u_scale, b_scale, inv_b_scale;
+    double nu, eta;
+    double G0, G1, period;
+    double yc, zc, radius;
+    int flow_control;
+    double u_target, k_c;
+};
+
+constexpr int kRedBlocks = 1024;   // fixed grid of the float64 reductions (fixed summation order)
+constexpr int kRedThreads = 256;
+constexpr int kBudgetVals = 16;    // per-block partial sums of a budget pass
+constexpr int kRingCap = 4096;     // budget records held on the device
+
+// Launch wrappers implemented in mhd_kernels.hip. Every pointer is a device pointer.
+struct SweepLaunch {
+    int tx, ty, zchunk;  // tile shape and z extent of one workgroup
+};
+
+hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c);
+hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part, StepConst c,
+                           double inv_count);
+hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo,
+                            const float *bext, StepConst c, SweepLaunch L);
+hipError_t launch_ib_interp(hipStream_t s, int kind, const void *phi, float scale, int64_t N,
+                            int M, const int *mk_ptr, const int *tap_cell, const float *tap_w,
+                            const float *sj, const float *wall, float *delta);
+hipError_t launch_ib_spread(hipStream_t s, int kind, void *phi, float scale, float inv_scale,
+                            int64_t N, int nband, const int *band_cell, const int *band_ptr,
+                            const int *band_mk, const float *band_w, const float *delta, int M);
+hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const float *bext,
+                          const DevCtrl *ctrl, float *F, StepConst c);
+hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,
+                        void *rho_o, void *u_o, StepConst c);
+hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c);
+hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b,
+                         const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring,
+                         StepConst c);
+// float32 staging <-> storage kind (round to nearest even on the way in).
+hipError_t launch_store_kind(hipStream_t s, int kind, const float *src, void *dst, int64_t n);
+hipError_t launch_load_kind(hipStream_t s, int kind, const void *src, float *dst, int64_t n);
+hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl);
+
+// Packs the three storage kinds (rho, u, b) into one dispatch code.
+inline int pack_kinds(int r, int u, int b) { return r | (u << 4) | (b << 8); }
+
+}  // namespace mhd

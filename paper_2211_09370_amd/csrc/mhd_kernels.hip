@@ -1,0 +1,902 @@
+// gfx950 kernels of the single-step simplified lattice Boltzmann step for quasi-static MHD pipe
+// flow (arXiv:2211.09370). All arithmetic is float32 except the budget / flow-rate reductions,
+// which convert the stored values to float64 and sum them in a fixed order.
+//
+// Field layout: component-major, x fastest; element (a, x, y, z) at a*N + x + nx*(y + ny*z).
+// Storage kinds: float32, or 16-bit offsets (rho - 1 in every kind, u / u_scale, b / b_scale).
+//
+// Kernels (per fluid step, in order):
+//   k_ctrl_begin   body force G(t) of the step (Sec. 4, variable-force form)
+//   k_mag_sweep    x n_mag: b*(x) = sum_i g_i^eq(x - e_i), tau_m = 1, c = 6 eta (Sec. 5.7)
+//   k_ib_interp    per marker: delta_j = s_j (b_wall - sum_k D_jk phi_k)     (Sec. 5.4 / 5.6)
+//   k_ib_spread    per wall-band cell: phi_k += sum_j D_jk delta_j (gather form, no atomics)
+//   k_lorentz      F = G x + (curl b) x (B_ext + b), isotropic differences    (Sec. 5.1)
+//   k_fluid        single-step rho, rho u with GZS forcing + discrete-effect term (Sec. 3.3, 5.1)
+//   k_ib_interp / k_ib_spread on u                                              (Sec. 5.3 / 5.5)
+//   k_flow_partial + k_step_end   flow-rate control sum (float64), step counter
+//   k_budget_partial + k_budget_final   every K steps: energy budgets of Sec. 4 (float64)
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "mhd_internal.h"
+
+namespace mhd {
+
+// -------------------------------------------------------------------------------------------
+// Storage traits
+// -------------------------------------------------------------------------------------------
+template <typename T>
+struct St;
+template <>
+struct St<float> {
+    static __device__ __forceinline__ float ld(const float *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ void st(float *p, int64_t i, float v) { p[i] = v; }
+};
+template <>
+struct St<__half> {
+    static __device__ __forceinline__ float ld(const __half *p, int64_t i) { return __half2float(p[i]); }
+    static __device__ __forceinline__ void st(__half *p, int64_t i, float v) { p[i] = __float2half_rn(v); }
+};
+template <>
+struct St<__hip_bfloat16> {
+    static __device__ __forceinline__ float ld(const __hip_bfloat16 *p, int64_t i) {
+        return __bfloat162float(p[i]);
+    }
+    static __device__ __forceinline__ void st(__hip_bfloat16 *p, int64_t i, float v) {
+        p[i] = __float2bfloat16(v);
+    }
+};
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// D3Q19 neighbour offsets without the rest direction: 6 faces (w = 1/18), 12 edges (w = 1/36).
+__constant__ int c_dir[18][3] = {{1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                                 {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
+                                 {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+#define W0 (1.0f / 3.0f)
+#define WF (1.0f / 18.0f)
+#define WE (1.0f / 36.0f)
+
+// -------------------------------------------------------------------------------------------
+// Control kernels
+// -------------------------------------------------------------------------------------------
+__global__ void k_ctrl_begin(DevCtrl *ctrl, StepConst c) {
+    if (threadIdx.x != 0) return;
+    double G;
+    if (c.flow_control)
+        G = ctrl->G;
+    else if (c.period > 0.0)
+        G = c.G0 + c.G1 * cos(2.0 * 3.14159265358979323846 * (double)ctrl->t / c.period);
+    else
+        G = c.G0;
+    ctrl->G_step = G;
+}
+
+// Fixed-order sum of the flow partials (one block), integral control law, step counter.
+__global__ void __launch_bounds__(kRedThreads) k_step_end(DevCtrl *ctrl, const double *part, StepConst c,
+                                                          double inv_count) {
+    __shared__ double sh[kRedThreads];
+    double s = 0.0;
+    if (c.flow_control)
+        for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c.flow_control) {
+            double ub = sh[0] * inv_count;
+            ctrl->G = ctrl->G + c.k_c * (8.0 * c.nu / (c.radius * c.radius)) * (c.u_target - ub);
+        } else {
+            ctrl->G = ctrl->G_step;
+        }
+        ctrl->t += 1;
+    }
+}
+
+__global__ void k_reset_records(DevCtrl *ctrl) {
+    if (threadIdx.x == 0) {
+        ctrl->n_records = 0;
+        ctrl->overflow = 0;
+    }
+}
+
+// -------------------------------------------------------------------------------------------
+// Magnetic sweep (Sec. 5.7): tau_m = 1, particle speed c = 6 eta, so c_i / c_s^2 = e_i / (2 eta).
+//
+//   b*_a(x) = sum_i w_i [ b_a(x - e_i) + kappa sum_c e_ic Lam_ac(x - e_i) ],
+//   Lam_ac = u_c B_a - u_a B_c,  B = B_ext + b,  kappa = 1 / (2 eta).
+//
+// Written per plane: a workgroup owns a TX x TY column of cells and marches along z over a
+// chunk of planes. Each new plane (with a one-cell x/y halo) is staged in LDS as
+// (b_x, b_y, b_z, kappa Lam_xy, kappa Lam_xz, kappa Lam_yz); every thread forms from its 3x3
+// in-plane neighbourhood the plane's contributions to the outputs at z-1, z and z+1
+// (A, B, C below) and keeps the running sums in registers, so each field value is read from
+// memory once per plane and every neighbour access is an LDS read.
+//
+// With D_c[f](x) = sum_i w_i e_ic f(x - e_i) and the in-plane sums
+//   P0 = c/3 + (faces)/18 + (corners)/36,  P1 = c/18 + (faces)/36,
+//   Q0x = (xm - xp)/18 + (mm + mp - pm - pp)/36,  Q1x = (xm - xp)/36   (Q*y likewise in y),
+// one has avg[f](z) = P0(z) + P1(z-1) + P1(z+1), D_x[f](z) = Q0x(z) + Q1x(z-1) + Q1x(z+1),
+// D_y likewise and D_z[f](z) = P1(z-1) - P1(z+1); then
+//   b*_x = avg b_x + D_y Lxy + D_z Lxz,  b*_y = avg b_y - D_x Lxy + D_z Lyz,
+//   b*_z = avg b_z - D_x Lxz - D_y Lyz.
+// -------------------------------------------------------------------------------------------
+struct SweepArgs {
+    const void *u;
+    const void *b;
+    void *bo;
+    const float *bext;  // 3 x nx
+    int nx, ny, nz;
+    int tiles_x, tiles_y, nzc, zchunk, nblocks;
+    float kappa, u_scale, b_scale, inv_b_scale;
+};
+
+template <int TX, int TY, typename TU, typename TB>
+__global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
+    constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    constexpr int NSLOT = (HN + NT - 1) / NT;
+    __shared__ float s_bx[HN], s_by[HN], s_bz[HN], s_lxy[HN], s_lxz[HN], s_lyz[HN];
+
+    // XCD-aware order: the hardware hands consecutive workgroups to the 8 XCDs in turn; give
+    // each XCD a contiguous run of tiles so neighbouring tiles share halo rows in one L2.
+    const int per = gridDim.x >> 3;
+    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (lb >= a.nblocks) return;
+    const int tix = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int tiy = rest % a.tiles_y;
+    const int tiz = rest / a.tiles_y;
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int z0 = tiz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int plane = nx * ny;
+
+    const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * N;
+    const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * N;
+    TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * N;
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool own = gx < nx && gy < ny;
+
+    // halo slots handled by this thread: fixed (x, y) for the whole march
+    int sxy[NSLOT];
+    float sbe[NSLOT][3];
+    bool sval[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int i = tid + s * NT;
+        sval[s] = i < HN;
+        const int hx = i % HX, hy = i / HX;
+        const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
+        sxy[s] = hxg + nx * hyg;
+        sbe[s][0] = sval[s] ? a.bext[hxg] : 0.f;
+        sbe[s][1] = sval[s] ? a.bext[nx + hxg] : 0.f;
+        sbe[s][2] = sval[s] ? a.bext[2 * nx + hxg] : 0.f;
+    }
+
+    float ru[NSLOT][3], rb[NSLOT][3];
+    auto load_plane = [&](int p) {
+        const int64_t off = (int64_t)wrapi(p, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (sval[s]) {
+                const int64_t k = off + sxy[s];
+                ru[s][0] = St<TU>::ld(u0, k) * a.u_scale;
+                ru[s][1] = St<TU>::ld(u1, k) * a.u_scale;
+                ru[s][2] = St<TU>::ld(u2, k) * a.u_scale;
+                rb[s][0] = St<TB>::ld(b0, k) * a.b_scale;
+                rb[s][1] = St<TB>::ld(b1, k) * a.b_scale;
+                rb[s][2] = St<TB>::ld(b2, k) * a.b_scale;
+            }
+        }
+    };
+
+    const int c0 = (ly + 1) * HX + (lx + 1);
+    const float kap = a.kappa;
+    constexpr float W6 = 1.0f / 6.0f;  // WF + 4 WE: weight of a neighbouring plane as a whole
+    // running sums of the plane contributions (difference form), and the column's own values
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    float ap0 = 0.f, ap1 = 0.f, ap2 = 0.f;
+    float cm0 = 0.f, cm1 = 0.f, cm2 = 0.f;  // b at (x, y, z-1)
+    float cc0 = 0.f, cc1 = 0.f, cc2 = 0.f;  // b at (x, y, z)
+    float lm_xz = 0.f, lm_yz = 0.f;         // kappa Lam_xz, Lam_yz at (x, y, z-1)
+    float lc_xz = 0.f, lc_yz = 0.f;         // kappa Lam_xz, Lam_yz at (x, y, z)
+
+    load_plane(z0 - 1);
+    for (int p = z0 - 1; p <= z1; ++p) {
+        __syncthreads();  // the previous plane's LDS reads are done
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (sval[s]) {
+                const int i = tid + s * NT;
+                const float Bx = rb[s][0] + sbe[s][0];
+                const float By = rb[s][1] + sbe[s][1];
+                const float Bz = rb[s][2] + sbe[s][2];
+                const float ux = ru[s][0], uy = ru[s][1], uz = ru[s][2];
+                s_bx[i] = rb[s][0];
+                s_by[i] = rb[s][1];
+                s_bz[i] = rb[s][2];
+                s_lxy[i] = kap * (uy * Bx - ux * By);
+                s_lxz[i] = kap * (uz * Bx - ux * Bz);
+                s_lyz[i] = kap * (uz * By - uy * Bz);
+            }
+        }
+        __syncthreads();
+        if (p < z1) load_plane(p + 1);  // in flight while this plane is reduced
+        if (own) {
+            // b components: centre value and in-plane sums of differences to it
+            //   dP0 = sum_faces WF (f - c) + sum_corners WE (f - c),  dP1 = sum_faces WE (f - c)
+            float c_x, c_y, c_z, dP0x, dP1x, dP0y, dP1y, dP0z, dP1z;
+#define MHD_PLANE_DIFFS(F, C, DP0, DP1)                                                              \
+    {                                                                                                \
+        const float *f = F;                                                                          \
+        C = f[c0];                                                                                   \
+        const float fs = ((f[c0 - 1] - C) + (f[c0 + 1] - C)) + ((f[c0 - HX] - C) + (f[c0 + HX] - C)); \
+        const float cs = ((f[c0 - HX - 1] - C) + (f[c0 - HX + 1] - C)) +                              \
+                         ((f[c0 + HX - 1] - C) + (f[c0 + HX + 1] - C));                               \
+        DP0 = WF * fs + WE * cs;                                                                     \
+        DP1 = WE * fs;                                                                               \
+    }
+            MHD_PLANE_DIFFS(s_bx, c_x, dP0x, dP1x)
+            MHD_PLANE_DIFFS(s_by, c_y, dP0y, dP1y)
+            MHD_PLANE_DIFFS(s_bz, c_z, dP0z, dP1z)
+            // kappa Lam_xy: Q0x, Q1x, Q0y, Q1y (differences across the cell)
+            float Q0xA, Q1xA, Q0yA, Q1yA;
+            {
+                const float *f = s_lxy;
+                const float dx = f[c0 - 1] - f[c0 + 1], dy = f[c0 - HX] - f[c0 + HX];
+                const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
+                Q0xA = WF * dx + WE * ((mm - pm) + (mp - pp));
+                Q1xA = WE * dx;
+                Q0yA = WF * dy + WE * ((mm - mp) + (pm - pp));
+                Q1yA = WE * dy;
+            }
+            // kappa Lam_xz: centre, dP1, Q0x, Q1x
+            float lxz, dP1B, Q0xB, Q1xB;
+            {
+                const float *f = s_lxz;
+                lxz = f[c0];
+                const float dx = f[c0 - 1] - f[c0 + 1];
+                const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
+                dP1B = WE * (((f[c0 - 1] - lxz) + (f[c0 + 1] - lxz)) + ((f[c0 - HX] - lxz) + (f[c0 + HX] - lxz)));
+                Q0xB = WF * dx + WE * ((mm - pm) + (mp - pp));
+                Q1xB = WE * dx;
+            }
+            // kappa Lam_yz: centre, dP1, Q0y, Q1y
+            float lyz, dP1C, Q0yC, Q1yC;
+            {
+                const float *f = s_lyz;
+                lyz = f[c0];
+                const float dy = f[c0 - HX] - f[c0 + HX];
+                const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
+                dP1C = WE * (((f[c0 - 1] - lyz) + (f[c0 + 1] - lyz)) + ((f[c0 - HX] - lyz) + (f[c0 + HX] - lyz)));
+                Q0yC = WF * dy + WE * ((mm - mp) + (pm - pp));
+                Q1yC = WE * dy;
+            }
+            // contributions of this plane to the outputs at z+1 (A), z (B), z-1 (C)
+            const float A0 = dP1x + Q1yA + dP1B, B0 = dP0x + Q0yA, C0 = dP1x + Q1yA - dP1B;
+            const float A1 = dP1y - Q1xA + dP1C, B1 = dP0y - Q0xA, C1 = dP1y - Q1xA - dP1C;
+            const float A2 = dP1z - Q1xB - Q1yC, B2 = dP0z - Q0xB - Q0yC;
+            if (p >= z0 + 1) {
+                // output plane p-1: b* = b_c + increment, the increment built from differences
+                const float d0 = (acc0 + C0) + W6 * (((cm0 - cc0) + (c_x - cc0)) + (lm_xz - lxz));
+                const float d1 = (acc1 + C1) + W6 * (((cm1 - cc1) + (c_y - cc1)) + (lm_yz - lyz));
+                const float d2 = (acc2 + A2) + W6 * ((cm2 - cc2) + (c_z - cc2));
+                const int64_t k = (int64_t)(p - 1) * plane + gx + nx * gy;
+                St<TB>::st(o0, k, (cc0 + d0) * a.inv_b_scale);
+                St<TB>::st(o1, k, (cc1 + d1) * a.inv_b_scale);
+                St<TB>::st(o2, k, (cc2 + d2) * a.inv_b_scale);
+            }
+            acc0 = ap0 + B0;
+            acc1 = ap1 + B1;
+            acc2 = ap2 + B2;
+            ap0 = A0;
+            ap1 = A1;
+            ap2 = A2;
+            cm0 = cc0;
+            cm1 = cc1;
+            cm2 = cc2;
+            cc0 = c_x;
+            cc1 = c_y;
+            cc2 = c_z;
+            lm_xz = lc_xz;
+            lm_yz = lc_yz;
+            lc_xz = lxz;
+            lc_yz = lyz;
+        }
+    }
+#undef MHD_PLANE_DIFFS
+}
+
+// -------------------------------------------------------------------------------------------
+// Immersed boundary (Sec. 5.2 - 5.6), explicit diagonal form:
+//   delta_j = s_j (phi_wall_j - sum_k D_jk phi*_k),  phi_k = phi*_k + sum_j D_jk delta_j,
+// s_j = lambda / (d_j (1 + d_j (lambda - 1))). Interpolation per marker, spreading per cell of
+// the wall band through a cell -> markers gather list (deterministic, no atomics).
+// -------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_interp(const T *phi, float scale, int64_t N, int M, const int *mk_ptr,
+                                                   const int *tap_cell, const float *tap_w, const float *sj,
+                                                   const float *wall, float *delta) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    float I0 = 0.f, I1 = 0.f, I2 = 0.f;
+    const int e = mk_ptr[j + 1];
+    for (int t = mk_ptr[j]; t < e; ++t) {
+        const int64_t k = tap_cell[t];
+        const float w = tap_w[t];
+        I0 += w * (St<T>::ld(phi, k) * scale);
+        I1 += w * (St<T>::ld(phi, N + k) * scale);
+        I2 += w * (St<T>::ld(phi, 2 * N + k) * scale);
+    }
+    const float s = sj[j];
+    const float t0 = wall ? wall[j] : 0.f, t1 = wall ? wall[M + j] : 0.f, t2 = wall ? wall[2 * M + j] : 0.f;
+    delta[j] = s * (t0 - I0);
+    delta[M + j] = s * (t1 - I1);
+    delta[2 * M + j] = s * (t2 - I2);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_spread(T *phi, float scale, float inv_scale, int64_t N, int nband,
+                                                   const int *band_cell, const int *band_ptr, const int *band_mk,
+                                                   const float *band_w, const float *delta, int M) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nband) return;
+    const int64_t k = band_cell[e];
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    const int qe = band_ptr[e + 1];
+    for (int q = band_ptr[e]; q < qe; ++q) {
+        const int j = band_mk[q];
+        const float w = band_w[q];
+        c0 += w * delta[j];
+        c1 += w * delta[M + j];
+        c2 += w * delta[2 * M + j];
+    }
+    St<T>::st(phi, k, (St<T>::ld(phi, k) * scale + c0) * inv_scale);
+    St<T>::st(phi, N + k, (St<T>::ld(phi, N + k) * scale + c1) * inv_scale);
+    St<T>::st(phi, 2 * N + k, (St<T>::ld(phi, 2 * N + k) * scale + c2) * inv_scale);
+}
+
+// -------------------------------------------------------------------------------------------
+// Lorentz + body force (Sec. 5.1): J = curl_h b with d_a f = 3 sum_i w_i e_ia f(x + e_i),
+// F = G x + J x (B_ext + b).
+// -------------------------------------------------------------------------------------------
+template <typename TB>
+__global__ void __launch_bounds__(256) k_lorentz(const TB *b, float bs, const float *bext, const DevCtrl *ctrl,
+                                                 float *F, StepConst c) {
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int x = (int)(k % c.nx);
+    const int y = (int)((k / c.nx) % c.ny);
+    const int z = (int)(k / ((int64_t)c.nx * c.ny));
+    float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // g[a][c] = d_c b_a
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+        const int ex = c_dir[i][0], ey = c_dir[i][1], ez = c_dir[i][2];
+        const float w = 3.0f * (i < 6 ? WF : WE);
+        const int64_t kn = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
+        const float v0 = St<TB>::ld(b, kn) * bs, v1 = St<TB>::ld(b, N + kn) * bs, v2 = St<TB>::ld(b, 2 * N + kn) * bs;
+        const float e3[3] = {(float)ex, (float)ey, (float)ez};
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const float we = w * e3[cc];
+            g[0][cc] += we * v0;
+            g[1][cc] += we * v1;
+            g[2][cc] += we * v2;
+        }
+    }
+    const float Jx = g[2][1] - g[1][2], Jy = g[0][2] - g[2][0], Jz = g[1][0] - g[0][1];
+    const float Bx = St<TB>::ld(b, k) * bs + bext[x];
+    const float By = St<TB>::ld(b, N + k) * bs + bext[c.nx + x];
+    const float Bz = St<TB>::ld(b, 2 * N + k) * bs + bext[2 * c.nx + x];
+    const float G = (float)ctrl->G_step;
+    F[k] = G + (Jy * Bz - Jz * By);
+    F[N + k] = Jz * Bx - Jx * Bz;
+    F[2 * N + k] = Jx * By - Jy * Bx;
+}
+
+// -------------------------------------------------------------------------------------------
+// Fluid single-step predictor (Sec. 3.3, Sec. 5.1):
+//   rho' = sum_i [1.5 f_i(x - e_i) - f_i(x) + 0.5 f_i(x + e_i)]
+//   rho' u* = sum_i e_i {f_i(x - e_i) + (tau - 1)[f_i(x + e_i) - 2 f_i(x) + f_i(x - e_i)]}
+//             - (tau/2) sum_i e_i [F_i(x + e_i) - F_i(x - e_i)] + F(x)
+// with f_i = f_i^eq(rho, u) and F_i = (1 - 1/(2 tau)) w_i [3 (e_i - u) . F + 9 (e_i . u)(e_i . F)].
+//
+// Evaluated as an increment per pair of opposite neighbours y+ = x + d, y- = x - d (weight w).
+// Writing f_i = w_i + h_i, h_i = w_i [drho + (1 + drho) q_i], q_i = 3 e.u + q2, q2 =
+// 4.5 (e.u)^2 - 1.5 u.u, J = (1 + drho) u, the parts that do not depend on the neighbours
+// cancel analytically (sum_i w_i = 1, sum_i w_i q_i = 0, sum_i w_i e_i e_i = I/3) and
+//   drho' - drho = sum_pairs w [2 (Ddrho+ + Ddrho-) + 2 (DQ+ + DQ-) + 3 d.(J- - J+)]
+//   rho' u* - rho u = sum_pairs d w [(drho- - drho+) + 3 (2 tau - 1) d.(DJ- + DJ+) + (DQ- - DQ+)]
+//                     - tau c_F sum_pairs d w (G+ - G-) + F(x)
+// with D. = value at y+- minus value at x (DQ compares (1 + drho) q2 along the same d),
+// G = 9 (d.u)(d.F) - 3 u.F and c_F = 1 - 1/(2 tau). Every term is a neighbour difference, so the
+// float32 rounding is relative to the change of the step, and the new state is
+// drho' = drho + delta, u* = u + (Dm - delta u) / (1 + drho').
+// -------------------------------------------------------------------------------------------
+__constant__ int c_pair[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0},
+                                 {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+
+template <typename TR, typename TU>
+__global__ void __launch_bounds__(256) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o, TU *u_o,
+                                               StepConst c) {
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int x = (int)(k % c.nx);
+    const int y = (int)((k / c.nx) % c.ny);
+    const int z = (int)(k / ((int64_t)c.nx * c.ny));
+    const float tau = c.tau, us = c.u_scale;
+    const float cF = 1.0f - 0.5f / tau;
+    const float a3 = 3.0f * (2.0f * tau - 1.0f);
+
+    const float d0 = St<TR>::ld(rho, k);
+    const float ux0 = St<TU>::ld(u, k) * us, uy0 = St<TU>::ld(u, N + k) * us, uz0 = St<TU>::ld(u, 2 * N + k) * us;
+    const float uu0 = ux0 * ux0 + uy0 * uy0 + uz0 * uz0;
+    float dr = 0.f;
+    float m0 = 0.f, m1 = 0.f, m2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
+        const float w = i < 3 ? WF : WE;
+        const int64_t kp = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
+        const int64_t km = wrapi(x - ex, c.nx) + (int64_t)c.nx * (wrapi(y - ey, c.ny) + (int64_t)c.ny * wrapi(z - ez, c.nz));
+        const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
+        const float upx = St<TU>::ld(u, kp) * us, upy = St<TU>::ld(u, N + kp) * us, upz = St<TU>::ld(u, 2 * N + kp) * us;
+        const float umx = St<TU>::ld(u, km) * us, umy = St<TU>::ld(u, N + km) * us, umz = St<TU>::ld(u, 2 * N + km) * us;
+        const float fpx = F[kp], fpy = F[N + kp], fpz = F[2 * N + kp];
+        const float fmx = F[km], fmy = F[N + km], fmz = F[2 * N + km];
+        // differences to the centre
+        const float Dpx = upx - ux0, Dpy = upy - uy0, Dpz = upz - uz0;
+        const float Dmx = umx - ux0, Dmy = umy - uy0, Dmz = umz - uz0;
+        const float Ddp = dp - d0, Ddm = dm - d0;
+        const float eu0 = ex * ux0 + ey * uy0 + ez * uz0;
+        const float eDp = ex * Dpx + ey * Dpy + ez * Dpz, eDm = ex * Dmx + ey * Dmy + ez * Dmz;
+        const float eup = eu0 + eDp, eum = eu0 + eDm;
+        // (1 + drho) q2 differences along d: q2(u+-) - q2(u0) = 4.5 (d.D)(d.S) - 1.5 D.S, S = u+- + u0
+        const float q20 = 4.5f * eu0 * eu0 - 1.5f * uu0;
+        const float dq2p = 4.5f * eDp * (eup + eu0) - 1.5f * (Dpx * (upx + ux0) + Dpy * (upy + uy0) + Dpz * (upz + uz0));
+        const float dq2m = 4.5f * eDm * (eum + eu0) - 1.5f * (Dmx * (umx + ux0) + Dmy * (umy + uy0) + Dmz * (umz + uz0));
+        const float DQp = (1.0f + dp) * dq2p + Ddp * q20, DQm = (1.0f + dm) * dq2m + Ddm * q20;
+        // momentum differences along d: d.(J+- - J0) = d.D + (drho+- d.u+- - drho0 d.u0)
+        const float dJp = eDp + (dp * eup - d0 * eu0), dJm = eDm + (dm * eum - d0 * eu0);
+        dr += w * (2.0f * (Ddp + Ddm) + 2.0f * (DQp + DQm) + 3.0f * (dJm - dJp));
+        const float cm = w * ((dm - dp) + a3 * (dJm + dJp) + (DQm - DQp));
+        m0 += ex * cm;
+        m1 += ey * cm;
+        m2 += ez * cm;
+        const float efp = ex * fpx + ey * fpy + ez * fpz, efm = ex * fmx + ey * fmy + ez * fmz;
+        const float Gp = 9.0f * eup * efp - 3.0f * (upx * fpx + upy * fpy + upz * fpz);
+        const float Gm = 9.0f * eum * efm - 3.0f * (umx * fmx + umy * fmy + umz * fmz);
+        const float cg = w * (Gp - Gm);
+        g0 += ex * cg;
+        g1 += ey * cg;
+        g2 += ez * cg;
+    }
+    const float dnew = d0 + dr;
+    const float tcF = tau * cF;
+    const float Dm0 = (m0 - tcF * g0) + F[k];
+    const float Dm1 = (m1 - tcF * g1) + F[N + k];
+    const float Dm2 = (m2 - tcF * g2) + F[2 * N + k];
+    const float inv = 1.0f / (1.0f + dnew);
+    St<TR>::st(rho_o, k, dnew);
+    St<TU>::st(u_o, k, (ux0 + (Dm0 - dr * ux0) * inv) * c.inv_u_scale);
+    St<TU>::st(u_o, N + k, (uy0 + (Dm1 - dr * uy0) * inv) * c.inv_u_scale);
+    St<TU>::st(u_o, 2 * N + k, (uz0 + (Dm2 - dr * uz0) * inv) * c.inv_u_scale);
+}
+
+// -------------------------------------------------------------------------------------------
+// Float64 reductions with a fixed summation order: a fixed grid of kRedBlocks workgroups walks
+// the cells with a fixed stride, each block tree-reduces in LDS and writes one partial; a
+// single block then sums the partials in index order.
+// -------------------------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_sum(double (*sh)[kRedThreads], double *v) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename TU>
+__global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, double *part, StepConst c) {
+    __shared__ double sh[1][kRedThreads];
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    const double R2 = c.radius * c.radius;
+    double s = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
+        const int y = (int)((k / c.nx) % c.ny);
+        const int z = (int)(k / ((int64_t)c.nx * c.ny));
+        const double dy = y - c.yc, dz = z - c.zc;
+        if (dy * dy + dz * dz <= R2) s += (double)(St<TU>::ld(u, k) * c.u_scale);
+    }
+    double v[1] = {s};
+    block_sum<1>(sh, v);
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0][0];
+}
+
+// partial layout: 0 Ek, 1 Em, 2 Eb, 3 sum u_x (Omega), 4 Pp, 5 Pnu/nu, 6 PL, 7 Meta/eta, 8 Madv,
+// 9 sum |J|^2, 10 mass, 11 Q sum, 12 n_omega, 13 max |u|^2, 14 nonfinite, 15 unused
+template <typename TR, typename TU, typename TB>
+__global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, const TU *u, const TB *b,
+                                                                const float *bext, double *part, StepConst c) {
+    __shared__ double sh[13][kRedThreads];
+    __shared__ double shm[kRedThreads];
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    const double us = c.u_scale, bs = c.b_scale;
+    const double R2 = c.radius * c.radius;
+    const double Ro = c.radius - 2.0, Ro2 = Ro * Ro;
+    double v[13];
+#pragma unroll
+    for (int q = 0; q < 13; ++q) v[q] = 0.0;
+    double umax2 = 0.0;
+    double nonfin = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
+        const int x = (int)(k % c.nx);
+        const int y = (int)((k / c.nx) % c.ny);
+        const int z = (int)(k / ((int64_t)c.nx * c.ny));
+        const double r = 1.0 + (double)St<TR>::ld(rho, k);
+        double uu[3], bb[3], B[3];
+        for (int a = 0; a < 3; ++a) {
+            uu[a] = (double)St<TU>::ld(u, a * N + k) * us;
+            bb[a] = (double)St<TB>::ld(b, a * N + k) * bs;
+            B[a] = bb[a] + (double)bext[a * c.nx + x];
+        }
+        const double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+        if (!isfinite(u2) || !isfinite(r)) nonfin = 1.0;
+        umax2 = fmax(umax2, u2);
+        v[10] += r;
+        const double dy = y - c.yc, dz = z - c.zc, r2 = dy * dy + dz * dz;
+        if (r2 <= R2) v[11] += uu[0];
+        if (r2 >= Ro2) continue;
+        v[12] += 1.0;
+        double grho[3] = {0, 0, 0}, lu[3] = {0, 0, 0}, lb[3] = {0, 0, 0}, divL[3] = {0, 0, 0};
+        double gb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int i = 0; i < 18; ++i) {
+            const int e[3] = {c_dir[i][0], c_dir[i][1], c_dir[i][2]};
+            const double w = i < 6 ? 1.0 / 18.0 : 1.0 / 36.0;
+            const int xn = wrapi(x + e[0], c.nx);
+            const int64_t kn = xn + (int64_t)c.nx * (wrapi(y + e[1], c.ny) + (int64_t)c.ny * wrapi(z + e[2], c.nz));
+            const double rn = 1.0 + (double)St<TR>::ld(rho, kn);
+            double un[3], bn[3], Bn[3];
+            for (int a = 0; a < 3; ++a) {
+                un[a] = (double)St<TU>::ld(u, a * N + kn) * us;
+                bn[a] = (double)St<TB>::ld(b, a * N + kn) * bs;
+                Bn[a] = bn[a] + (double)bext[a * c.nx + xn];
+            }
+            for (int a = 0; a < 3; ++a) {
+                grho[a] += 3.0 * w * e[a] * rn;
+                lu[a] += 6.0 * w * (un[a] - uu[a]);
+                lb[a] += 6.0 * w * (bn[a] - bb[a]);
+                double dl = 0.0;
+                for (int cc = 0; cc < 3; ++cc) {
+                    gb[a][cc] += 3.0 * w * e[cc] * bn[a];
+                    dl += e[cc] * (un[cc] * Bn[a] - Bn[cc] * un[a]);
+                }
+                divL[a] += 3.0 * w * dl;
+            }
+        }
+        const double J[3] = {gb[2][1] - gb[1][2], gb[0][2] - gb[2][0], gb[1][0] - gb[0][1]};
+        const double JxB[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2], J[0] * B[1] - J[1] * B[0]};
+        v[0] += 0.5 * r * u2;
+        v[1] += 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+        v[2] += 0.5 * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]);
+        v[3] += uu[0];
+        for (int a = 0; a < 3; ++a) {
+            v[4] += -uu[a] * (grho[a] / 3.0);
+            v[5] += uu[a] * lu[a];
+            v[6] += uu[a] * JxB[a];
+            v[7] += B[a] * lb[a];
+            v[8] += -B[a] * divL[a];
+            v[9] += J[a] * J[a];
+        }
+    }
+    block_sum<13>(sh, v);
+    // max |u|^2 and "any non-finite" in the same fixed tree
+    __shared__ double shf[kRedThreads];
+    shm[threadIdx.x] = umax2;
+    shf[threadIdx.x] = nonfin;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
+            shf[threadIdx.x] = fmax(shf[threadIdx.x], shf[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *o = part + (int64_t)blockIdx.x * kBudgetVals;
+        for (int q = 0; q < 13; ++q) o[q] = sh[q][0];
+        o[13] = shm[0];
+        o[14] = shf[0];
+        o[15] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part, DevCtrl *ctrl, mhd_budget *ring,
+                                                              StepConst c) {
+    __shared__ double sh[13][kRedThreads];
+    __shared__ double shm[kRedThreads], shf[kRedThreads];
+    double v[13];
+#pragma unroll
+    for (int q = 0; q < 13; ++q) v[q] = 0.0;
+    double m = 0.0, f = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) {
+        const double *p = part + (int64_t)i * kBudgetVals;
+#pragma unroll
+        for (int q = 0; q < 13; ++q) v[q] += p[q];
+        m = fmax(m, p[13]);
+        f = fmax(f, p[14]);
+    }
+    block_sum<13>(sh, v);
+    shm[threadIdx.x] = m;
+    shf[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
+            shf[threadIdx.x] = fmax(shf[threadIdx.x], shf[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = sh[12][0];
+        const double inv = n > 0.0 ? 1.0 / n : 0.0;
+        mhd_budget r;
+        r.step = ctrl->t;
+        r.G = ctrl->G_step;
+        r.E_k = sh[0][0] * inv;
+        r.E_m = sh[1][0] * inv;
+        r.E_b = sh[2][0] * inv;
+        r.P_in = r.G * sh[3][0] * inv;
+        r.P_p = sh[4][0] * inv;
+        r.P_nu = c.nu * sh[5][0] * inv;
+        r.P_L = sh[6][0] * inv;
+        r.M_eta = c.eta * sh[7][0] * inv;
+        r.M_adv = sh[8][0] * inv;
+        r.joule = c.eta * sh[9][0] * inv;
+        r.mass = sh[10][0];
+        r.Q = sh[11][0] / (double)c.nx;
+        r.u_max = sqrt(shm[0]);
+        r.n_omega = n;
+        // |u| >= c_s = 1/sqrt(3) or a non-finite value marks the run unstable
+        if (shf[0] != 0.0 || !(shm[0] < 1.0 / 3.0) || !isfinite(sh[0][0])) ctrl->status |= 1;
+        const int idx = ctrl->n_records;
+        if (idx < kRingCap) {
+            ring[idx] = r;
+            ctrl->n_records = idx + 1;
+        } else {
+            ctrl->overflow += 1;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------------------------
+// Storage conversion (float32 staging <-> storage kind)
+// -------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_store(const float *src, T *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        St<T>::st(dst, i, src[i]);
+}
+template <typename T>
+__global__ void k_load(const T *src, float *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = St<T>::ld(src, i);
+}
+
+// ===========================================================================================
+// Host-side launch wrappers
+// ===========================================================================================
+static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c) {
+    hipLaunchKernelGGL(k_ctrl_begin, dim3(1), dim3(64), 0, s, ctrl, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part, StepConst c, double inv_count) {
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(kRedThreads), 0, s, ctrl, flow_part, c, inv_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl) {
+    hipLaunchKernelGGL(k_reset_records, dim3(1), dim3(64), 0, s, ctrl);
+    return hipGetLastError();
+}
+
+template <int TX, int TY, typename TU, typename TB>
+static hipError_t sweep_tile(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
+                             int zchunk) {
+    SweepArgs a;
+    a.u = u;
+    a.b = b;
+    a.bo = bo;
+    a.bext = bext;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.tiles_x = (c.nx + TX - 1) / TX;
+    a.tiles_y = (c.ny + TY - 1) / TY;
+    a.zchunk = zchunk;
+    a.nzc = (c.nz + zchunk - 1) / zchunk;
+    a.nblocks = a.tiles_x * a.tiles_y * a.nzc;
+    a.kappa = c.kappa;
+    a.u_scale = c.u_scale;
+    a.b_scale = c.b_scale;
+    a.inv_b_scale = c.inv_b_scale;
+    const unsigned grid = (unsigned)(((a.nblocks + 7) / 8) * 8);
+    hipLaunchKernelGGL((k_mag_sweep<TX, TY, TU, TB>), dim3(grid), dim3(TX * TY), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename TU, typename TB>
+static hipError_t sweep_typed(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
+                              SweepLaunch L) {
+    switch (L.tx) {
+        case 64: return sweep_tile<64, 4, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+        case 32: return sweep_tile<32, 8, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+        case 16: return sweep_tile<16, 16, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+        default: return sweep_tile<8, 32, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+    }
+}
+
+// Supported storage mixes: all float32; rho f16 with u f16 or bf16 and b f16; all bf16.
+#define MHD_KIND_F32 0
+#define MHD_KIND_F16 1
+#define MHD_KIND_BF16 2
+
+hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo, const float *bext,
+                            StepConst c, SweepLaunch L) {
+    const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
+    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32) return sweep_typed<float, float>(s, u, b, bo, bext, c, L);
+    if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16) return sweep_typed<__half, __half>(s, u, b, bo, bext, c, L);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16) return sweep_typed<__hip_bfloat16, __half>(s, u, b, bo, bext, c, L);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
+        return sweep_typed<__hip_bfloat16, __hip_bfloat16>(s, u, b, bo, bext, c, L);
+    return hipErrorInvalidValue;
+}
+
+#define MHD_DISPATCH1(kind, FN, ...)                                       \
+    switch (kind) {                                                        \
+        case MHD_KIND_F32: return FN<float>(__VA_ARGS__);                  \
+        case MHD_KIND_F16: return FN<__half>(__VA_ARGS__);                 \
+        case MHD_KIND_BF16: return FN<__hip_bfloat16>(__VA_ARGS__);        \
+        default: return hipErrorInvalidValue;                              \
+    }
+
+template <typename T>
+static hipError_t ib_interp_t(hipStream_t s, const void *phi, float scale, int64_t N, int M, const int *mk_ptr,
+                              const int *tap_cell, const float *tap_w, const float *sj, const float *wall,
+                              float *delta) {
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ib_interp<T>, dim3(blocks_for(M, 256)), dim3(256), 0, s, (const T *)phi, scale, N, M, mk_ptr,
+                       tap_cell, tap_w, sj, wall, delta);
+    return hipGetLastError();
+}
+hipError_t launch_ib_interp(hipStream_t s, int kind, const void *phi, float scale, int64_t N, int M, const int *mk_ptr,
+                            const int *tap_cell, const float *tap_w, const float *sj, const float *wall,
+                            float *delta) {
+    MHD_DISPATCH1(kind, ib_interp_t, s, phi, scale, N, M, mk_ptr, tap_cell, tap_w, sj, wall, delta)
+}
+
+template <typename T>
+static hipError_t ib_spread_t(hipStream_t s, void *phi, float scale, float inv_scale, int64_t N, int nband,
+                              const int *band_cell, const int *band_ptr, const int *band_mk, const float *band_w,
+                              const float *delta, int M) {
+    if (nband <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ib_spread<T>, dim3(blocks_for(nband, 256)), dim3(256), 0, s, (T *)phi, scale, inv_scale, N,
+                       nband, band_cell, band_ptr, band_mk, band_w, delta, M);
+    return hipGetLastError();
+}
+hipError_t launch_ib_spread(hipStream_t s, int kind, void *phi, float scale, float inv_scale, int64_t N, int nband,
+                            const int *band_cell, const int *band_ptr, const int *band_mk, const float *band_w,
+                            const float *delta, int M) {
+    MHD_DISPATCH1(kind, ib_spread_t, s, phi, scale, inv_scale, N, nband, band_cell, band_ptr, band_mk, band_w, delta,
+                  M)
+}
+
+template <typename T>
+static hipError_t lorentz_t(hipStream_t s, const void *b, const float *bext, const DevCtrl *ctrl, float *F,
+                            StepConst c) {
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    hipLaunchKernelGGL(k_lorentz<T>, dim3(blocks_for(N, 256)), dim3(256), 0, s, (const T *)b, c.b_scale, bext, ctrl,
+                       F, c);
+    return hipGetLastError();
+}
+hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const float *bext, const DevCtrl *ctrl, float *F,
+                          StepConst c) {
+    MHD_DISPATCH1(kind_b, lorentz_t, s, b, bext, ctrl, F, c)
+}
+
+template <typename TR, typename TU>
+static hipError_t fluid_t(hipStream_t s, const void *rho, const void *u, const float *F, void *rho_o, void *u_o,
+                          StepConst c) {
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    hipLaunchKernelGGL((k_fluid<TR, TU>), dim3(blocks_for(N, 256)), dim3(256), 0, s, (const TR *)rho, (const TU *)u,
+                       F, (TR *)rho_o, (TU *)u_o, c);
+    return hipGetLastError();
+}
+hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F, void *rho_o,
+                        void *u_o, StepConst c) {
+    const int kr = kinds & 15, ku = (kinds >> 4) & 15;
+    if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32) return fluid_t<float, float>(s, rho, u, F, rho_o, u_o, c);
+    if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16) return fluid_t<__half, __half>(s, rho, u, F, rho_o, u_o, c);
+    if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16) return fluid_t<__half, __hip_bfloat16>(s, rho, u, F, rho_o, u_o, c);
+    if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16)
+        return fluid_t<__hip_bfloat16, __hip_bfloat16>(s, rho, u, F, rho_o, u_o, c);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t flow_t(hipStream_t s, const void *u, double *part, StepConst c) {
+    hipLaunchKernelGGL(k_flow_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const T *)u, part, c);
+    return hipGetLastError();
+}
+hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c) {
+    MHD_DISPATCH1(kind_u, flow_t, s, u, part, c)
+}
+
+template <typename TR, typename TU, typename TB>
+static hipError_t budget_t(hipStream_t s, const void *rho, const void *u, const void *b, const float *bext,
+                           DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
+    hipLaunchKernelGGL((k_budget_partial<TR, TU, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const TR *)rho,
+                       (const TU *)u, (const TB *)b, bext, part, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(kRedThreads), 0, s, part, ctrl, ring, c);
+    return hipGetLastError();
+}
+hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b, const float *bext,
+                         DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
+    const int kr = kinds & 15, ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
+    if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
+        return budget_t<float, float, float>(s, rho, u, b, bext, ctrl, part, ring, c);
+    if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
+        return budget_t<__half, __half, __half>(s, rho, u, b, bext, ctrl, part, ring, c);
+    if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
+        return budget_t<__half, __hip_bfloat16, __half>(s, rho, u, b, bext, ctrl, part, ring, c);
+    if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
+        return budget_t<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>(s, rho, u, b, bext, ctrl, part, ring, c);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t store_t(hipStream_t s, const float *src, void *dst, int64_t n) {
+    hipLaunchKernelGGL(k_store<T>, dim3((unsigned)std::min<int64_t>(blocks_for(n, 256), 65536)), dim3(256), 0, s, src,
+                       (T *)dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_store_kind(hipStream_t s, int kind, const float *src, void *dst, int64_t n) {
+    MHD_DISPATCH1(kind, store_t, s, src, dst, n)
+}
+
+template <typename T>
+static hipError_t load_t(hipStream_t s, const void *src, float *dst, int64_t n) {
+    hipLaunchKernelGGL(k_load<T>, dim3((unsigned)std::min<int64_t>(blocks_for(n, 256), 65536)), dim3(256), 0, s,
+                       (const T *)src, dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_load_kind(hipStream_t s, int kind, const void *src, float *dst, int64_t n) {
+    MHD_DISPATCH1(kind, load_t, s, src, dst, n)
+}
+
+}  // namespace mhd

@@ -1,0 +1,721 @@
+// Host runtime of mhdlbm: workspace carving, argument checks, marker preprocessing (Lagrange
+// taps, row sums d_j, gather lists), the step launch sequence and the C ABI of include/mhdlbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "mhd_internal.h"
+
+using namespace mhd;
+
+namespace {
+
+thread_local std::string g_err;
+
+mhd_status fail(mhd_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+mhd_status fail(mhd_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(MHD_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t kind_bytes(int k) { return k == MHD_STORE_F32 ? 4 : 2; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Byte offsets of every region of the caller's workspace.
+struct Layout {
+    size_t rho[2], u[2], b[2], F, bext, ctrl, mk_ptr, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
+    size_t band_cell, band_ptr, band_mk, band_w, red_part, flow_part, ring, total;
+};
+
+Layout make_layout(const mhd_grid_desc &g, int64_t M) {
+    Layout L{};
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t T = 27 * std::max<int64_t>(M, 0);  // taps / gather entries, at most 27 per marker
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    for (int i = 0; i < 2; ++i) L.rho[i] = take(N * kind_bytes(g.rho_storage));
+    for (int i = 0; i < 2; ++i) L.u[i] = take(3 * N * kind_bytes(g.u_storage));
+    for (int i = 0; i < 2; ++i) L.b[i] = take(3 * N * kind_bytes(g.b_storage));
+    L.F = take(3 * N * sizeof(float));
+    L.bext = take(3 * (size_t)g.nx * sizeof(float));
+    L.ctrl = take(sizeof(DevCtrl));
+    L.mk_ptr = take((M + 1) * sizeof(int));
+    L.tap_cell = take(T * sizeof(int));
+    L.tap_w = take(T * sizeof(float));
+    L.s_u = take(M * sizeof(float));
+    L.s_b = take(M * sizeof(float));
+    L.uwall = take(3 * M * sizeof(float));
+    L.bwall = take(3 * M * sizeof(float));
+    L.delta = take(3 * M * sizeof(float));
+    L.band_cell = take(T * sizeof(int));
+    L.band_ptr = take((T + 1) * sizeof(int));
+    L.band_mk = take(T * sizeof(int));
+    L.band_w = take(T * sizeof(float));
+    L.red_part = take((size_t)kRedBlocks * kBudgetVals * sizeof(double));
+    L.flow_part = take((size_t)kRedBlocks * sizeof(double));
+    L.ring = take((size_t)kRingCap * sizeof(mhd_budget));
+    L.total = off;
+    return L;
+}
+
+mhd_status check_desc(const mhd_grid_desc *g) {
+    if (!g) return fail(MHD_ERR_INVALID_ARG, "grid descriptor is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(MHD_ERR_INVALID_ARG, "box size must be >= 1 per axis");
+    const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    if (3 * N >= (int64_t)1 << 31) return fail(MHD_ERR_INVALID_ARG, "3*nx*ny*nz must stay below 2^31");
+    for (int k : {g->rho_storage, g->u_storage, g->b_storage})
+        if (k < MHD_STORE_F32 || k > MHD_STORE_BF16) return fail(MHD_ERR_INVALID_ARG, "unknown storage kind %d", k);
+    const int r = g->rho_storage, u = g->u_storage, b = g->b_storage;
+    const bool ok = (r == 0 && u == 0 && b == 0) || (r == 1 && u == 1 && b == 1) || (r == 1 && u == 2 && b == 1) ||
+                    (r == 2 && u == 2 && b == 2);
+    if (!ok)
+        return fail(MHD_ERR_UNSUPPORTED,
+                    "storage mix (rho %d, u %d, b %d) not built: use all f32, f16/f16/f16, f16/bf16/f16 or all bf16", r,
+                    u, b);
+    if (u != 0 && !(g->u_scale > 0.0)) return fail(MHD_ERR_INVALID_ARG, "u_scale must be > 0 for 16-bit u");
+    if (b != 0 && !(g->b_scale > 0.0)) return fail(MHD_ERR_INVALID_ARG, "b_scale must be > 0 for 16-bit b");
+    return MHD_OK;
+}
+
+// Three-point Lagrange weights of the nodes n0-1, n0, n0+1 nearest to X (n0 = floor(X + 1/2),
+// s = X - n0 in [-1/2, 1/2)): the quadratic through the three nodes evaluated at X.
+inline int lagrange_nodes(double X, double w[3]) {
+    const int n0 = (int)std::floor(X + 0.5);
+    const double s = X - n0;
+    w[0] = -0.5 * s * (1.0 - s);
+    w[1] = 1.0 - s * s;
+    w[2] = 0.5 * s * (1.0 + s);
+    return n0 - 1;
+}
+
+inline int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+struct Event2 {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mhd_sim {
+    mhd_grid_desc g{};
+    int64_t N = 0, Mcap = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *ws = nullptr;
+    Layout L{};
+    int kinds = 0;
+    // ping-pong state
+    int cr = 0, cu = 0, cb = 0;
+    // host state
+    bool have_params = false;
+    mhd_params prm{};
+    int64_t M = 0, nband = 0;
+    std::vector<double> d;  // row sums of D D^T
+    int64_t t_host = 0;
+    SweepLaunch sweep{64, 4, 8};
+    double flow_inv_count = 0.0;
+    // profiling
+    bool prof = false;
+    std::vector<Event2> ev_pool[MHD_K_COUNT];
+    size_t ev_used[MHD_K_COUNT] = {};
+
+    template <typename T>
+    T *at(size_t off) const {
+        return reinterpret_cast<T *>(ws + off);
+    }
+    void *rho(int i) const { return ws + L.rho[i]; }
+    void *u(int i) const { return ws + L.u[i]; }
+    void *b(int i) const { return ws + L.b[i]; }
+    DevCtrl *ctrl() const { return at<DevCtrl>(L.ctrl); }
+};
+
+namespace {
+
+StepConst step_const(const mhd_sim *s) {
+    StepConst c{};
+    c.nx = s->g.nx;
+    c.ny = s->g.ny;
+    c.nz = s->g.nz;
+    const mhd_params &p = s->prm;
+    c.kappa = (float)(1.0 / (2.0 * p.eta));
+    c.tau = (float)(3.0 * p.nu + 0.5);
+    c.u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.u_scale;
+    c.inv_u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.u_scale);
+    c.b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.b_scale;
+    c.inv_b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.b_scale);
+    c.nu = p.nu;
+    c.eta = p.eta;
+    c.G0 = p.G0;
+    c.G1 = p.G1;
+    c.period = p.period;
+    c.yc = p.yc;
+    c.zc = p.zc;
+    c.radius = p.avg_radius;
+    c.flow_control = p.flow_control;
+    c.u_target = p.u_bulk_target;
+    c.k_c = p.k_c;
+    return c;
+}
+
+double lambda_u_of(const mhd_params &p) { return p.lambda_u > 0.0 ? p.lambda_u : 1.0; }
+double lambda_b_of(const mhd_params &p) { return p.lambda_b > 0.0 ? p.lambda_b : 6.0 * p.eta; }
+
+// s_j = lambda / (d_j (1 + d_j (lambda - 1))) for both fields, uploaded to the workspace.
+mhd_status upload_scalings(mhd_sim *s) {
+    if (!s->have_params || s->M == 0) return MHD_OK;
+    const double lu = lambda_u_of(s->prm), lb = lambda_b_of(s->prm);
+    std::vector<float> su(s->M), sb(s->M);
+    for (int64_t j = 0; j < s->M; ++j) {
+        const double dj = s->d[j];
+        const double qu = 1.0 + dj * (lu - 1.0), qb = 1.0 + dj * (lb - 1.0);
+        if (!(dj > 0.0) || !(qu > 0.0) || !(qb > 0.0))
+            return fail(MHD_ERR_INVALID_ARG,
+                        "marker %lld: d_j = %g makes the wall scaling singular (1 + d (lambda - 1) = %g / %g)",
+                        (long long)j, dj, qu, qb);
+        su[j] = (float)(lu / (dj * qu));
+        sb[j] = (float)(lb / (dj * qb));
+    }
+    HIPCHK(hipMemcpyAsync(s->at<float>(s->L.s_u), su.data(), s->M * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->at<float>(s->L.s_b), sb.data(), s->M * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MHD_OK;
+}
+
+// Imposed field per x plane (3 x nx table).
+mhd_status upload_bext(mhd_sim *s) {
+    const int nx = s->g.nx;
+    std::vector<float> t(3 * (size_t)nx, 0.f);
+    const mhd_params &p = s->prm;
+    for (int x = 0; x < nx; ++x) {
+        double By = 0.0;
+        if (p.bext_kind == MHD_BEXT_UNIFORM_Y)
+            By = p.B0;
+        else if (p.bext_kind == MHD_BEXT_TANH_FRINGE_Y)
+            By = p.B0 * 0.5 * (1.0 + std::tanh(((double)x - p.fringe_x0) / p.fringe_w));
+        t[nx + x] = (float)By;
+    }
+    HIPCHK(hipMemcpyAsync(s->at<float>(s->L.bext), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MHD_OK;
+}
+
+mhd_status fill_field(mhd_sim *s, mhd_field f, const double *host, bool zero) {
+    const int64_t N = s->N;
+    const int ncomp = f == MHD_FIELD_RHO ? 1 : 3;
+    const int64_t n = ncomp * N;
+    int kind;
+    double scale = 1.0, offset = 0.0;
+    void *dst;
+    if (f == MHD_FIELD_RHO) {
+        kind = s->g.rho_storage;
+        offset = 1.0;
+        dst = s->rho(s->cr);
+    } else if (f == MHD_FIELD_U) {
+        kind = s->g.u_storage;
+        if (kind != MHD_STORE_F32) scale = s->g.u_scale;
+        dst = s->u(s->cu);
+    } else {
+        kind = s->g.b_storage;
+        if (kind != MHD_STORE_F32) scale = s->g.b_scale;
+        dst = s->b(s->cb);
+    }
+    std::vector<float> tmp((size_t)n);
+    for (int64_t i = 0; i < n; ++i) tmp[i] = zero ? 0.f : (float)((host[i] - offset) / scale);
+    float *stage = s->at<float>(s->L.F);  // 3N floats, free between steps
+    HIPCHK(hipMemcpyAsync(stage, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(launch_store_kind(s->stream, kind, stage, dst, n));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MHD_OK;
+}
+
+inline Event2 &next_event(mhd_sim *s, int k) {
+    if (s->ev_used[k] == s->ev_pool[k].size()) {
+        Event2 e;
+        (void)hipEventCreate(&e.a);
+        (void)hipEventCreate(&e.b);
+        s->ev_pool[k].push_back(e);
+    }
+    return s->ev_pool[k][s->ev_used[k]++];
+}
+
+// Launch helper: brackets the launch with events when profiling is on.
+template <typename Fn>
+mhd_status timed(mhd_sim *s, int k, const char *what, Fn fn) {
+    Event2 *e = nullptr;
+    if (s->prof) {
+        e = &next_event(s, k);
+        HIPCHK(hipEventRecord(e->a, s->stream));
+    }
+    hipError_t err = fn();
+    if (err != hipSuccess) return fail(MHD_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(err));
+    if (e) HIPCHK(hipEventRecord(e->b, s->stream));
+    return MHD_OK;
+}
+
+#define STEPCHK(x)                     \
+    do {                               \
+        mhd_status st_ = (x);          \
+        if (st_ != MHD_OK) return st_; \
+    } while (0)
+
+mhd_status ib_correct(mhd_sim *s, int kind, void *phi, float scale, float inv_scale, const float *sj,
+                      const float *wall) {
+    if (s->M == 0) return MHD_OK;
+    const int M = (int)s->M;
+    float *delta = s->at<float>(s->L.delta);
+    STEPCHK(timed(s, MHD_K_IB_INTERP, "ib_interp", [&] {
+        return launch_ib_interp(s->stream, kind, phi, scale, s->N, M, s->at<int>(s->L.mk_ptr), s->at<int>(s->L.tap_cell),
+                                s->at<float>(s->L.tap_w), sj, wall, delta);
+    }));
+    STEPCHK(timed(s, MHD_K_IB_SPREAD, "ib_spread", [&] {
+        return launch_ib_spread(s->stream, kind, phi, scale, inv_scale, s->N, (int)s->nband, s->at<int>(s->L.band_cell),
+                                s->at<int>(s->L.band_ptr), s->at<int>(s->L.band_mk), s->at<float>(s->L.band_w), delta,
+                                M);
+    }));
+    return MHD_OK;
+}
+
+mhd_status one_step(mhd_sim *s) {
+    const StepConst c = step_const(s);
+    hipStream_t st = s->stream;
+    STEPCHK(timed(s, MHD_K_CONTROL, "ctrl_begin", [&] { return launch_ctrl_begin(st, s->ctrl(), c); }));
+    // 1. magnetic iteration, wall correction after every sweep
+    for (int m = 0; m < s->prm.n_mag; ++m) {
+        const int nb = 1 - s->cb;
+        STEPCHK(timed(s, MHD_K_MAG_SWEEP, "mag_sweep", [&] {
+            return launch_mag_sweep(st, s->kinds, s->u(s->cu), s->b(s->cb), s->b(nb), s->at<float>(s->L.bext), c,
+                                    s->sweep);
+        }));
+        STEPCHK(ib_correct(s, s->g.b_storage, s->b(nb), c.b_scale, c.inv_b_scale, s->at<float>(s->L.s_b),
+                           s->at<float>(s->L.bwall)));
+        s->cb = nb;
+    }
+    // 2. Lorentz + body force from the new b
+    float *F = s->at<float>(s->L.F);
+    STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
+        return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->at<float>(s->L.bext), s->ctrl(), F, c);
+    }));
+    // 3. fluid predictor, 4. velocity wall correction
+    const int nr = 1 - s->cr, nu = 1 - s->cu;
+    STEPCHK(timed(s, MHD_K_FLUID, "fluid", [&] {
+        return launch_fluid(st, s->kinds, s->rho(s->cr), s->u(s->cu), F, s->rho(nr), s->u(nu), c);
+    }));
+    STEPCHK(ib_correct(s, s->g.u_storage, s->u(nu), c.u_scale, c.inv_u_scale, s->at<float>(s->L.s_u),
+                       s->at<float>(s->L.uwall)));
+    s->cr = nr;
+    s->cu = nu;
+    // 5. flow-rate control sum (float64, fixed order) and step counter
+    double *fp = s->at<double>(s->L.flow_part);
+    if (c.flow_control)
+        STEPCHK(timed(s, MHD_K_CONTROL, "flow_partial",
+                      [&] { return launch_flow_partial(st, s->g.u_storage, s->u(s->cu), fp, c); }));
+    STEPCHK(timed(s, MHD_K_CONTROL, "step_end",
+                  [&] { return launch_step_end(st, s->ctrl(), fp, c, s->flow_inv_count); }));
+    s->t_host += 1;
+    return MHD_OK;
+}
+
+mhd_status record_budget(mhd_sim *s) {
+    const StepConst c = step_const(s);
+    return timed(s, MHD_K_BUDGET, "budget", [&] {
+        return launch_budget(s->stream, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->at<float>(s->L.bext),
+                             s->ctrl(), s->at<double>(s->L.red_part), s->at<mhd_budget>(s->L.ring), c);
+    });
+}
+
+mhd_status read_ctrl(mhd_sim *s, DevCtrl *h) {
+    HIPCHK(hipMemcpyAsync(h, s->ctrl(), sizeof(DevCtrl), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MHD_OK;
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mhd_last_error(void) { return g_err.c_str(); }
+
+mhd_status mhd_workspace_size(const mhd_grid_desc *g, int64_t n_markers, size_t *bytes) {
+    g_err.clear();
+    STEPCHK(check_desc(g));
+    if (!bytes) return fail(MHD_ERR_INVALID_ARG, "bytes is NULL");
+    if (n_markers < 0 || n_markers >= ((int64_t)1 << 26))
+        return fail(MHD_ERR_INVALID_ARG, "n_markers must be in [0, 2^26)");
+    *bytes = make_layout(*g, n_markers).total;
+    return MHD_OK;
+}
+
+mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_workspace, size_t bytes, void *hip_stream,
+                      mhd_sim **out) {
+    g_err.clear();
+    if (!out) return fail(MHD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    STEPCHK(check_desc(g));
+    if (n_markers < 0 || n_markers >= ((int64_t)1 << 26))
+        return fail(MHD_ERR_INVALID_ARG, "n_markers must be in [0, 2^26)");
+    if (!dev_workspace) return fail(MHD_ERR_INVALID_ARG, "device workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return fail(MHD_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    const Layout L = make_layout(*g, n_markers);
+    if (bytes < L.total)
+        return fail(MHD_ERR_OOM, "workspace has %zu bytes, %zu needed", bytes, L.total);
+    mhd_sim *s = new (std::nothrow) mhd_sim();
+    if (!s) return fail(MHD_ERR_OOM, "host allocation failed");
+    s->g = *g;
+    s->N = (int64_t)g->nx * g->ny * g->nz;
+    s->Mcap = n_markers;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    s->ws = static_cast<char *>(dev_workspace);
+    s->L = L;
+    s->kinds = pack_kinds(g->rho_storage, g->u_storage, g->b_storage);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(MHD_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    }
+    // tile shape: widest x tile that the box fills, 256 work-items per workgroup
+    const int nx = g->nx;
+    s->sweep.tx = nx >= 64 ? 64 : nx >= 32 ? 32 : nx >= 16 ? 16 : 8;
+    s->sweep.ty = 256 / s->sweep.tx;
+    s->sweep.tx = env_int("MHD_SWEEP_TX", s->sweep.tx);
+    s->sweep.ty = 256 / s->sweep.tx;
+    s->sweep.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", 8));
+    // initial state: rho = 1, u = 0, b = 0, t = 0, G = 0
+    DevCtrl hc{};
+    mhd_status st;
+    auto cleanup = [&](mhd_status r) {
+        delete s;
+        return r;
+    };
+    e = hipMemsetAsync(s->ws, 0, L.total, s->stream);
+    if (e != hipSuccess) return cleanup(fail(MHD_ERR_HIP, "hipMemsetAsync failed: %s", hipGetErrorString(e)));
+    e = hipMemcpyAsync(s->ctrl(), &hc, sizeof hc, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return cleanup(fail(MHD_ERR_HIP, "hipMemcpyAsync failed: %s", hipGetErrorString(e)));
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return cleanup(fail(MHD_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e)));
+    (void)st;
+    *out = s;
+    return MHD_OK;
+}
+
+mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const double *u_wall, const double *b_wall) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (M < 0 || M > s->Mcap) return fail(MHD_ERR_INVALID_ARG, "M = %lld outside [0, %lld]", (long long)M, (long long)s->Mcap);
+    if (M > 0 && !xyz) return fail(MHD_ERR_INVALID_ARG, "xyz is NULL");
+    const int n[3] = {s->g.nx, s->g.ny, s->g.nz};
+    for (int64_t j = 0; j < M; ++j)
+        for (int a = 0; a < 3; ++a) {
+            const double v = xyz[a * M + j];
+            if (!(v >= 0.0 && v < (double)n[a]))
+                return fail(MHD_ERR_INVALID_ARG, "marker %lld coordinate %d = %g outside [0, %d)", (long long)j, a, v, n[a]);
+        }
+    // taps with nonzero weight, per marker
+    std::vector<int> mk_ptr((size_t)M + 1, 0), tap_cell;
+    std::vector<double> tap_w;
+    tap_cell.reserve((size_t)M * 9);
+    tap_w.reserve((size_t)M * 9);
+    for (int64_t j = 0; j < M; ++j) {
+        double w[3][3];
+        int base[3];
+        for (int a = 0; a < 3; ++a) base[a] = lagrange_nodes(xyz[a * M + j], w[a]);
+        for (int cz = 0; cz < 3; ++cz)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx = 0; cx < 3; ++cx) {
+                    const double wt = w[0][cx] * w[1][cy] * w[2][cz];
+                    if (wt == 0.0) continue;
+                    const int64_t k = wrap(base[0] + cx, n[0]) +
+                                      (int64_t)n[0] * (wrap(base[1] + cy, n[1]) + (int64_t)n[1] * wrap(base[2] + cz, n[2]));
+                    tap_cell.push_back((int)k);
+                    tap_w.push_back(wt);
+                }
+        mk_ptr[j + 1] = (int)tap_cell.size();
+    }
+    // row sums d_j = sum_k D_jk (sum_i D_ik)
+    std::unordered_map<int, double> S;
+    S.reserve(tap_cell.size() * 2);
+    for (size_t t = 0; t < tap_cell.size(); ++t) S[tap_cell[t]] += tap_w[t];
+    std::vector<double> d((size_t)M);
+    for (int64_t j = 0; j < M; ++j) {
+        double acc = 0.0;
+        for (int t = mk_ptr[j]; t < mk_ptr[j + 1]; ++t) acc += tap_w[t] * S[tap_cell[t]];
+        d[j] = acc;
+    }
+    // gather lists: band cells in increasing index, markers in increasing index per cell
+    std::map<int, std::vector<std::pair<int, double>>> band;
+    for (int64_t j = 0; j < M; ++j)
+        for (int t = mk_ptr[j]; t < mk_ptr[j + 1]; ++t) band[tap_cell[t]].push_back({(int)j, tap_w[t]});
+    std::vector<int> band_cell, band_ptr(1, 0), band_mk;
+    std::vector<float> band_w;
+    band_cell.reserve(band.size());
+    for (auto &kv : band) {
+        band_cell.push_back(kv.first);
+        for (auto &e : kv.second) {
+            band_mk.push_back(e.first);
+            band_w.push_back((float)e.second);
+        }
+        band_ptr.push_back((int)band_mk.size());
+    }
+    std::vector<float> tap_wf(tap_w.begin(), tap_w.end());
+    std::vector<float> uw((size_t)(3 * M), 0.f), bw((size_t)(3 * M), 0.f);
+    if (u_wall)
+        for (int64_t i = 0; i < 3 * M; ++i) uw[i] = (float)u_wall[i];
+    if (b_wall)
+        for (int64_t i = 0; i < 3 * M; ++i) bw[i] = (float)b_wall[i];
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream);
+    };
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(up(s->L.mk_ptr, mk_ptr.data(), mk_ptr.size() * sizeof(int)));
+    HIPCHK(up(s->L.tap_cell, tap_cell.data(), tap_cell.size() * sizeof(int)));
+    HIPCHK(up(s->L.tap_w, tap_wf.data(), tap_wf.size() * sizeof(float)));
+    HIPCHK(up(s->L.uwall, uw.data(), uw.size() * sizeof(float)));
+    HIPCHK(up(s->L.bwall, bw.data(), bw.size() * sizeof(float)));
+    HIPCHK(up(s->L.band_cell, band_cell.data(), band_cell.size() * sizeof(int)));
+    HIPCHK(up(s->L.band_ptr, band_ptr.data(), band_ptr.size() * sizeof(int)));
+    HIPCHK(up(s->L.band_mk, band_mk.data(), band_mk.size() * sizeof(int)));
+    HIPCHK(up(s->L.band_w, band_w.data(), band_w.size() * sizeof(float)));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int64_t oldM = s->M;
+    std::vector<double> oldd = std::move(s->d);
+    s->M = M;
+    s->nband = (int64_t)band_cell.size();
+    s->d = std::move(d);
+    mhd_status st = upload_scalings(s);
+    if (st != MHD_OK) {  // keep the previous wall usable
+        s->M = 0;
+        s->nband = 0;
+        (void)oldM;
+        (void)oldd;
+        return st;
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
+    g_err.clear();
+    if (!s || !p) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    const double tau = 3.0 * p->nu + 0.5;
+    if (!(p->nu > 0.0)) return fail(MHD_ERR_INVALID_ARG, "nu = %g gives tau = %g <= 1/2", p->nu, tau);
+    if (!(tau < 1.0)) return fail(MHD_ERR_UNSUPPORTED, "tau = %g >= 1 needs the macroscopic fluid branch (not built)", tau);
+    if (!(p->eta > 0.0)) return fail(MHD_ERR_INVALID_ARG, "eta must be > 0");
+    if (p->n_mag < 1) return fail(MHD_ERR_INVALID_ARG, "n_mag must be >= 1");
+    if (p->bext_kind < 0 || p->bext_kind > 2) return fail(MHD_ERR_INVALID_ARG, "unknown bext_kind %d", p->bext_kind);
+    if (p->bext_kind == MHD_BEXT_TANH_FRINGE_Y && !(p->fringe_w > 0.0))
+        return fail(MHD_ERR_INVALID_ARG, "fringe_w must be > 0");
+    if (p->flow_control && !(p->avg_radius > 0.0)) return fail(MHD_ERR_INVALID_ARG, "flow control needs avg_radius > 0");
+    for (double v : {p->nu, p->eta, p->lambda_u, p->lambda_b, p->G0, p->G1, p->period, p->B0, p->fringe_x0, p->fringe_w,
+                     p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c})
+        if (!std::isfinite(v)) return fail(MHD_ERR_INVALID_ARG, "non-finite parameter");
+    const bool first = !s->have_params;
+    const mhd_params old = s->prm;
+    s->prm = *p;
+    s->have_params = true;
+    mhd_status st = upload_scalings(s);
+    if (st != MHD_OK) {
+        s->prm = old;
+        s->have_params = !first;
+        return st;
+    }
+    STEPCHK(upload_bext(s));
+    // cells of the flow-rate region r <= R
+    int64_t cnt = 0;
+    const double R2 = p->avg_radius * p->avg_radius;
+    for (int z = 0; z < s->g.nz; ++z)
+        for (int y = 0; y < s->g.ny; ++y) {
+            const double dy = y - p->yc, dz = z - p->zc;
+            if (dy * dy + dz * dz <= R2) cnt += s->g.nx;
+        }
+    s->flow_inv_count = cnt ? 1.0 / (double)cnt : 0.0;
+    if (first) {  // the controlled force starts from G0
+        DevCtrl h;
+        STEPCHK(read_ctrl(s, &h));
+        h.G = p->G0;
+        HIPCHK(hipMemcpyAsync(s->ctrl(), &h, sizeof h, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_set_field(mhd_sim *s, mhd_field f, const double *host) {
+    g_err.clear();
+    if (!s || !host) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (f < MHD_FIELD_RHO || f > MHD_FIELD_B_INDUCED) return fail(MHD_ERR_INVALID_ARG, "unknown field %d", (int)f);
+    const int64_t n = (f == MHD_FIELD_RHO ? 1 : 3) * s->N;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(host[i])) return fail(MHD_ERR_INVALID_ARG, "non-finite value at index %lld", (long long)i);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return fill_field(s, f, host, false);
+}
+
+mhd_status mhd_get_field(mhd_sim *s, mhd_field f, double *host) {
+    g_err.clear();
+    if (!s || !host) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (f < MHD_FIELD_RHO || f > MHD_FIELD_B_INDUCED) return fail(MHD_ERR_INVALID_ARG, "unknown field %d", (int)f);
+    const int ncomp = f == MHD_FIELD_RHO ? 1 : 3;
+    const int64_t n = ncomp * s->N;
+    int kind;
+    double scale = 1.0, offset = 0.0;
+    const void *src;
+    if (f == MHD_FIELD_RHO) {
+        kind = s->g.rho_storage;
+        offset = 1.0;
+        src = s->rho(s->cr);
+    } else if (f == MHD_FIELD_U) {
+        kind = s->g.u_storage;
+        if (kind != MHD_STORE_F32) scale = s->g.u_scale;
+        src = s->u(s->cu);
+    } else {
+        kind = s->g.b_storage;
+        if (kind != MHD_STORE_F32) scale = s->g.b_scale;
+        src = s->b(s->cb);
+    }
+    float *stage = s->at<float>(s->L.F);
+    HIPCHK(launch_load_kind(s->stream, kind, src, stage, n));
+    std::vector<float> tmp((size_t)n);
+    HIPCHK(hipMemcpyAsync(tmp.data(), stage, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < n; ++i) host[i] = (double)tmp[i] * scale + offset;
+    DevCtrl h;
+    STEPCHK(read_ctrl(s, &h));
+    if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a budget pass found non-finite values or |u| >= c_s");
+    return MHD_OK;
+}
+
+mhd_status mhd_get_time(mhd_sim *s, int64_t *t, double *G) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    DevCtrl h;
+    STEPCHK(read_ctrl(s, &h));
+    if (t) *t = h.t;
+    if (G) *G = h.G;
+    return MHD_OK;
+}
+
+mhd_status mhd_set_time(mhd_sim *s, int64_t t, double G) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (t < 0 || !std::isfinite(G)) return fail(MHD_ERR_INVALID_ARG, "t must be >= 0 and G finite");
+    DevCtrl h;
+    STEPCHK(read_ctrl(s, &h));
+    h.t = t;
+    h.G = G;
+    h.G_step = G;
+    HIPCHK(hipMemcpyAsync(s->ctrl(), &h, sizeof h, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->t_host = t;
+    return MHD_OK;
+}
+
+mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called before mhd_step");
+    if (n_steps < 0) return fail(MHD_ERR_INVALID_ARG, "n_steps < 0");
+    for (int64_t i = 0; i < n_steps; ++i) {
+        STEPCHK(one_step(s));
+        if (budget_every > 0 && s->t_host % budget_every == 0) STEPCHK(record_budget(s));
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_record_budget(mhd_sim *s) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called first");
+    return record_budget(s);
+}
+
+mhd_status mhd_get_budgets(mhd_sim *s, mhd_budget *out, int64_t cap, int64_t *n_out) {
+    g_err.clear();
+    if (!s || !n_out) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (cap > 0 && !out) return fail(MHD_ERR_INVALID_ARG, "out is NULL");
+    DevCtrl h;
+    STEPCHK(read_ctrl(s, &h));
+    const int64_t n = std::min<int64_t>(h.n_records, std::max<int64_t>(cap, 0));
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(out, s->at<mhd_budget>(s->L.ring), n * sizeof(mhd_budget), hipMemcpyDeviceToHost,
+                              s->stream));
+    }
+    HIPCHK(launch_reset_records(s->stream, s->ctrl()));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    *n_out = n;
+    if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a budget pass found non-finite values or |u| >= c_s");
+    return MHD_OK;
+}
+
+mhd_status mhd_set_profiling(mhd_sim *s, int32_t enable) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    s->prof = enable != 0;
+    return MHD_OK;
+}
+
+mhd_status mhd_kernel_stats(mhd_sim *s, int32_t kernel, int64_t *launches, double *total_ms) {
+    g_err.clear();
+    if (!s || !launches || !total_ms) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (kernel < 0 || kernel >= MHD_K_COUNT) return fail(MHD_ERR_INVALID_ARG, "unknown kernel id %d", kernel);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < s->ev_used[kernel]; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev_pool[kernel][i].a, s->ev_pool[kernel][i].b));
+        tot += ms;
+    }
+    *launches = (int64_t)s->ev_used[kernel];
+    *total_ms = tot;
+    s->ev_used[kernel] = 0;
+    return MHD_OK;
+}
+
+mhd_status mhd_destroy(mhd_sim *s) {
+    g_err.clear();
+    if (!s) return MHD_OK;
+    (void)hipStreamSynchronize(s->stream);
+    for (int k = 0; k < MHD_K_COUNT; ++k)
+        for (auto &e : s->ev_pool[k]) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    delete s;
+    return MHD_OK;
+}
+
+}  // extern "C"

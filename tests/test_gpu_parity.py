@@ -1,0 +1,287 @@
+"""HIP path vs the FP64 oracle, through the C ABI, on the same seeded inputs.
+
+Error measure (max-normalised, so near-zero cells do not divide by zero):
+    err(f) = max |f_gpu - f_oracle| / max |f_oracle|        for u and b,
+    err(rho) = max |rho_gpu - rho_oracle| / max(max |rho_oracle - 1|, sqrt(3) max |u_oracle|)
+The density offset is measured on the acoustic scale u / c_s: through the continuity equation
+a velocity error du moves rho by about du / c_s, and in slow flows rho - 1 itself (of order
+Ma^2) can be far smaller than that, so dividing by it alone would grade the float32 rounding
+of u, not the density update.
+The bar is 1e-5 for all three in float32 storage: the kernels round each sweep / step at
+~6e-8 relative and the slowest modes contract by ~2e-3 per step, so the accumulated
+round-off stays well below it (about 1e-6 after 2000 steps).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def err(a, ref):
+    scale = np.abs(ref).max()
+    return np.abs(a - ref).max() / scale if scale > 0 else np.abs(a).max()
+
+
+def gpu_run(w, steps, markers=True, budget_every=0, u_wall=None, b_wall=None, **over):
+    from paper_2211_09370_amd import Sim
+
+    M = w.markers.shape[1] if markers else 0
+    sim = Sim(w.nx, w.ny, w.nz, M)
+    if M:
+        sim.set_markers(w.markers, u_wall, b_wall)
+    sim.set_params(w.params, **over)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.step(steps, budget_every)
+    return sim
+
+
+def oracle_run(w, steps, markers=True, u_wall=None, b_wall=None, **over):
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params, **over)
+    o = oracle.Oracle(p, w.markers if markers else None, w.rho, w.u, w.b, u_wall, b_wall)
+    o.step(steps)
+    return o
+
+
+def compare(sim, o, tol=TOL, label=""):
+    rho_scale = max(np.abs(o.rho - 1.0).max(), math.sqrt(3.0) * np.abs(o.u).max())
+    e_r = np.abs(sim.get_field("rho") - o.rho).max() / rho_scale
+    e_u = err(sim.get_field("u"), o.u)
+    e_b = err(sim.get_field("b"), o.b)
+    print(f"{label} err rho-1 {e_r:.2e} u {e_u:.2e} b {e_b:.2e}", flush=True)
+    assert e_u <= tol, ("u", e_u)
+    assert e_b <= tol, ("b", e_b)
+    assert e_r <= tol, ("rho", e_r)
+    return e_r, e_u, e_b
+
+
+def random_box(nx, ny, nz, key, bext_kind=W.BEXT_TANH_FRINGE_Y, n_mag=1, eta=3.0, nu=0.05,
+               R=None):
+    """Random state (u ~ 0.05, b ~ 0.01, rho - 1 ~ 1e-3) in a box, fringe field."""
+    g = W.rng_for(key)
+    rho = 1.0 + 1e-3 * g.uniform(-1, 1, size=(nz, ny, nx))
+    u = 0.05 * g.uniform(-1, 1, size=(3, nz, ny, nx))
+    b = 0.01 * g.uniform(-1, 1, size=(3, nz, ny, nx))
+    R = R if R is not None else 0.3 * min(ny, nz)
+    p = W.Params(nu=nu, eta=eta, n_mag=n_mag, G0=2e-5, bext_kind=bext_kind, B0=0.4,
+                 fringe_x0=nx / 2, fringe_w=3.0, yc=ny // 2, zc=nz // 2, avg_radius=R)
+    X = W.pipe_markers(nx, R, ny // 2, nz // 2)
+    return W.Workload(f"box{nx}x{ny}x{nz}", nx, ny, nz, R, p, X, rho, u, b)
+
+
+# ---------------------------------------------------------------------------------------------
+# single kernels through one step
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(37, 21, 13), (8, 32, 32), (16, 16, 9), (32, 11, 17), (64, 8, 5),
+                                   (100, 12, 10), (1, 24, 1), (130, 5, 3)])
+def test_one_step_no_wall_ragged_shapes(shape):
+    print("case", shape, flush=True)
+    w = random_box(*shape, key=200, n_mag=2)
+    compare(gpu_run(w, 1, markers=False), oracle_run(w, 1, markers=False), label=str(shape))
+
+
+@pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
+def test_one_step_with_wall(bext):
+    w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)
+    compare(gpu_run(w, 1), oracle_run(w, 1), label=f"bext {bext}")
+
+
+def test_nonzero_wall_values():
+    w = random_box(12, 26, 26, key=202, n_mag=4, R=9.0)
+    M = w.markers.shape[1]
+    g = W.rng_for(203)
+    uw = 0.01 * g.uniform(-1, 1, size=(3, M))
+    bw = 0.005 * g.uniform(-1, 1, size=(3, M))
+    compare(gpu_run(w, 2, u_wall=uw, b_wall=bw), oracle_run(w, 2, u_wall=uw, b_wall=bw))
+
+
+# ---------------------------------------------------------------------------------------------
+# whole steps on the pipe workloads
+# ---------------------------------------------------------------------------------------------
+
+def test_small_pipe_10_steps_full_sweeps():
+    w = W.small_pipe()
+    compare(gpu_run(w, 10), oracle_run(w, 10), label="pipe8 10 steps")
+
+
+def test_small_pipe_2000_steps_vs_stored_oracle():
+    path = os.path.join(HERE, "golden", "oracle_pipe8x32x32_2000steps.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run missing (tests/golden/make_oracle_pipe8.py writes it)")
+    ref = np.load(path)
+    w = W.small_pipe()
+    sim = gpu_run(w, int(ref["steps"]))
+
+    class R:
+        rho, u, b = ref["rho"], ref["u"], ref["b"]
+
+    compare(sim, R, label="pipe8 2000 steps")
+
+
+def test_fringe_pipe_full_size_one_step():
+    # the benchmarked workload at its full size and launch configuration, 270 sweeps
+    w = W.fringe_pipe(b_amp=1e-4)
+    compare(gpu_run(w, 1), oracle_run(w, 1), label="fringe128 1 step")
+
+
+def test_quarter_fringe_pipe_20_steps():
+    w = W.quarter_fringe_pipe(b_amp=1e-4)
+    w.params.n_mag = 60
+    compare(gpu_run(w, 20), oracle_run(w, 20), label="fringe32 20 steps")
+
+
+def test_flow_control_and_oscillating_force():
+    w = W.small_pipe()
+    w.params.n_mag = 20
+    w.params.flow_control = 1
+    w.params.u_bulk_target = 0.05
+    w.params.k_c = 0.5
+    sim = gpu_run(w, 25)
+    o = oracle_run(w, 25)
+    compare(sim, o, label="flow control")
+    t, G = sim.time()
+    assert t == 25
+    assert abs(G - o.G.value) <= 1e-6 * abs(o.G.value), (G, o.G.value)
+
+    w2 = W.small_pipe()
+    w2.params.n_mag = 20
+    w2.params.G1 = 3 * w2.params.G0
+    w2.params.period = 7.0
+    compare(gpu_run(w2, 15), oracle_run(w2, 15), label="oscillating G")
+
+
+# ---------------------------------------------------------------------------------------------
+# budgets
+# ---------------------------------------------------------------------------------------------
+
+def test_budget_reduction_matches_oracle_on_the_same_fields():
+    w = W.small_pipe(b_amp=1e-3)
+    w.params.n_mag = 30
+    sim = gpu_run(w, 5, budget_every=5)
+    recs = sim.budgets()
+    assert len(recs) == 1 and recs[0]["step"] == 5
+    r = recs[0]
+    rho, u, b = sim.get_field("rho"), sim.get_field("u"), sim.get_field("b")
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params)
+    ref = oracle.budgets(p, rho, u, b, r["G"])
+    for k in ("E_k", "E_m", "E_b", "P_in", "P_p", "P_nu", "P_L", "M_eta", "M_adv", "joule", "mass",
+              "Q", "u_max", "n_omega"):
+        scale = max(abs(ref[k]), 1e-300)
+        assert abs(r[k] - ref[k]) <= 1e-9 * scale, (k, r[k], ref[k])
+
+
+def test_budget_trajectory_matches_oracle():
+    w = W.small_pipe()
+    w.params.n_mag = 40
+    sim = gpu_run(w, 30, budget_every=10)
+    recs = sim.budgets()
+    assert [r["step"] for r in recs] == [10, 20, 30]
+    o = oracle_run(w, 30)
+    ref = o.budgets()
+    for k in ("E_k", "E_m", "E_b", "Q", "mass"):
+        assert abs(recs[-1][k] - ref[k]) <= 3e-5 * abs(ref[k]), (k, recs[-1][k], ref[k])
+    for k in ("P_nu", "P_L", "M_eta", "M_adv", "joule"):
+        assert abs(recs[-1][k] - ref[k]) <= 1e-3 * abs(ref[k]), (k, recs[-1][k], ref[k])
+
+
+# ---------------------------------------------------------------------------------------------
+# properties
+# ---------------------------------------------------------------------------------------------
+
+def test_runs_are_bitwise_deterministic():
+    w = W.small_pipe()
+    w.params.n_mag = 50
+    a = gpu_run(w, 6)
+    b = gpu_run(w, 6)
+    for f in ("rho", "u", "b"):
+        assert np.array_equal(a.get_field(f), b.get_field(f)), f
+
+
+def test_checkpoint_resume_is_bitwise():
+    w = W.small_pipe()
+    w.params.n_mag = 30
+    w.params.G1 = w.params.G0
+    w.params.period = 5.0
+    full = gpu_run(w, 8)
+    half = gpu_run(w, 4)
+    state = {f: half.get_field(f) for f in ("rho", "u", "b")}
+    t, G = half.time()
+    from paper_2211_09370_amd import Sim
+
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+    sim.set_markers(w.markers)
+    sim.set_params(w.params)
+    for f, v in state.items():
+        sim.set_field(f, v)
+    sim.set_time(t, G)
+    sim.step(4)
+    for f in ("rho", "u", "b"):
+        assert np.array_equal(sim.get_field(f), full.get_field(f)), f
+
+
+def test_mass_is_conserved_in_float32():
+    w = W.small_pipe(rho_amp=1e-3)
+    w.params.n_mag = 10
+    sim = gpu_run(w, 100)
+    m0 = w.rho.sum()
+    assert abs(sim.get_field("rho").sum() - m0) <= 1e-9 * m0
+
+
+def test_unstable_state_is_reported():
+    from paper_2211_09370_amd import _abi
+
+    w = W.small_pipe()
+    w.params.n_mag = 2
+    u = w.u.copy()
+    u[0, 3, 4, 5] = 0.9
+    w.u = u
+    sim = gpu_run(w, 0)
+    sim.record_budget()
+    sim.budgets()
+    assert sim.last_status == _abi.MHD_ERR_UNSTABLE
+    sim.get_field("u")
+    assert sim.last_status == _abi.MHD_ERR_UNSTABLE
+
+
+def test_argument_checks():
+    from paper_2211_09370_amd import MhdError, Sim, _abi
+
+    w = W.small_pipe()
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+    with pytest.raises(MhdError) as e:
+        sim.step(1)
+    assert e.value.status == _abi.MHD_ERR_STATE
+    for over, st in ((dict(nu=0.2), _abi.MHD_ERR_UNSUPPORTED), (dict(nu=0.0), _abi.MHD_ERR_INVALID_ARG),
+                     (dict(n_mag=0), _abi.MHD_ERR_INVALID_ARG), (dict(eta=-1.0), _abi.MHD_ERR_INVALID_ARG)):
+        with pytest.raises(MhdError) as e:
+            sim.set_params(w.params, **over)
+        assert e.value.status == st, over
+    sim.set_markers(w.markers)
+    with pytest.raises(MhdError) as e:  # 1 + d_j (lambda - 1) <= 0 for the outermost d_j
+        sim.set_params(w.params, lambda_u=0.02)
+    assert e.value.status == _abi.MHD_ERR_INVALID_ARG
+    bad = w.markers.copy()
+    bad[1, 0] = w.ny + 0.5
+    with pytest.raises(MhdError) as e:
+        sim.set_markers(bad)
+    assert e.value.status == _abi.MHD_ERR_INVALID_ARG
+    with pytest.raises(MhdError):
+        sim.set_markers(np.zeros((3, w.markers.shape[1] + 1)))
+    bad_u = w.u.copy()
+    bad_u[0, 0, 0, 0] = np.nan
+    with pytest.raises(MhdError):
+        sim.set_field("u", bad_u)
+    sim.set_params(w.params)
+    sim.step(0)  # empty request is a no-op
+    assert sim.time()[0] == 0

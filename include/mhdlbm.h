@@ -152,14 +152,13 @@ mhd_status mhd_record_budget(mhd_sim *s);
  * launch of the kernels with events; mhd_kernel_stats synchronises and returns the number of
  * timed launches and their summed duration for one kernel id, then forgets them. */
 typedef enum {
-    MHD_K_MAG_SWEEP = 0,
-    MHD_K_IB_INTERP = 1,
-    MHD_K_IB_SPREAD = 2,
-    MHD_K_LORENTZ = 3,
-    MHD_K_FLUID = 4,
-    MHD_K_BUDGET = 5,
-    MHD_K_CONTROL = 6,
-    MHD_K_COUNT = 7
+    MHD_K_MAG_SWEEP = 0, /* magnetic sweep                                              */
+    MHD_K_IB = 1,        /* wall correction of b or u (one launch, two for huge groups)  */
+    MHD_K_LORENTZ = 2,
+    MHD_K_FLUID = 3,
+    MHD_K_BUDGET = 4,
+    MHD_K_CONTROL = 5,   /* body force, flow-rate control, step counter                  */
+    MHD_K_COUNT = 6
 } mhd_kernel_id;
 mhd_status mhd_set_profiling(mhd_sim *s, int32_t enable);
 mhd_status mhd_kernel_stats(mhd_sim *s, int32_t kernel, int64_t *launches, double *total_ms);

@@ -15,7 +15,7 @@ import numpy as np
 from . import _abi
 from ._abi import (MHD_BEXT_NONE, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_UNIFORM_Y, MHD_FIELD_B_INDUCED,
                    MHD_FIELD_RHO, MHD_FIELD_U, MHD_K_BUDGET, MHD_K_CONTROL, MHD_K_FLUID,
-                   MHD_K_IB_INTERP, MHD_K_IB_SPREAD, MHD_K_LORENTZ, MHD_K_MAG_SWEEP,
+                   MHD_K_IB, MHD_K_LORENTZ, MHD_K_MAG_SWEEP,
                    MHD_STORE_BF16, MHD_STORE_F16, MHD_STORE_F32, MhdError, mhd_budget,
                    mhd_grid_desc, mhd_params)
 

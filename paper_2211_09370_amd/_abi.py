@@ -24,8 +24,8 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "UNSTABLE"
 MHD_STORE_F32, MHD_STORE_F16, MHD_STORE_BF16 = 0, 1, 2
 MHD_BEXT_NONE, MHD_BEXT_UNIFORM_Y, MHD_BEXT_TANH_FRINGE_Y = 0, 1, 2
 MHD_FIELD_RHO, MHD_FIELD_U, MHD_FIELD_B_INDUCED = 0, 1, 2
-(MHD_K_MAG_SWEEP, MHD_K_IB_INTERP, MHD_K_IB_SPREAD, MHD_K_LORENTZ, MHD_K_FLUID, MHD_K_BUDGET,
- MHD_K_CONTROL, MHD_K_COUNT) = range(8)
+(MHD_K_MAG_SWEEP, MHD_K_IB, MHD_K_LORENTZ, MHD_K_FLUID, MHD_K_BUDGET, MHD_K_CONTROL,
+ MHD_K_COUNT) = range(7)
 
 EXPORTS = ("mhd_last_error", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",

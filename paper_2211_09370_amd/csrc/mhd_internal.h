@@ -49,12 +49,21 @@ hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part
                            double inv_count);
 hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo,
                             const float *bext, StepConst c, SweepLaunch L);
-hipError_t launch_ib_interp(hipStream_t s, int kind, const void *phi, float scale, int64_t N,
-                            int M, const int *mk_ptr, const int *tap_cell, const float *tap_w,
-                            const float *sj, const float *wall, float *delta);
-hipError_t launch_ib_spread(hipStream_t s, int kind, void *phi, float scale, float inv_scale,
-                            int64_t N, int nband, const int *band_cell, const int *band_ptr,
-                            const int *band_mk, const float *band_w, const float *delta, int M);
+// Wall correction data (device pointers), markers in the library's internal order.
+struct IbArgs {
+    int64_t N;
+    int M, nband, tm, km;
+    const int *tap_cell;   // [tm][M] cells of the taps (padded taps repeat a valid cell)
+    const float *tap_w;    // [tm][M] weights D_jk (0 for padding)
+    const float *sj;       // [M] diagonal scaling
+    const float *wall;     // [3][M] imposed wall values
+    const int *band_cell;  // [nband] cells touched by some marker, increasing
+    const int *band_mk;    // [km][nband] marker of each gather entry (padding: a valid marker)
+    const float *band_w;   // [km][nband] weight of each gather entry (0 for padding)
+    float *delta;          // [3][M] Lagrangian corrections
+};
+// Interpolation launch, then spreading launch.
+hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_scale, const IbArgs &a);
 hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const float *bext,
                           const DevCtrl *ctrl, float *F, StepConst c);
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,

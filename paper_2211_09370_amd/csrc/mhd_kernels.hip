@@ -322,50 +322,68 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
 // -------------------------------------------------------------------------------------------
 // Immersed boundary (Sec. 5.2 - 5.6), explicit diagonal form:
 //   delta_j = s_j (phi_wall_j - sum_k D_jk phi*_k),  phi_k = phi*_k + sum_j D_jk delta_j,
-// s_j = lambda / (d_j (1 + d_j (lambda - 1))). Interpolation per marker, spreading per cell of
-// the wall band through a cell -> markers gather list (deterministic, no atomics).
+// s_j = lambda / (d_j (1 + d_j (lambda - 1))).
+// Two launches: every interpolation (per marker, to delta in memory) is taken before any cell
+// changes (per wall-band cell gather, no atomics, entries in marker order). Taps of a marker
+// and entries of a cell are padded to fixed counts (weight 0) and stored structure-of-arrays,
+// so all loads of a thread are independent. Markers are ordered by the (y, z) of their stencil
+// and then by x, band cells by cell index: neighbouring lanes of a wave then address
+// neighbouring x, i.e. consecutive words of the x-fastest fields.
 // -------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_ib_interp(const T *phi, float scale, int64_t N, int M, const int *mk_ptr,
-                                                   const int *tap_cell, const float *tap_w, const float *sj,
-                                                   const float *wall, float *delta) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
+__device__ __forceinline__ void ib_marker(const T *phi, float scale, const IbArgs &a, int j, float &d0, float &d1,
+                                          float &d2) {
     float I0 = 0.f, I1 = 0.f, I2 = 0.f;
-    const int e = mk_ptr[j + 1];
-    for (int t = mk_ptr[j]; t < e; ++t) {
-        const int64_t k = tap_cell[t];
-        const float w = tap_w[t];
+#pragma unroll 9
+    for (int t = 0; t < a.tm; ++t) {
+        const int64_t k = a.tap_cell[(int64_t)t * a.M + j];
+        const float w = a.tap_w[(int64_t)t * a.M + j];
         I0 += w * (St<T>::ld(phi, k) * scale);
-        I1 += w * (St<T>::ld(phi, N + k) * scale);
-        I2 += w * (St<T>::ld(phi, 2 * N + k) * scale);
+        I1 += w * (St<T>::ld(phi, a.N + k) * scale);
+        I2 += w * (St<T>::ld(phi, 2 * a.N + k) * scale);
     }
-    const float s = sj[j];
-    const float t0 = wall ? wall[j] : 0.f, t1 = wall ? wall[M + j] : 0.f, t2 = wall ? wall[2 * M + j] : 0.f;
-    delta[j] = s * (t0 - I0);
-    delta[M + j] = s * (t1 - I1);
-    delta[2 * M + j] = s * (t2 - I2);
+    const float s = a.sj[j];
+    d0 = s * (a.wall[j] - I0);
+    d1 = s * (a.wall[a.M + j] - I1);
+    d2 = s * (a.wall[2 * a.M + j] - I2);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_ib_spread(T *phi, float scale, float inv_scale, int64_t N, int nband,
-                                                   const int *band_cell, const int *band_ptr, const int *band_mk,
-                                                   const float *band_w, const float *delta, int M) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nband) return;
-    const int64_t k = band_cell[e];
+__device__ __forceinline__ void ib_cell(T *phi, float scale, float inv_scale, const IbArgs &a, int e,
+                                        const float *d0, const float *d1, const float *d2, int base) {
+    const int64_t k = a.band_cell[e];
+    const float v0 = St<T>::ld(phi, k) * scale, v1 = St<T>::ld(phi, a.N + k) * scale,
+                v2 = St<T>::ld(phi, 2 * a.N + k) * scale;
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    const int qe = band_ptr[e + 1];
-    for (int q = band_ptr[e]; q < qe; ++q) {
-        const int j = band_mk[q];
-        const float w = band_w[q];
-        c0 += w * delta[j];
-        c1 += w * delta[M + j];
-        c2 += w * delta[2 * M + j];
+#pragma unroll 4
+    for (int q = 0; q < a.km; ++q) {
+        const int j = a.band_mk[(int64_t)q * a.nband + e] - base;
+        const float w = a.band_w[(int64_t)q * a.nband + e];
+        c0 += w * d0[j];
+        c1 += w * d1[j];
+        c2 += w * d2[j];
     }
-    St<T>::st(phi, k, (St<T>::ld(phi, k) * scale + c0) * inv_scale);
-    St<T>::st(phi, N + k, (St<T>::ld(phi, N + k) * scale + c1) * inv_scale);
-    St<T>::st(phi, 2 * N + k, (St<T>::ld(phi, 2 * N + k) * scale + c2) * inv_scale);
+    St<T>::st(phi, k, (v0 + c0) * inv_scale);
+    St<T>::st(phi, a.N + k, (v1 + c1) * inv_scale);
+    St<T>::st(phi, 2 * a.N + k, (v2 + c2) * inv_scale);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_interp(const T *phi, float scale, IbArgs a) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.M) return;
+    float d0, d1, d2;
+    ib_marker(phi, scale, a, j, d0, d1, d2);
+    a.delta[j] = d0;
+    a.delta[a.M + j] = d1;
+    a.delta[2 * a.M + j] = d2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ib_spread(T *phi, float scale, float inv_scale, IbArgs a) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.nband) return;
+    ib_cell(phi, scale, inv_scale, a, e, a.delta, a.delta + a.M, a.delta + 2 * a.M, 0);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -784,34 +802,16 @@ hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void 
     }
 
 template <typename T>
-static hipError_t ib_interp_t(hipStream_t s, const void *phi, float scale, int64_t N, int M, const int *mk_ptr,
-                              const int *tap_cell, const float *tap_w, const float *sj, const float *wall,
-                              float *delta) {
-    if (M <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ib_interp<T>, dim3(blocks_for(M, 256)), dim3(256), 0, s, (const T *)phi, scale, N, M, mk_ptr,
-                       tap_cell, tap_w, sj, wall, delta);
+static hipError_t ib_t(hipStream_t s, void *phi, float scale, float inv_scale, const IbArgs &a) {
+    if (a.M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ib_interp<T>, dim3(blocks_for(a.M, 256)), dim3(256), 0, s, (const T *)phi, scale, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.nband <= 0) return e;
+    hipLaunchKernelGGL(k_ib_spread<T>, dim3(blocks_for(a.nband, 256)), dim3(256), 0, s, (T *)phi, scale, inv_scale, a);
     return hipGetLastError();
 }
-hipError_t launch_ib_interp(hipStream_t s, int kind, const void *phi, float scale, int64_t N, int M, const int *mk_ptr,
-                            const int *tap_cell, const float *tap_w, const float *sj, const float *wall,
-                            float *delta) {
-    MHD_DISPATCH1(kind, ib_interp_t, s, phi, scale, N, M, mk_ptr, tap_cell, tap_w, sj, wall, delta)
-}
-
-template <typename T>
-static hipError_t ib_spread_t(hipStream_t s, void *phi, float scale, float inv_scale, int64_t N, int nband,
-                              const int *band_cell, const int *band_ptr, const int *band_mk, const float *band_w,
-                              const float *delta, int M) {
-    if (nband <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ib_spread<T>, dim3(blocks_for(nband, 256)), dim3(256), 0, s, (T *)phi, scale, inv_scale, N,
-                       nband, band_cell, band_ptr, band_mk, band_w, delta, M);
-    return hipGetLastError();
-}
-hipError_t launch_ib_spread(hipStream_t s, int kind, void *phi, float scale, float inv_scale, int64_t N, int nband,
-                            const int *band_cell, const int *band_ptr, const int *band_mk, const float *band_w,
-                            const float *delta, int M) {
-    MHD_DISPATCH1(kind, ib_spread_t, s, phi, scale, inv_scale, N, nband, band_cell, band_ptr, band_mk, band_w, delta,
-                  M)
+hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_scale, const IbArgs &a) {
+    MHD_DISPATCH1(kind, ib_t, s, phi, scale, inv_scale, a)
 }
 
 template <typename T>

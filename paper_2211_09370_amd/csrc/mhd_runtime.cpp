@@ -44,16 +44,20 @@ size_t kind_bytes(int k) { return k == MHD_STORE_F32 ? 4 : 2; }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Padded gather entries reserved per marker of capacity (band cells x entries per cell).
+constexpr int64_t kBandSlots = 64;
+
 // Byte offsets of every region of the caller's workspace.
 struct Layout {
-    size_t rho[2], u[2], b[2], F, bext, ctrl, mk_ptr, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
-    size_t band_cell, band_ptr, band_mk, band_w, red_part, flow_part, ring, total;
+    size_t rho[2], u[2], b[2], F, bext, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
+    size_t band_cell, band_mk, band_w, red_part, flow_part, ring, total;
 };
 
 Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     Layout L{};
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t T = 27 * std::max<int64_t>(M, 0);  // taps / gather entries, at most 27 per marker
+    const int64_t T = 27 * std::max<int64_t>(M, 0);  // taps, at most 27 per marker
+    const int64_t TB = kBandSlots * std::max<int64_t>(M, 0);  // padded gather entries
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -66,7 +70,6 @@ Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     L.F = take(3 * N * sizeof(float));
     L.bext = take(3 * (size_t)g.nx * sizeof(float));
     L.ctrl = take(sizeof(DevCtrl));
-    L.mk_ptr = take((M + 1) * sizeof(int));
     L.tap_cell = take(T * sizeof(int));
     L.tap_w = take(T * sizeof(float));
     L.s_u = take(M * sizeof(float));
@@ -75,9 +78,8 @@ Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     L.bwall = take(3 * M * sizeof(float));
     L.delta = take(3 * M * sizeof(float));
     L.band_cell = take(T * sizeof(int));
-    L.band_ptr = take((T + 1) * sizeof(int));
-    L.band_mk = take(T * sizeof(int));
-    L.band_w = take(T * sizeof(float));
+    L.band_mk = take(TB * sizeof(int));
+    L.band_w = take(TB * sizeof(float));
     L.red_part = take((size_t)kRedBlocks * kBudgetVals * sizeof(double));
     L.flow_part = take((size_t)kRedBlocks * sizeof(double));
     L.ring = take((size_t)kRingCap * sizeof(mhd_budget));
@@ -140,7 +142,8 @@ struct mhd_sim {
     bool have_params = false;
     mhd_params prm{};
     int64_t M = 0, nband = 0;
-    std::vector<double> d;  // row sums of D D^T
+    int tm = 0, km = 0;
+    std::vector<double> d;  // row sums of D D^T (internal marker order)
     int64_t t_host = 0;
     SweepLaunch sweep{64, 4, 8};
     double flow_inv_count = 0.0;
@@ -292,18 +295,22 @@ mhd_status timed(mhd_sim *s, int k, const char *what, Fn fn) {
 mhd_status ib_correct(mhd_sim *s, int kind, void *phi, float scale, float inv_scale, const float *sj,
                       const float *wall) {
     if (s->M == 0) return MHD_OK;
-    const int M = (int)s->M;
-    float *delta = s->at<float>(s->L.delta);
-    STEPCHK(timed(s, MHD_K_IB_INTERP, "ib_interp", [&] {
-        return launch_ib_interp(s->stream, kind, phi, scale, s->N, M, s->at<int>(s->L.mk_ptr), s->at<int>(s->L.tap_cell),
-                                s->at<float>(s->L.tap_w), sj, wall, delta);
-    }));
-    STEPCHK(timed(s, MHD_K_IB_SPREAD, "ib_spread", [&] {
-        return launch_ib_spread(s->stream, kind, phi, scale, inv_scale, s->N, (int)s->nband, s->at<int>(s->L.band_cell),
-                                s->at<int>(s->L.band_ptr), s->at<int>(s->L.band_mk), s->at<float>(s->L.band_w), delta,
-                                M);
-    }));
-    return MHD_OK;
+    IbArgs a;
+    a.N = s->N;
+    a.M = (int)s->M;
+    a.nband = (int)s->nband;
+    a.tm = s->tm;
+    a.km = s->km;
+    a.tap_cell = s->at<int>(s->L.tap_cell);
+    a.tap_w = s->at<float>(s->L.tap_w);
+    a.sj = sj;
+    a.wall = wall;
+    a.band_cell = s->at<int>(s->L.band_cell);
+    a.band_mk = s->at<int>(s->L.band_mk);
+    a.band_w = s->at<float>(s->L.band_w);
+    a.delta = s->at<float>(s->L.delta);
+    return timed(s, MHD_K_IB, "wall correction",
+                 [&] { return launch_ib(s->stream, kind, phi, scale, inv_scale, a); });
 }
 
 mhd_status one_step(mhd_sim *s) {
@@ -446,11 +453,11 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
             if (!(v >= 0.0 && v < (double)n[a]))
                 return fail(MHD_ERR_INVALID_ARG, "marker %lld coordinate %d = %g outside [0, %d)", (long long)j, a, v, n[a]);
         }
-    // taps with nonzero weight, per marker
-    std::vector<int> mk_ptr((size_t)M + 1, 0), tap_cell;
-    std::vector<double> tap_w;
-    tap_cell.reserve((size_t)M * 9);
-    tap_w.reserve((size_t)M * 9);
+    // 1. nonzero Lagrange taps of every marker (original order)
+    std::vector<int> tptr((size_t)M + 1, 0), tcell;
+    std::vector<double> tw;
+    tcell.reserve((size_t)M * 9);
+    tw.reserve((size_t)M * 9);
     for (int64_t j = 0; j < M; ++j) {
         double w[3][3];
         int base[3];
@@ -462,68 +469,99 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
                     if (wt == 0.0) continue;
                     const int64_t k = wrap(base[0] + cx, n[0]) +
                                       (int64_t)n[0] * (wrap(base[1] + cy, n[1]) + (int64_t)n[1] * wrap(base[2] + cz, n[2]));
-                    tap_cell.push_back((int)k);
-                    tap_w.push_back(wt);
+                    tcell.push_back((int)k);
+                    tw.push_back(wt);
                 }
-        mk_ptr[j + 1] = (int)tap_cell.size();
+        tptr[j + 1] = (int)tcell.size();
     }
-    // row sums d_j = sum_k D_jk (sum_i D_ik)
+    // 2. row sums d_j = sum_k D_jk (sum_i D_ik)
     std::unordered_map<int, double> S;
-    S.reserve(tap_cell.size() * 2);
-    for (size_t t = 0; t < tap_cell.size(); ++t) S[tap_cell[t]] += tap_w[t];
-    std::vector<double> d((size_t)M);
+    S.reserve(tcell.size() * 2);
+    for (size_t t = 0; t < tcell.size(); ++t) S[tcell[t]] += tw[t];
+    std::vector<double> d0((size_t)M);
     for (int64_t j = 0; j < M; ++j) {
         double acc = 0.0;
-        for (int t = mk_ptr[j]; t < mk_ptr[j + 1]; ++t) acc += tap_w[t] * S[tap_cell[t]];
-        d[j] = acc;
+        for (int t = tptr[j]; t < tptr[j + 1]; ++t) acc += tw[t] * S[tcell[t]];
+        d0[j] = acc;
     }
-    // gather lists: band cells in increasing index, markers in increasing index per cell
-    std::map<int, std::vector<std::pair<int, double>>> band;
-    for (int64_t j = 0; j < M; ++j)
-        for (int t = mk_ptr[j]; t < mk_ptr[j + 1]; ++t) band[tap_cell[t]].push_back({(int)j, tap_w[t]});
-    std::vector<int> band_cell, band_ptr(1, 0), band_mk;
-    std::vector<float> band_w;
-    band_cell.reserve(band.size());
-    for (auto &kv : band) {
-        band_cell.push_back(kv.first);
-        for (auto &e : kv.second) {
-            band_mk.push_back(e.first);
-            band_w.push_back((float)e.second);
+    // 3. internal order: by the (y, z) of the first tap, then x, so that markers at the same
+    //    cross-section position on neighbouring x planes sit next to each other
+    const int nx = n[0];
+    std::vector<int64_t> perm((size_t)M);
+    for (int64_t j = 0; j < M; ++j) perm[j] = j;
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+        const int ka = tcell[tptr[a]], kb = tcell[tptr[b]];
+        const int ya = ka / nx, yb = kb / nx;
+        return ya != yb ? ya < yb : (ka % nx) < (kb % nx);
+    });
+    int tm = 1;
+    for (int64_t j = 0; j < M; ++j) tm = std::max(tm, tptr[j + 1] - tptr[j]);
+    std::vector<int> tap_cell((size_t)tm * M);
+    std::vector<float> tap_w((size_t)tm * M, 0.f);
+    std::vector<double> d((size_t)M);
+    for (int64_t i = 0; i < M; ++i) {
+        const int64_t j = perm[i];
+        d[i] = d0[j];
+        for (int t = 0; t < tm; ++t) {
+            const int src = tptr[j] + t;
+            const bool real = src < tptr[j + 1];
+            tap_cell[(size_t)t * M + i] = real ? tcell[src] : tcell[tptr[j]];
+            tap_w[(size_t)t * M + i] = real ? (float)tw[src] : 0.f;
         }
-        band_ptr.push_back((int)band_mk.size());
     }
-    std::vector<float> tap_wf(tap_w.begin(), tap_w.end());
+    // 4. band cells in increasing index, each with its (internal marker, weight) entries
+    std::map<int, std::vector<std::pair<int, double>>> band;
+    for (int64_t i = 0; i < M; ++i) {
+        const int64_t j = perm[i];
+        for (int t = tptr[j]; t < tptr[j + 1]; ++t) band[tcell[t]].push_back({(int)i, tw[t]});
+    }
+    const int64_t nband = (int64_t)band.size();
+    int km = 1;
+    for (auto &kv : band) km = std::max<int>(km, (int)kv.second.size());
+    if (nband * km > kBandSlots * s->Mcap)
+        return fail(MHD_ERR_INVALID_ARG, "markers too dense: %lld wall cells x %d entries exceed the workspace",
+                    (long long)nband, km);
+    std::vector<int> band_cell((size_t)nband), band_mk((size_t)nband * km);
+    std::vector<float> band_w((size_t)nband * km, 0.f);
+    int64_t e = 0;
+    for (auto &kv : band) {
+        band_cell[e] = kv.first;
+        for (int q = 0; q < km; ++q) {
+            const bool real = q < (int)kv.second.size();
+            band_mk[(size_t)q * nband + e] = real ? kv.second[q].first : kv.second[0].first;
+            band_w[(size_t)q * nband + e] = real ? (float)kv.second[q].second : 0.f;
+        }
+        ++e;
+    }
+    // 5. wall values in internal order
     std::vector<float> uw((size_t)(3 * M), 0.f), bw((size_t)(3 * M), 0.f);
-    if (u_wall)
-        for (int64_t i = 0; i < 3 * M; ++i) uw[i] = (float)u_wall[i];
-    if (b_wall)
-        for (int64_t i = 0; i < 3 * M; ++i) bw[i] = (float)b_wall[i];
+    for (int64_t i = 0; i < M; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (u_wall) uw[(size_t)a * M + i] = (float)u_wall[a * M + perm[i]];
+            if (b_wall) bw[(size_t)a * M + i] = (float)b_wall[a * M + perm[i]];
+        }
     auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream);
     };
     HIPCHK(hipStreamSynchronize(s->stream));
-    HIPCHK(up(s->L.mk_ptr, mk_ptr.data(), mk_ptr.size() * sizeof(int)));
     HIPCHK(up(s->L.tap_cell, tap_cell.data(), tap_cell.size() * sizeof(int)));
-    HIPCHK(up(s->L.tap_w, tap_wf.data(), tap_wf.size() * sizeof(float)));
+    HIPCHK(up(s->L.tap_w, tap_w.data(), tap_w.size() * sizeof(float)));
     HIPCHK(up(s->L.uwall, uw.data(), uw.size() * sizeof(float)));
     HIPCHK(up(s->L.bwall, bw.data(), bw.size() * sizeof(float)));
     HIPCHK(up(s->L.band_cell, band_cell.data(), band_cell.size() * sizeof(int)));
-    HIPCHK(up(s->L.band_ptr, band_ptr.data(), band_ptr.size() * sizeof(int)));
     HIPCHK(up(s->L.band_mk, band_mk.data(), band_mk.size() * sizeof(int)));
     HIPCHK(up(s->L.band_w, band_w.data(), band_w.size() * sizeof(float)));
     HIPCHK(hipStreamSynchronize(s->stream));
-    const int64_t oldM = s->M;
-    std::vector<double> oldd = std::move(s->d);
     s->M = M;
-    s->nband = (int64_t)band_cell.size();
+    s->nband = nband;
+    s->tm = tm;
+    s->km = km;
     s->d = std::move(d);
     mhd_status st = upload_scalings(s);
-    if (st != MHD_OK) {  // keep the previous wall usable
+    if (st != MHD_OK) {  // the wall is dropped rather than left half-configured
         s->M = 0;
         s->nband = 0;
-        (void)oldM;
-        (void)oldd;
         return st;
     }
     return MHD_OK;

@@ -106,6 +106,22 @@ def test_nonzero_wall_values():
     compare(gpu_run(w, 2, u_wall=uw, b_wall=bw), oracle_run(w, 2, u_wall=uw, b_wall=bw))
 
 
+def test_off_plane_markers_form_one_group():
+    # markers between x planes couple neighbouring planes: the whole wall becomes one group
+    w = random_box(10, 24, 24, key=204, n_mag=3, R=8.2)
+    w.markers[0] += 0.37 * ((np.arange(w.markers.shape[1]) % 3) - 1) % w.nx
+    w.markers[0] %= w.nx
+    compare(gpu_run(w, 2), oracle_run(w, 2), label="off-plane markers")
+
+
+def test_dense_marker_cloud():
+    # two close concentric rings: wall-band cells gather from many markers (long entry lists)
+    w = random_box(6, 30, 30, key=205, n_mag=3, R=10.0)
+    inner = W.pipe_markers(w.nx, 9.4, w.ny // 2, w.nz // 2, m_slice=97)
+    w.markers = np.concatenate([w.markers, inner], axis=1)
+    compare(gpu_run(w, 2), oracle_run(w, 2), label="dense markers")
+
+
 # ---------------------------------------------------------------------------------------------
 # whole steps on the pipe workloads
 # ---------------------------------------------------------------------------------------------

@@ -475,7 +475,8 @@ void orc_step(orc_ctx *c, double *rho, double *u, double *b, int64_t n, int64_t 
         /* 3. fluid predictor */
         orc_fluid(p, rho, u, c->F, c->rho2, c->u2);
         /* 4. velocity wall correction (density is not corrected) */
-        if (p->ib_u && c->M > 0) orc_ib_correct(p, c->M, c->X, c->d, p->lambda_u, c->uwall, c->u2);
+        if (p->ib_u && c->M > 0)
+            orc_ib_correct(p, c->M, c->X, c->d, p->lambda_u > 0.0 ? p->lambda_u : 1.0, c->uwall, c->u2);
         memcpy(rho, c->rho2, (size_t)N * sizeof(double));
         memcpy(u, c->u2, (size_t)(3 * N) * sizeof(double));
         /* 5. flow-rate control of the driving force (integral law on the bulk velocity) */

@@ -19,6 +19,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mhd_internal.h"
 
 namespace mhd {
@@ -28,15 +30,23 @@ namespace mhd {
 // -------------------------------------------------------------------------------------------
 template <typename T>
 struct St;
+// cvt: stored value -> float; from: float times inverse scale -> stored value (float32 storage
+// ignores the scale, which is 1 there).
 template <>
 struct St<float> {
     static __device__ __forceinline__ float ld(const float *p, int64_t i) { return p[i]; }
     static __device__ __forceinline__ void st(float *p, int64_t i, float v) { p[i] = v; }
+    static __device__ __forceinline__ float cvt(float v) { return v; }
+    static __device__ __forceinline__ float val(float v, float) { return v; }
+    static __device__ __forceinline__ float from(float v, float) { return v; }
 };
 template <>
 struct St<__half> {
     static __device__ __forceinline__ float ld(const __half *p, int64_t i) { return __half2float(p[i]); }
     static __device__ __forceinline__ void st(__half *p, int64_t i, float v) { p[i] = __float2half_rn(v); }
+    static __device__ __forceinline__ float cvt(__half v) { return __half2float(v); }
+    static __device__ __forceinline__ float val(__half v, float scale) { return __half2float(v) * scale; }
+    static __device__ __forceinline__ __half from(float v, float inv) { return __float2half_rn(v * inv); }
 };
 template <>
 struct St<__hip_bfloat16> {
@@ -46,7 +56,21 @@ struct St<__hip_bfloat16> {
     static __device__ __forceinline__ void st(__hip_bfloat16 *p, int64_t i, float v) {
         p[i] = __float2bfloat16(v);
     }
+    static __device__ __forceinline__ float cvt(__hip_bfloat16 v) { return __bfloat162float(v); }
+    static __device__ __forceinline__ float val(__hip_bfloat16 v, float scale) { return __bfloat162float(v) * scale; }
+    static __device__ __forceinline__ __hip_bfloat16 from(float v, float inv) { return __float2bfloat16(v * inv); }
 };
+
+// Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the
+// scalar-base + 32-bit vector-offset addressing form instead of 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, unsigned byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, unsigned byte_off, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
 
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
@@ -142,7 +166,8 @@ template <int TX, int TY, typename TU, typename TB>
 __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
     constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
     constexpr int NSLOT = (HN + NT - 1) / NT;
-    __shared__ float s_bx[HN], s_by[HN], s_bz[HN], s_lxy[HN], s_lxz[HN], s_lyz[HN];
+    // two LDS planes: the next plane is staged while the current one is reduced
+    __shared__ float s_pl[2][6][HN];
 
     // XCD-aware order: the hardware hands consecutive workgroups to the 8 XCDs in turn; give
     // each XCD a contiguous run of tiles so neighbouring tiles share halo rows in one L2.
@@ -157,12 +182,12 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
     const int z0 = tiz * a.zchunk;
     const int z1 = min(z0 + a.zchunk, a.nz);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int64_t N = (int64_t)nx * ny * nz;
-    const int plane = nx * ny;
+    const unsigned N = (unsigned)nx * ny * nz;  // 3 N < 2^31: 32-bit offsets from uniform bases
+    const unsigned plane = (unsigned)nx * ny;
 
-    const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * N;
-    const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * N;
-    TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * N;
+    const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * (size_t)N;
+    const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * (size_t)N;
+    TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * (size_t)N;
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -170,7 +195,7 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
     const bool own = gx < nx && gy < ny;
 
     // halo slots handled by this thread: fixed (x, y) for the whole march
-    int sxy[NSLOT];
+    unsigned sxy[NSLOT];
     float sbe[NSLOT][3];
     bool sval[NSLOT];
 #pragma unroll
@@ -179,25 +204,29 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
         sval[s] = i < HN;
         const int hx = i % HX, hy = i / HX;
         const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
-        sxy[s] = hxg + nx * hyg;
+        sxy[s] = (unsigned)(hxg + nx * hyg);
         sbe[s][0] = sval[s] ? a.bext[hxg] : 0.f;
         sbe[s][1] = sval[s] ? a.bext[nx + hxg] : 0.f;
         sbe[s][2] = sval[s] ? a.bext[2 * nx + hxg] : 0.f;
     }
 
-    float ru[NSLOT][3], rb[NSLOT][3];
+    // raw stored values of the next plane: converted only when they are written to LDS, so the
+    // loads stay in flight while the current plane is reduced
+    TU ru[NSLOT][3];
+    TB rb[NSLOT][3];
     auto load_plane = [&](int p) {
-        const int64_t off = (int64_t)wrapi(p, nz) * plane;
+        const unsigned off = (unsigned)wrapi(p, nz) * plane;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             if (sval[s]) {
-                const int64_t k = off + sxy[s];
-                ru[s][0] = St<TU>::ld(u0, k) * a.u_scale;
-                ru[s][1] = St<TU>::ld(u1, k) * a.u_scale;
-                ru[s][2] = St<TU>::ld(u2, k) * a.u_scale;
-                rb[s][0] = St<TB>::ld(b0, k) * a.b_scale;
-                rb[s][1] = St<TB>::ld(b1, k) * a.b_scale;
-                rb[s][2] = St<TB>::ld(b2, k) * a.b_scale;
+                const unsigned ku = (off + sxy[s]) * (unsigned)sizeof(TU);
+                const unsigned kb = (off + sxy[s]) * (unsigned)sizeof(TB);
+                ru[s][0] = ld_off(u0, ku);
+                ru[s][1] = ld_off(u1, ku);
+                ru[s][2] = ld_off(u2, ku);
+                rb[s][0] = ld_off(b0, kb);
+                rb[s][1] = ld_off(b1, kb);
+                rb[s][2] = ld_off(b2, kb);
             }
         }
     };
@@ -210,30 +239,53 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
     float ap0 = 0.f, ap1 = 0.f, ap2 = 0.f;
     float cm0 = 0.f, cm1 = 0.f, cm2 = 0.f;  // b at (x, y, z-1)
     float cc0 = 0.f, cc1 = 0.f, cc2 = 0.f;  // b at (x, y, z)
-    float lm_xz = 0.f, lm_yz = 0.f;         // kappa Lam_xz, Lam_yz at (x, y, z-1)
-    float lc_xz = 0.f, lc_yz = 0.f;         // kappa Lam_xz, Lam_yz at (x, y, z)
 
-    load_plane(z0 - 1);
-    for (int p = z0 - 1; p <= z1; ++p) {
-        __syncthreads();  // the previous plane's LDS reads are done
+    // stage the raw values in the registers into LDS buffer S as (b, kappa Lam)
+    auto stage = [&](auto buf) {
+        constexpr int S = decltype(buf)::value;
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             if (sval[s]) {
                 const int i = tid + s * NT;
-                const float Bx = rb[s][0] + sbe[s][0];
-                const float By = rb[s][1] + sbe[s][1];
-                const float Bz = rb[s][2] + sbe[s][2];
-                const float ux = ru[s][0], uy = ru[s][1], uz = ru[s][2];
-                s_bx[i] = rb[s][0];
-                s_by[i] = rb[s][1];
-                s_bz[i] = rb[s][2];
-                s_lxy[i] = kap * (uy * Bx - ux * By);
-                s_lxz[i] = kap * (uz * Bx - ux * Bz);
-                s_lyz[i] = kap * (uz * By - uy * Bz);
+                const float bx = St<TB>::val(rb[s][0], a.b_scale);
+                const float by = St<TB>::val(rb[s][1], a.b_scale);
+                const float bz = St<TB>::val(rb[s][2], a.b_scale);
+                const float Bx = bx + sbe[s][0];
+                const float By = by + sbe[s][1];
+                const float Bz = bz + sbe[s][2];
+                const float ux = St<TU>::val(ru[s][0], a.u_scale);
+                const float uy = St<TU>::val(ru[s][1], a.u_scale);
+                const float uz = St<TU>::val(ru[s][2], a.u_scale);
+                s_pl[S][0][i] = bx;
+                s_pl[S][1][i] = by;
+                s_pl[S][2][i] = bz;
+                s_pl[S][3][i] = kap * (uy * Bx - ux * By);
+                s_pl[S][4][i] = kap * (uz * Bx - ux * Bz);
+                s_pl[S][5][i] = kap * (uz * By - uy * Bz);
             }
         }
-        __syncthreads();
-        if (p < z1) load_plane(p + 1);  // in flight while this plane is reduced
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+
+    // plane r = p - (z0 - 1) is reduced from LDS buffer r % 2; while it is, the next plane is
+    // staged into the other buffer and the one after that is requested into the registers
+    load_plane(z0 - 1);
+    stage(I0{});
+    load_plane(z0);
+    __syncthreads();
+    auto body = [&](auto par, int p) {
+        constexpr int P = decltype(par)::value;  // parity of plane p
+        using Q = std::integral_constant<int, 1 - P>;
+        // plane p+1 goes from the registers to the other LDS buffer (its last readers passed
+        // the previous barrier); the registers then request plane p+2
+        if (p < z1) {
+            stage(Q{});
+            if (p + 2 <= z1) load_plane(p + 2);
+        }
+        const int cur = P;
+        const float *s_bx = s_pl[cur][0], *s_by = s_pl[cur][1], *s_bz = s_pl[cur][2];
+        const float *s_lxy = s_pl[cur][3], *s_lxz = s_pl[cur][4], *s_lyz = s_pl[cur][5];
         if (own) {
             // b components: centre value and in-plane sums of differences to it
             //   dP0 = sum_faces WF (f - c) + sum_corners WE (f - c),  dP1 = sum_faces WE (f - c)
@@ -262,41 +314,39 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
                 Q0yA = WF * dy + WE * ((mm - mp) + (pm - pp));
                 Q1yA = WE * dy;
             }
-            // kappa Lam_xz: centre, dP1, Q0x, Q1x
-            float lxz, dP1B, Q0xB, Q1xB;
+            // kappa Lam_xz: P1, Q0x, Q1x and kappa Lam_yz: P1, Q0y, Q1y. These flux terms are
+            // of order b / R, so plain weighted sums keep their rounding below that of b.
+            float P1B, Q0xB, Q1xB;
             {
                 const float *f = s_lxz;
-                lxz = f[c0];
-                const float dx = f[c0 - 1] - f[c0 + 1];
+                const float xm = f[c0 - 1], xp = f[c0 + 1];
                 const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
-                dP1B = WE * (((f[c0 - 1] - lxz) + (f[c0 + 1] - lxz)) + ((f[c0 - HX] - lxz) + (f[c0 + HX] - lxz)));
-                Q0xB = WF * dx + WE * ((mm - pm) + (mp - pp));
-                Q1xB = WE * dx;
+                P1B = WF * f[c0] + WE * ((xm + xp) + (f[c0 - HX] + f[c0 + HX]));
+                Q0xB = WF * (xm - xp) + WE * ((mm - pm) + (mp - pp));
+                Q1xB = WE * (xm - xp);
             }
-            // kappa Lam_yz: centre, dP1, Q0y, Q1y
-            float lyz, dP1C, Q0yC, Q1yC;
+            float P1C, Q0yC, Q1yC;
             {
                 const float *f = s_lyz;
-                lyz = f[c0];
-                const float dy = f[c0 - HX] - f[c0 + HX];
+                const float ym = f[c0 - HX], yp = f[c0 + HX];
                 const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
-                dP1C = WE * (((f[c0 - 1] - lyz) + (f[c0 + 1] - lyz)) + ((f[c0 - HX] - lyz) + (f[c0 + HX] - lyz)));
-                Q0yC = WF * dy + WE * ((mm - mp) + (pm - pp));
-                Q1yC = WE * dy;
+                P1C = WF * f[c0] + WE * ((f[c0 - 1] + f[c0 + 1]) + (ym + yp));
+                Q0yC = WF * (ym - yp) + WE * ((mm - mp) + (pm - pp));
+                Q1yC = WE * (ym - yp);
             }
             // contributions of this plane to the outputs at z+1 (A), z (B), z-1 (C)
-            const float A0 = dP1x + Q1yA + dP1B, B0 = dP0x + Q0yA, C0 = dP1x + Q1yA - dP1B;
-            const float A1 = dP1y - Q1xA + dP1C, B1 = dP0y - Q0xA, C1 = dP1y - Q1xA - dP1C;
+            const float A0 = dP1x + Q1yA + P1B, B0 = dP0x + Q0yA, C0 = dP1x + Q1yA - P1B;
+            const float A1 = dP1y - Q1xA + P1C, B1 = dP0y - Q0xA, C1 = dP1y - Q1xA - P1C;
             const float A2 = dP1z - Q1xB - Q1yC, B2 = dP0z - Q0xB - Q0yC;
             if (p >= z0 + 1) {
                 // output plane p-1: b* = b_c + increment, the increment built from differences
-                const float d0 = (acc0 + C0) + W6 * (((cm0 - cc0) + (c_x - cc0)) + (lm_xz - lxz));
-                const float d1 = (acc1 + C1) + W6 * (((cm1 - cc1) + (c_y - cc1)) + (lm_yz - lyz));
+                const float d0 = (acc0 + C0) + W6 * ((cm0 - cc0) + (c_x - cc0));
+                const float d1 = (acc1 + C1) + W6 * ((cm1 - cc1) + (c_y - cc1));
                 const float d2 = (acc2 + A2) + W6 * ((cm2 - cc2) + (c_z - cc2));
-                const int64_t k = (int64_t)(p - 1) * plane + gx + nx * gy;
-                St<TB>::st(o0, k, (cc0 + d0) * a.inv_b_scale);
-                St<TB>::st(o1, k, (cc1 + d1) * a.inv_b_scale);
-                St<TB>::st(o2, k, (cc2 + d2) * a.inv_b_scale);
+                const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(gx + nx * gy)) * (unsigned)sizeof(TB);
+                st_off(o0, k, St<TB>::from(cc0 + d0, a.inv_b_scale));
+                st_off(o1, k, St<TB>::from(cc1 + d1, a.inv_b_scale));
+                st_off(o2, k, St<TB>::from(cc2 + d2, a.inv_b_scale));
             }
             acc0 = ap0 + B0;
             acc1 = ap1 + B1;
@@ -310,11 +360,12 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
             cc0 = c_x;
             cc1 = c_y;
             cc2 = c_z;
-            lm_xz = lc_xz;
-            lm_yz = lc_yz;
-            lc_xz = lxz;
-            lc_yz = lyz;
         }
+        __syncthreads();  // plane p+1 is staged; buffer `cur` may be overwritten next
+    };
+    for (int p = z0 - 1; p <= z1; p += 2) {
+        body(I0{}, p);
+        if (p + 1 <= z1) body(I1{}, p + 1);
     }
 #undef MHD_PLANE_DIFFS
 }

@@ -403,3 +403,21 @@ def test_plane_hartmann_closed_form_solves_its_ode():
     ua, ba = gold.plane_hartmann(np.array([-a, a]), a, nu, eta, B0, G)
     np.testing.assert_allclose(ua, 0.0, atol=1e-12)
     np.testing.assert_allclose(ba, 0.0, atol=1e-12)
+
+
+def test_flow_rate_control_reaches_its_target():
+    # Integral control of G on the bulk velocity over the flow region: at steady state the
+    # plane channel carries the parabola whose node average equals the target, so
+    # G = 2 nu U_t (2a + 1) / sum_{|y| <= a} (a^2 - y^2).
+    oracle.set_threads(1)
+    ny, yc, a, nu, Ut = 24, 12, 8, 0.1, 0.01
+    p, X = _plane_channel(ny, yc, a, nu=nu, eta=1.0, n_mag=1, G0=0.0, flow_control=1,
+                          u_target=Ut, k_c=1.0)
+    o = oracle.Oracle(p, X)
+    o.step(20000)
+    y = np.arange(-a, a + 1)
+    G_ss = 2 * nu * Ut * (2 * a + 1) / np.sum(a * a - y * y)
+    assert abs(o.G.value - G_ss) <= 1e-6 * G_ss, (o.G.value, G_ss)
+    ub = o.u[0, 0, yc - a:yc + a + 1, 0].mean()
+    assert abs(ub - Ut) <= 1e-6 * Ut
+    oracle.set_threads(8)

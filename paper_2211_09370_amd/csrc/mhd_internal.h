@@ -42,6 +42,7 @@ constexpr int kRingCap = 4096;     // budget records held on the device
 // Launch wrappers implemented in mhd_kernels.hip. Every pointer is a device pointer.
 struct SweepLaunch {
     int tx, ty, zchunk;  // tile shape and z extent of one workgroup
+    int pair;            // 1: two x cells per lane (n_x a multiple of 128); ty = rows per tile
 };
 
 hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c);

@@ -371,6 +371,278 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
 }
 
 // -------------------------------------------------------------------------------------------
+// Paired magnetic sweep for boxes with n_x a multiple of 128: the same plane march and the same
+// per-cell arithmetic as k_mag_sweep, but every lane owns two neighbouring x cells, so a wave
+// covers a 128-cell row. Rows are loaded and stored as 8-byte (float32) or 4-byte (16-bit)
+// pairs — half the memory instructions per cell — and a lane reads the four values x-1 .. x+2
+// of a row from LDS with one 8-byte and two 4-byte reads serving both of its cells.
+// -------------------------------------------------------------------------------------------
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using raw = float2;
+    static __device__ __forceinline__ float lo(raw v, float) { return v.x; }
+    static __device__ __forceinline__ float hi(raw v, float) { return v.y; }
+    static __device__ __forceinline__ raw make(float a, float b, float) { return make_float2(a, b); }
+};
+template <>
+struct Pair<__half> {
+    using raw = __half2;
+    static __device__ __forceinline__ float lo(raw v, float s) { return __low2float(v) * s; }
+    static __device__ __forceinline__ float hi(raw v, float s) { return __high2float(v) * s; }
+    static __device__ __forceinline__ raw make(float a, float b, float inv) {
+        return __halves2half2(__float2half_rn(a * inv), __float2half_rn(b * inv));
+    }
+};
+template <>
+struct Pair<__hip_bfloat16> {
+    using raw = unsigned;  // low half = element x, high half = element x + 1
+    static __device__ __forceinline__ float lo(raw v, float s) { return __uint_as_float(v << 16) * s; }
+    static __device__ __forceinline__ float hi(raw v, float s) { return __uint_as_float(v & 0xffff0000u) * s; }
+    static __device__ __forceinline__ raw make(float a, float b, float inv) {
+        const __hip_bfloat16 x = __float2bfloat16(a * inv), y = __float2bfloat16(b * inv);
+        return (unsigned)__bfloat16_as_ushort(x) | ((unsigned)__bfloat16_as_ushort(y) << 16);
+    }
+};
+
+// The per-plane terms of one cell from the 3x3 in-plane neighbourhoods of the six staged
+// fields: f[k][r][j] = field k, row y-1+r, column x-1+j.
+struct PlaneTerms {
+    float c0, c1, c2;          // b at the cell
+    float A0, A1, A2;          // contribution to the output one plane up
+    float B0, B1, B2;          // contribution to the output in this plane
+    float C0, C1;              // contribution one plane down (C2 = A2)
+};
+
+__device__ __forceinline__ void diffs3(const float (&f)[3][3], float &c, float &dP0, float &dP1) {
+    c = f[1][1];
+    const float fs = ((f[1][0] - c) + (f[1][2] - c)) + ((f[0][1] - c) + (f[2][1] - c));
+    const float cs = ((f[0][0] - c) + (f[0][2] - c)) + ((f[2][0] - c) + (f[2][2] - c));
+    dP0 = WF * fs + WE * cs;
+    dP1 = WE * fs;
+}
+
+__device__ __forceinline__ PlaneTerms plane_terms(const float (&bx)[3][3], const float (&by)[3][3],
+                                                  const float (&bz)[3][3], const float (&lxy)[3][3],
+                                                  const float (&lxz)[3][3], const float (&lyz)[3][3]) {
+    PlaneTerms t;
+    float dP0x, dP1x, dP0y, dP1y, dP0z, dP1z;
+    diffs3(bx, t.c0, dP0x, dP1x);
+    diffs3(by, t.c1, dP0y, dP1y);
+    diffs3(bz, t.c2, dP0z, dP1z);
+    // f[r][j]: r = y index (0: y-1), j = x index (0: x-1); mm = (x-1, y-1), pm = (x+1, y-1), ...
+    const float dxA = lxy[1][0] - lxy[1][2], dyA = lxy[0][1] - lxy[2][1];
+    const float Q0xA = WF * dxA + WE * ((lxy[0][0] - lxy[0][2]) + (lxy[2][0] - lxy[2][2]));
+    const float Q1xA = WE * dxA;
+    const float Q0yA = WF * dyA + WE * ((lxy[0][0] - lxy[2][0]) + (lxy[0][2] - lxy[2][2]));
+    const float Q1yA = WE * dyA;
+    const float dxB = lxz[1][0] - lxz[1][2];
+    const float P1B = WF * lxz[1][1] + WE * ((lxz[1][0] + lxz[1][2]) + (lxz[0][1] + lxz[2][1]));
+    const float Q0xB = WF * dxB + WE * ((lxz[0][0] - lxz[0][2]) + (lxz[2][0] - lxz[2][2]));
+    const float Q1xB = WE * dxB;
+    const float dyC = lyz[0][1] - lyz[2][1];
+    const float P1C = WF * lyz[1][1] + WE * ((lyz[1][0] + lyz[1][2]) + (lyz[0][1] + lyz[2][1]));
+    const float Q0yC = WF * dyC + WE * ((lyz[0][0] - lyz[2][0]) + (lyz[0][2] - lyz[2][2]));
+    const float Q1yC = WE * dyC;
+    t.A0 = dP1x + Q1yA + P1B;
+    t.B0 = dP0x + Q0yA;
+    t.C0 = dP1x + Q1yA - P1B;
+    t.A1 = dP1y - Q1xA + P1C;
+    t.B1 = dP0y - Q0xA;
+    t.C1 = dP1y - Q1xA - P1C;
+    t.A2 = dP1z - Q1xB - Q1yC;
+    t.B2 = dP0z - Q0xB - Q0yC;
+    return t;
+}
+
+template <int TY, typename TU, typename TB>
+__global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a) {
+    constexpr int NT = 64 * TY;
+    constexpr int HY = TY + 2;        // staged rows
+    constexpr int RS = 132;           // LDS row stride: x0-1 at 1, x0 .. x0+127 at 2 .. 129, x0+128 at 130
+    constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
+    __shared__ __align__(16) float s_pl[2][6][HY * RS];
+
+    const int per = gridDim.x >> 3;
+    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (lb >= a.nblocks) return;
+    const int tix = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int tiy = rest % a.tiles_y;
+    const int tiz = rest / a.tiles_y;
+    const int x0 = tix * 128, y0 = tiy * TY;
+    const int z0 = tiz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned N = (unsigned)nx * ny * nz;
+    const unsigned plane = (unsigned)nx * ny;
+    const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * (size_t)N;
+    const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * (size_t)N;
+    TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * (size_t)N;
+    using PU = Pair<TU>;
+    using PB = Pair<TB>;
+    using RU = typename PU::raw;
+    using RB = typename PB::raw;
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int xa = x0 + 2 * l;            // this lane's cells: xa, xa + 1 (always inside: nx % 128 == 0)
+    const int gy = y0 + w;
+    const bool own = gy < ny;
+    const float kap = a.kappa;
+    // B_ext of this lane's pair of columns and of the two halo columns
+    const float bea[3] = {a.bext[xa], a.bext[nx + xa], a.bext[2 * nx + xa]};
+    const float beb[3] = {a.bext[xa + 1], a.bext[nx + xa + 1], a.bext[2 * nx + xa + 1]};
+
+    // row loads: round r stages row hy = w + r * TY (if < HY) at columns xa, xa + 1
+    unsigned rowoff[NR];
+    bool rowval[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int hy = w + r * TY;
+        rowval[r] = hy < HY;
+        rowoff[r] = (unsigned)(xa + nx * wrapi(y0 - 1 + hy, ny));
+    }
+    // halo columns: lanes 0 .. 2*HY-1 of the last wave, lane -> (row hy = lane / 2, side)
+    const bool hval = (w == TY - 1) && (l < 2 * HY);
+    const int hhy = l >> 1, hside = l & 1;
+    const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
+    const unsigned hoff = (unsigned)(hx + nx * wrapi(y0 - 1 + min(hhy, HY - 1), ny));
+    const int hidx = min(hhy, HY - 1) * RS + (hside ? 130 : 1);
+    const float hbe[3] = {a.bext[hx], a.bext[nx + hx], a.bext[2 * nx + hx]};
+
+    RU ru[NR][3];
+    RB rb[NR][3];
+    TU hu[3];
+    TB hb[3];
+    auto load_plane = [&](int p) {
+        const unsigned off = (unsigned)wrapi(p, nz) * plane;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (rowval[r]) {
+                const unsigned ku = (off + rowoff[r]) * (unsigned)sizeof(TU);
+                const unsigned kb = (off + rowoff[r]) * (unsigned)sizeof(TB);
+                ru[r][0] = ld_off(reinterpret_cast<const RU *>(u0), ku);
+                ru[r][1] = ld_off(reinterpret_cast<const RU *>(u1), ku);
+                ru[r][2] = ld_off(reinterpret_cast<const RU *>(u2), ku);
+                rb[r][0] = ld_off(reinterpret_cast<const RB *>(b0), kb);
+                rb[r][1] = ld_off(reinterpret_cast<const RB *>(b1), kb);
+                rb[r][2] = ld_off(reinterpret_cast<const RB *>(b2), kb);
+            }
+        }
+        if (hval) {
+            const unsigned ku = (off + hoff) * (unsigned)sizeof(TU), kb = (off + hoff) * (unsigned)sizeof(TB);
+            hu[0] = ld_off(u0, ku);
+            hu[1] = ld_off(u1, ku);
+            hu[2] = ld_off(u2, ku);
+            hb[0] = ld_off(b0, kb);
+            hb[1] = ld_off(b1, kb);
+            hb[2] = ld_off(b2, kb);
+        }
+    };
+    auto put = [&](int buf, int idx, float bx, float by, float bz, float ux, float uy, float uz, const float *be) {
+        const float Bx = bx + be[0], By = by + be[1], Bz = bz + be[2];
+        s_pl[buf][0][idx] = bx;
+        s_pl[buf][1][idx] = by;
+        s_pl[buf][2][idx] = bz;
+        s_pl[buf][3][idx] = kap * (uy * Bx - ux * By);
+        s_pl[buf][4][idx] = kap * (uz * Bx - ux * Bz);
+        s_pl[buf][5][idx] = kap * (uz * By - uy * Bz);
+    };
+    auto stage = [&](auto bufc) {
+        constexpr int S = decltype(bufc)::value;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (rowval[r]) {
+                const int idx = (w + r * TY) * RS + 2 + 2 * l;
+                const float us = a.u_scale, bs = a.b_scale;
+                put(S, idx, PB::lo(rb[r][0], bs), PB::lo(rb[r][1], bs), PB::lo(rb[r][2], bs), PU::lo(ru[r][0], us),
+                    PU::lo(ru[r][1], us), PU::lo(ru[r][2], us), bea);
+                put(S, idx + 1, PB::hi(rb[r][0], bs), PB::hi(rb[r][1], bs), PB::hi(rb[r][2], bs), PU::hi(ru[r][0], us),
+                    PU::hi(ru[r][1], us), PU::hi(ru[r][2], us), beb);
+            }
+        }
+        if (hval)
+            put(S, hidx, St<TB>::val(hb[0], a.b_scale), St<TB>::val(hb[1], a.b_scale), St<TB>::val(hb[2], a.b_scale),
+                St<TU>::val(hu[0], a.u_scale), St<TU>::val(hu[1], a.u_scale), St<TU>::val(hu[2], a.u_scale), hbe);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+
+    constexpr float W6 = 1.0f / 6.0f;
+    float acc[2][3] = {}, ap[2][3] = {}, cm[2][3] = {}, cc[2][3] = {};
+
+    load_plane(z0 - 1);
+    stage(I0{});
+    load_plane(z0);
+    __syncthreads();
+    auto body = [&](auto par, int p) {
+        constexpr int P = decltype(par)::value;
+        using Q = std::integral_constant<int, 1 - P>;
+        if (p < z1) {
+            stage(Q{});
+            if (p + 2 <= z1) load_plane(p + 2);
+        }
+        if (own) {
+            // rows y-1, y, y+1 of the six fields at columns xa-1 .. xa+2
+            float v[6][3][4];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float *row = &s_pl[P][k][(w + r) * RS + 1 + 2 * l];
+                    v[k][r][0] = row[0];
+                    const float2 mid = *reinterpret_cast<const float2 *>(row + 1);
+                    v[k][r][1] = mid.x;
+                    v[k][r][2] = mid.y;
+                    v[k][r][3] = row[3];
+                }
+            }
+            float out[2][3];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                float f[6][3][3];
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) f[k][r][j] = v[k][r][e + j];
+                const PlaneTerms t = plane_terms(f[0], f[1], f[2], f[3], f[4], f[5]);
+                // output plane p-1: b* = b_c + increment (differences only)
+                out[e][0] = cc[e][0] + ((acc[e][0] + t.C0) + W6 * ((cm[e][0] - cc[e][0]) + (t.c0 - cc[e][0])));
+                out[e][1] = cc[e][1] + ((acc[e][1] + t.C1) + W6 * ((cm[e][1] - cc[e][1]) + (t.c1 - cc[e][1])));
+                out[e][2] = cc[e][2] + ((acc[e][2] + t.A2) + W6 * ((cm[e][2] - cc[e][2]) + (t.c2 - cc[e][2])));
+                acc[e][0] = ap[e][0] + t.B0;
+                acc[e][1] = ap[e][1] + t.B1;
+                acc[e][2] = ap[e][2] + t.B2;
+                ap[e][0] = t.A0;
+                ap[e][1] = t.A1;
+                ap[e][2] = t.A2;
+                cm[e][0] = cc[e][0];
+                cm[e][1] = cc[e][1];
+                cm[e][2] = cc[e][2];
+                cc[e][0] = t.c0;
+                cc[e][1] = t.c1;
+                cc[e][2] = t.c2;
+            }
+            if (p >= z0 + 1) {
+                const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);
+                st_off(reinterpret_cast<RB *>(o0), k, PB::make(out[0][0], out[1][0], a.inv_b_scale));
+                st_off(reinterpret_cast<RB *>(o1), k, PB::make(out[0][1], out[1][1], a.inv_b_scale));
+                st_off(reinterpret_cast<RB *>(o2), k, PB::make(out[0][2], out[1][2], a.inv_b_scale));
+            }
+        }
+        __syncthreads();
+    };
+    for (int p = z0 - 1; p <= z1; p += 2) {
+        body(I0{}, p);
+        if (p + 1 <= z1) body(I1{}, p + 1);
+    }
+}
+
+// -------------------------------------------------------------------------------------------
 // Immersed boundary (Sec. 5.2 - 5.6), explicit diagonal form:
 //   delta_j = s_j (phi_wall_j - sum_k D_jk phi*_k),  phi_k = phi*_k + sum_j D_jk delta_j,
 // s_j = lambda / (d_j (1 + d_j (lambda - 1))).
@@ -817,9 +1089,38 @@ static hipError_t sweep_tile(hipStream_t s, const void *u, const void *b, void *
     return hipGetLastError();
 }
 
+template <int TY, typename TU, typename TB>
+static hipError_t sweep_pair_tile(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
+                                  int zchunk) {
+    SweepArgs a;
+    a.u = u;
+    a.b = b;
+    a.bo = bo;
+    a.bext = bext;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.tiles_x = c.nx / 128;
+    a.tiles_y = (c.ny + TY - 1) / TY;
+    a.zchunk = zchunk;
+    a.nzc = (c.nz + zchunk - 1) / zchunk;
+    a.nblocks = a.tiles_x * a.tiles_y * a.nzc;
+    a.kappa = c.kappa;
+    a.u_scale = c.u_scale;
+    a.b_scale = c.b_scale;
+    a.inv_b_scale = c.inv_b_scale;
+    const unsigned grid = (unsigned)(((a.nblocks + 7) / 8) * 8);
+    hipLaunchKernelGGL((k_mag_sweep_pair<TY, TU, TB>), dim3(grid), dim3(64 * TY), 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename TU, typename TB>
 static hipError_t sweep_typed(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
                               SweepLaunch L) {
+    if (L.pair && c.nx % 128 == 0) {
+        if (L.ty >= 8) return sweep_pair_tile<8, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+        return sweep_pair_tile<4, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+    }
     switch (L.tx) {
         case 64: return sweep_tile<64, 4, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
         case 32: return sweep_tile<32, 8, TU, TB>(s, u, b, bo, bext, c, L.zchunk);

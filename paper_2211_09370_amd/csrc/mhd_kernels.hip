@@ -408,59 +408,11 @@ struct Pair<__hip_bfloat16> {
 
 // The per-plane terms of one cell from the 3x3 in-plane neighbourhoods of the six staged
 // fields: f[k][r][j] = field k, row y-1+r, column x-1+j.
-struct PlaneTerms {
-    float c0, c1, c2;          // b at the cell
-    float A0, A1, A2;          // contribution to the output one plane up
-    float B0, B1, B2;          // contribution to the output in this plane
-    float C0, C1;              // contribution one plane down (C2 = A2)
-};
-
-__device__ __forceinline__ void diffs3(const float (&f)[3][3], float &c, float &dP0, float &dP1) {
-    c = f[1][1];
-    const float fs = ((f[1][0] - c) + (f[1][2] - c)) + ((f[0][1] - c) + (f[2][1] - c));
-    const float cs = ((f[0][0] - c) + (f[0][2] - c)) + ((f[2][0] - c) + (f[2][2] - c));
-    dP0 = WF * fs + WE * cs;
-    dP1 = WE * fs;
-}
-
-__device__ __forceinline__ PlaneTerms plane_terms(const float (&bx)[3][3], const float (&by)[3][3],
-                                                  const float (&bz)[3][3], const float (&lxy)[3][3],
-                                                  const float (&lxz)[3][3], const float (&lyz)[3][3]) {
-    PlaneTerms t;
-    float dP0x, dP1x, dP0y, dP1y, dP0z, dP1z;
-    diffs3(bx, t.c0, dP0x, dP1x);
-    diffs3(by, t.c1, dP0y, dP1y);
-    diffs3(bz, t.c2, dP0z, dP1z);
-    // f[r][j]: r = y index (0: y-1), j = x index (0: x-1); mm = (x-1, y-1), pm = (x+1, y-1), ...
-    const float dxA = lxy[1][0] - lxy[1][2], dyA = lxy[0][1] - lxy[2][1];
-    const float Q0xA = WF * dxA + WE * ((lxy[0][0] - lxy[0][2]) + (lxy[2][0] - lxy[2][2]));
-    const float Q1xA = WE * dxA;
-    const float Q0yA = WF * dyA + WE * ((lxy[0][0] - lxy[2][0]) + (lxy[0][2] - lxy[2][2]));
-    const float Q1yA = WE * dyA;
-    const float dxB = lxz[1][0] - lxz[1][2];
-    const float P1B = WF * lxz[1][1] + WE * ((lxz[1][0] + lxz[1][2]) + (lxz[0][1] + lxz[2][1]));
-    const float Q0xB = WF * dxB + WE * ((lxz[0][0] - lxz[0][2]) + (lxz[2][0] - lxz[2][2]));
-    const float Q1xB = WE * dxB;
-    const float dyC = lyz[0][1] - lyz[2][1];
-    const float P1C = WF * lyz[1][1] + WE * ((lyz[1][0] + lyz[1][2]) + (lyz[0][1] + lyz[2][1]));
-    const float Q0yC = WF * dyC + WE * ((lyz[0][0] - lyz[2][0]) + (lyz[0][2] - lyz[2][2]));
-    const float Q1yC = WE * dyC;
-    t.A0 = dP1x + Q1yA + P1B;
-    t.B0 = dP0x + Q0yA;
-    t.C0 = dP1x + Q1yA - P1B;
-    t.A1 = dP1y - Q1xA + P1C;
-    t.B1 = dP0y - Q0xA;
-    t.C1 = dP1y - Q1xA - P1C;
-    t.A2 = dP1z - Q1xB - Q1yC;
-    t.B2 = dP0z - Q0xB - Q0yC;
-    return t;
-}
-
 template <int TY, typename TU, typename TB>
 __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a) {
     constexpr int NT = 64 * TY;
     constexpr int HY = TY + 2;        // staged rows
-    constexpr int RS = 132;           // LDS row stride: x0-1 at 1, x0 .. x0+127 at 2 .. 129, x0+128 at 130
+    constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
     constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
     __shared__ __align__(16) float s_pl[2][6][HY * RS];
 
@@ -509,7 +461,7 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a) {
     const int hhy = l >> 1, hside = l & 1;
     const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
     const unsigned hoff = (unsigned)(hx + nx * wrapi(y0 - 1 + min(hhy, HY - 1), ny));
-    const int hidx = min(hhy, HY - 1) * RS + (hside ? 130 : 1);
+    const int hidx = min(hhy, HY - 1) * RS + (hside ? 129 : 0);
     const float hbe[3] = {a.bext[hx], a.bext[nx + hx], a.bext[2 * nx + hx]};
 
     RU ru[NR][3];
@@ -555,7 +507,7 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (rowval[r]) {
-                const int idx = (w + r * TY) * RS + 2 + 2 * l;
+                const int idx = (w + r * TY) * RS + 1 + 2 * l;
                 const float us = a.u_scale, bs = a.b_scale;
                 put(S, idx, PB::lo(rb[r][0], bs), PB::lo(rb[r][1], bs), PB::lo(rb[r][2], bs), PU::lo(ru[r][0], us),
                     PU::lo(ru[r][1], us), PU::lo(ru[r][2], us), bea);
@@ -585,47 +537,101 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a) {
             if (p + 2 <= z1) load_plane(p + 2);
         }
         if (own) {
-            // rows y-1, y, y+1 of the six fields at columns xa-1 .. xa+2
-            float v[6][3][4];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
+            // per field: rows y-1, y, y+1 at columns xa-1 .. xa+2 (two aligned 8-byte reads per
+            // row), reduced at once into the plane terms of both cells
+            float A[2][3], B[2][3], C[2][2], cen[2][3];
+            auto rows = [&](int k, float (&v)[3][4]) {
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
-                    const float *row = &s_pl[P][k][(w + r) * RS + 1 + 2 * l];
-                    v[k][r][0] = row[0];
-                    const float2 mid = *reinterpret_cast<const float2 *>(row + 1);
-                    v[k][r][1] = mid.x;
-                    v[k][r][2] = mid.y;
-                    v[k][r][3] = row[3];
+                    const float *row = &s_pl[P][k][(w + r) * RS + 2 * l];
+                    const float2 lo = *reinterpret_cast<const float2 *>(row);
+                    const float2 hi = *reinterpret_cast<const float2 *>(row + 2);
+                    v[r][0] = lo.x;
+                    v[r][1] = lo.y;
+                    v[r][2] = hi.x;
+                    v[r][3] = hi.y;
+                }
+            };
+            {  // b components
+                float v[3][4];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    rows(k, v);
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float c = v[1][1 + e];
+                        const float fs = ((v[1][e] - c) + (v[1][e + 2] - c)) + ((v[0][1 + e] - c) + (v[2][1 + e] - c));
+                        const float cs = ((v[0][e] - c) + (v[0][e + 2] - c)) + ((v[2][e] - c) + (v[2][e + 2] - c));
+                        const float dP0 = WF * fs + WE * cs, dP1 = WE * fs;
+                        cen[e][k] = c;
+                        A[e][k] = dP1;
+                        B[e][k] = dP0;
+                        if (k < 2) C[e][k] = dP1;
+                    }
+                }
+            }
+            {  // kappa Lam_xy: Q0x, Q1x, Q0y, Q1y
+                float v[3][4];
+                rows(3, v);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float dx = v[1][e] - v[1][e + 2], dy = v[0][1 + e] - v[2][1 + e];
+                    const float Q0x = WF * dx + WE * ((v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]));
+                    const float Q1x = WE * dx;
+                    const float Q0y = WF * dy + WE * ((v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]));
+                    const float Q1y = WE * dy;
+                    A[e][0] += Q1y;
+                    B[e][0] += Q0y;
+                    C[e][0] += Q1y;
+                    A[e][1] -= Q1x;
+                    B[e][1] -= Q0x;
+                    C[e][1] -= Q1x;
+                }
+            }
+            {  // kappa Lam_xz: P1, Q0x, Q1x
+                float v[3][4];
+                rows(4, v);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float dx = v[1][e] - v[1][e + 2];
+                    const float P1 = WF * v[1][1 + e] + WE * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
+                    const float Q0x = WF * dx + WE * ((v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]));
+                    const float Q1x = WE * dx;
+                    A[e][0] += P1;
+                    C[e][0] -= P1;
+                    A[e][2] -= Q1x;
+                    B[e][2] -= Q0x;
+                }
+            }
+            {  // kappa Lam_yz: P1, Q0y, Q1y
+                float v[3][4];
+                rows(5, v);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float dy = v[0][1 + e] - v[2][1 + e];
+                    const float P1 = WF * v[1][1 + e] + WE * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
+                    const float Q0y = WF * dy + WE * ((v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]));
+                    const float Q1y = WE * dy;
+                    A[e][1] += P1;
+                    C[e][1] -= P1;
+                    A[e][2] -= Q1y;
+                    B[e][2] -= Q0y;
                 }
             }
             float out[2][3];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                float f[6][3][3];
+                // output plane p-1: b* = b_c + increment (differences only); C2 = A2
+                out[e][0] = cc[e][0] + ((acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0])));
+                out[e][1] = cc[e][1] + ((acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1])));
+                out[e][2] = cc[e][2] + ((acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2])));
 #pragma unroll
-                for (int k = 0; k < 6; ++k)
-#pragma unroll
-                    for (int r = 0; r < 3; ++r)
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) f[k][r][j] = v[k][r][e + j];
-                const PlaneTerms t = plane_terms(f[0], f[1], f[2], f[3], f[4], f[5]);
-                // output plane p-1: b* = b_c + increment (differences only)
-                out[e][0] = cc[e][0] + ((acc[e][0] + t.C0) + W6 * ((cm[e][0] - cc[e][0]) + (t.c0 - cc[e][0])));
-                out[e][1] = cc[e][1] + ((acc[e][1] + t.C1) + W6 * ((cm[e][1] - cc[e][1]) + (t.c1 - cc[e][1])));
-                out[e][2] = cc[e][2] + ((acc[e][2] + t.A2) + W6 * ((cm[e][2] - cc[e][2]) + (t.c2 - cc[e][2])));
-                acc[e][0] = ap[e][0] + t.B0;
-                acc[e][1] = ap[e][1] + t.B1;
-                acc[e][2] = ap[e][2] + t.B2;
-                ap[e][0] = t.A0;
-                ap[e][1] = t.A1;
-                ap[e][2] = t.A2;
-                cm[e][0] = cc[e][0];
-                cm[e][1] = cc[e][1];
-                cm[e][2] = cc[e][2];
-                cc[e][0] = t.c0;
-                cc[e][1] = t.c1;
-                cc[e][2] = t.c2;
+                for (int q = 0; q < 3; ++q) {
+                    acc[e][q] = ap[e][q] + B[e][q];
+                    ap[e][q] = A[e][q];
+                    cm[e][q] = cc[e][q];
+                    cc[e][q] = cen[e][q];
+                }
             }
             if (p >= z0 + 1) {
                 const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);

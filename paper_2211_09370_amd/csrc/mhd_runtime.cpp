@@ -423,7 +423,8 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
     s->sweep.tx = env_int("MHD_SWEEP_TX", s->sweep.tx);
     s->sweep.ty = 256 / s->sweep.tx;
     s->sweep.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", 8));
-    s->sweep.pair = (nx % 128 == 0) && env_int("MHD_SWEEP_PAIR", 0) != 0;
+    // two x cells per lane whenever a row splits into 128-cell tiles (fewer LDS reads per cell)
+    s->sweep.pair = (nx % 128 == 0) && env_int("MHD_SWEEP_PAIR", 1) != 0;
     if (s->sweep.pair) s->sweep.ty = env_int("MHD_SWEEP_PAIR_TY", 4) >= 8 ? 8 : 4;
     // initial state: rho = 1, u = 0, b = 0, t = 0, G = 0
     DevCtrl hc{};

@@ -163,8 +163,69 @@ typedef enum {
 mhd_status mhd_set_profiling(mhd_sim *s, int32_t enable);
 mhd_status mhd_kernel_stats(mhd_sim *s, int32_t kernel, int64_t *launches, double *total_ms);
 
-/* Free library host state (events included). Device workspace stays the caller's. */
+/* Free library host state (events included). Device workspace stays the caller's.
+ * STATE for a box of a batch (mhd_batch_destroy frees those). */
 mhd_status mhd_destroy(mhd_sim *s);
+
+/* Tile choice of the magnetic sweep (performance only): tiles[0] = x tile (8, 16, 32 or 64
+ * cells, 256 work-items per workgroup), tiles[1] = z planes marched per workgroup (>= 1),
+ * tiles[2] = 1 for two x cells per lane with 128-cell x tiles (used only when nx is a multiple
+ * of 128), tiles[3] = rows per workgroup of that form (4 or 8). Results do not depend on the
+ * choice beyond float32 rounding of contracted multiply-adds. */
+mhd_status mhd_get_tiles(mhd_sim *s, int32_t tiles[4]);
+mhd_status mhd_set_tiles(mhd_sim *s, const int32_t tiles[4]);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched form: many independent pipes (boxes), each with its own size, markers, parameters and
+ * number of magnetic sweeps, advanced together. One fluid step of the whole batch is a fixed
+ * sequence of launches, each covering every box that takes part in it: sweep round r runs on
+ * the boxes with n_mag > r, followed by their b wall correction; then Lorentz, fluid and u wall
+ * correction run on all boxes. With graphs enabled (default) that sequence is captured once in
+ * a HIP graph per state of the boxes' double buffers and replayed, one graph launch per step.
+ * Every box evolves bitwise as a single box with the same tile choice would.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct mhd_batch mhd_batch;
+
+typedef struct {
+    mhd_grid_desc grid;   /* box of this pipe; all pipes of a batch share the storage kinds   */
+    int64_t n_markers;    /* marker capacity of this pipe                                      */
+} mhd_pipe_desc;
+
+/* Bytes of device workspace for the batch (host-only). */
+mhd_status mhd_batch_workspace_size(const mhd_pipe_desc *pipes, int32_t n, size_t *bytes);
+
+/* Create a batch of n >= 1 pipes on the current device; workspace and stream rules as for
+ * mhd_create. A stream of NULL disables graphs (the NULL stream cannot be captured). */
+mhd_status mhd_batch_create(const mhd_pipe_desc *pipes, int32_t n, void *dev_workspace, size_t bytes,
+                            void *hip_stream, mhd_batch **out);
+
+/* Handle of pipe i, owned by the batch. mhd_set_markers, mhd_set_params, mhd_set_field,
+ * mhd_get_field, mhd_get_time, mhd_set_time, mhd_record_budget, mhd_get_budgets and the tile
+ * calls work on it as on a single box; mhd_step and mhd_destroy return STATE. */
+mhd_status mhd_batch_pipe(mhd_batch *b, int32_t i, mhd_sim **out);
+
+/* Autotuner of the sweep tiles (mhd_get_tiles). Pipes are grouped by nx; for each group in
+ * turn, every valid tile choice is tried with the other groups fixed by timing reps (default 5
+ * if reps <= 0) batched sweep rounds over the whole batch on the live fields, and the fastest
+ * is kept; two passes, starting from the current choice. The timed sweeps write only the
+ * scratch copy of b, so the state is unchanged. Synchronous. */
+mhd_status mhd_batch_tune(mhd_batch *b, int32_t reps);
+
+/* Advance every pipe by n_steps fluid steps (asynchronous, like mhd_step). If budget_every > 0,
+ * each pipe records a budget after every step whose new step count is a multiple of it. STATE
+ * if a pipe has no parameters. */
+mhd_status mhd_batch_step(mhd_batch *b, int64_t n_steps, int32_t budget_every);
+
+/* 1 (default): replay captured graphs; 0: issue the launches directly. */
+mhd_status mhd_batch_set_graph(mhd_batch *b, int32_t enable);
+
+/* Kernel timing as mhd_set_profiling / mhd_kernel_stats, per batched launch (graphs are
+ * bypassed while profiling is on). */
+mhd_status mhd_batch_set_profiling(mhd_batch *b, int32_t enable);
+mhd_status mhd_batch_kernel_stats(mhd_batch *b, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Free the batch, its pipes and its graphs. Device workspace stays the caller's. */
+mhd_status mhd_batch_destroy(mhd_batch *b);
 
 #ifdef __cplusplus
 }

@@ -17,12 +17,15 @@ from ._abi import (MHD_BEXT_NONE, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_UNIFORM_Y, MH
                    MHD_FIELD_RHO, MHD_FIELD_U, MHD_K_BUDGET, MHD_K_CONTROL, MHD_K_FLUID,
                    MHD_K_IB, MHD_K_LORENTZ, MHD_K_MAG_SWEEP,
                    MHD_STORE_BF16, MHD_STORE_F16, MHD_STORE_F32, MhdError, mhd_budget,
-                   mhd_grid_desc, mhd_params)
+                   mhd_grid_desc, mhd_params, mhd_pipe_desc)
 
-__all__ = ["Sim", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
+__all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
-           "mhd_kernel_stats", "mhd_destroy", "mhd_last_error", "BUDGET_FIELDS"]
+           "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles",
+           "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
+           "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
+           "mhd_batch_kernel_stats", "mhd_batch_destroy", "mhd_last_error", "BUDGET_FIELDS"]
 
 BUDGET_FIELDS = [f for f, _ in mhd_budget._fields_]
 _STORAGE = {"f32": MHD_STORE_F32, "f16": MHD_STORE_F16, "bf16": MHD_STORE_BF16}
@@ -130,6 +133,75 @@ def mhd_destroy(h):
     _abi.check(_abi.lib().mhd_destroy(h), "mhd_destroy")
 
 
+def mhd_get_tiles(h):
+    t = (C.c_int32 * 4)()
+    _abi.check(_abi.lib().mhd_get_tiles(h, t), "mhd_get_tiles")
+    return tuple(int(v) for v in t)
+
+
+def mhd_set_tiles(h, tiles):
+    t = (C.c_int32 * 4)(*[int(v) for v in tiles])
+    _abi.check(_abi.lib().mhd_set_tiles(h, t), "mhd_set_tiles")
+
+
+def _pipe_array(pipes):
+    arr = (mhd_pipe_desc * len(pipes))()
+    for i, p in enumerate(pipes):
+        arr[i] = p
+    return arr
+
+
+def mhd_batch_workspace_size(pipes) -> int:
+    n = C.c_size_t(0)
+    arr = _pipe_array(pipes)
+    _abi.check(_abi.lib().mhd_batch_workspace_size(arr, len(pipes), C.byref(n)),
+               "mhd_batch_workspace_size")
+    return int(n.value)
+
+
+def mhd_batch_create(pipes, dev_ptr: int, nbytes: int, stream: int):
+    h = C.c_void_p()
+    arr = _pipe_array(pipes)
+    _abi.check(_abi.lib().mhd_batch_create(arr, len(pipes), C.c_void_p(dev_ptr), int(nbytes),
+                                           C.c_void_p(stream), C.byref(h)), "mhd_batch_create")
+    return h
+
+
+def mhd_batch_pipe(h, i: int):
+    out = C.c_void_p()
+    _abi.check(_abi.lib().mhd_batch_pipe(h, int(i), C.byref(out)), "mhd_batch_pipe")
+    return out
+
+
+def mhd_batch_tune(h, reps: int = 5):
+    _abi.check(_abi.lib().mhd_batch_tune(h, int(reps)), "mhd_batch_tune")
+
+
+def mhd_batch_step(h, n_steps: int, budget_every: int = 0):
+    _abi.check(_abi.lib().mhd_batch_step(h, int(n_steps), int(budget_every)), "mhd_batch_step")
+
+
+def mhd_batch_set_graph(h, enable: bool):
+    _abi.check(_abi.lib().mhd_batch_set_graph(h, 1 if enable else 0), "mhd_batch_set_graph")
+
+
+def mhd_batch_set_profiling(h, enable: bool):
+    _abi.check(_abi.lib().mhd_batch_set_profiling(h, 1 if enable else 0),
+               "mhd_batch_set_profiling")
+
+
+def mhd_batch_kernel_stats(h, kernel: int):
+    n = C.c_int64(0)
+    ms = C.c_double(0)
+    _abi.check(_abi.lib().mhd_batch_kernel_stats(h, int(kernel), C.byref(n), C.byref(ms)),
+               "mhd_batch_kernel_stats")
+    return int(n.value), float(ms.value)
+
+
+def mhd_batch_destroy(h):
+    _abi.check(_abi.lib().mhd_batch_destroy(h), "mhd_batch_destroy")
+
+
 # ----------------------------------------------------------------------------------------------
 # Convenience wrapper: torch owns the workspace and the stream
 # ----------------------------------------------------------------------------------------------
@@ -161,15 +233,20 @@ class Sim:
 
     def __init__(self, nx: int, ny: int, nz: int, n_markers: int = 0, *, rho_storage="f32",
                  u_storage="f32", b_storage="f32", u_scale: float = 1.0, b_scale: float = 1.0,
-                 device=None, stream=None):
-        import torch
-
+                 device=None, stream=None, _handle=None, _owner=None):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.N = self.nx * self.ny * self.nz
         self.desc = mhd_grid_desc(self.nx, self.ny, self.nz, _STORAGE[rho_storage],
                                   _STORAGE[u_storage], _STORAGE[b_storage], float(u_scale),
                                   float(b_scale))
         self.n_markers = int(n_markers)
+        if _handle is not None:  # a pipe of a Batch: the batch owns the handle and the memory
+            self._h = _handle
+            self._owner = _owner
+            return
+        self._owner = None
+        import torch
+
         nbytes = mhd_workspace_size(self.desc, self.n_markers)
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self._stream = stream if stream is not None else torch.cuda.current_stream(dev)
@@ -224,9 +301,83 @@ class Sim:
     def kernel_stats(self, kernel: int):
         return mhd_kernel_stats(self._h, kernel)
 
+    @property
+    def tiles(self):
+        """Sweep tile choice (x tile, z chunk, paired form, rows of the paired form)."""
+        return mhd_get_tiles(self._h)
+
+    @tiles.setter
+    def tiles(self, t):
+        mhd_set_tiles(self._h, t)
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h = None
+            return
         if getattr(self, "_h", None) is not None and self._h.value:
             mhd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent boxes advanced together (`mhd_batch_*`); `pipes[i]` is a Sim view of
+    box i for setup and read-back. Stepped on a torch CUDA stream of its own unless one is
+    given (`stream.synchronize()` or `torch.cuda.synchronize()` before timing)."""
+
+    def __init__(self, boxes, *, rho_storage="f32", u_storage="f32", b_storage="f32",
+                 u_scale: float = 1.0, b_scale: float = 1.0, device=None, stream=None):
+        """boxes: sequence of (nx, ny, nz, n_markers)."""
+        import torch
+
+        self.boxes = [tuple(int(v) for v in b) for b in boxes]
+        kinds = (_STORAGE[rho_storage], _STORAGE[u_storage], _STORAGE[b_storage])
+        descs = [mhd_pipe_desc(mhd_grid_desc(nx, ny, nz, *kinds, float(u_scale), float(b_scale)), m)
+                 for nx, ny, nz, m in self.boxes]
+        nbytes = mhd_batch_workspace_size(descs)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        # a stream of its own by default: the NULL stream cannot be captured into a graph
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize(dev)  # the workspace allocation is ordered on torch's stream
+        self._ptr = (self._ws.data_ptr() + 255) & ~255
+        self.workspace_bytes = nbytes
+        self._h = mhd_batch_create(descs, self._ptr, nbytes, self._stream.cuda_stream)
+        self.pipes = []
+        for i, (nx, ny, nz, m) in enumerate(self.boxes):
+            self.pipes.append(Sim(nx, ny, nz, m, rho_storage=rho_storage, u_storage=u_storage,
+                                  b_storage=b_storage, u_scale=u_scale, b_scale=b_scale,
+                                  _handle=mhd_batch_pipe(self._h, i), _owner=self))
+
+    @property
+    def n_cells(self) -> int:
+        return sum(nx * ny * nz for nx, ny, nz, _ in self.boxes)
+
+    def tune(self, reps: int = 5):
+        mhd_batch_tune(self._h, reps)
+
+    def step(self, n: int = 1, budget_every: int = 0):
+        mhd_batch_step(self._h, n, budget_every)
+
+    def set_graph(self, on: bool):
+        mhd_batch_set_graph(self._h, on)
+
+    def set_profiling(self, on: bool):
+        mhd_batch_set_profiling(self._h, on)
+
+    def kernel_stats(self, kernel: int):
+        return mhd_batch_kernel_stats(self._h, kernel)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for p in self.pipes:
+                p._h = None
+            mhd_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -30,13 +30,20 @@ MHD_FIELD_RHO, MHD_FIELD_U, MHD_FIELD_B_INDUCED = 0, 1, 2
 EXPORTS = ("mhd_last_error", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
-           "mhd_kernel_stats", "mhd_destroy")
+           "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles",
+           "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
+           "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
+           "mhd_batch_kernel_stats", "mhd_batch_destroy")
 
 
 class mhd_grid_desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("rho_storage", C.c_int32), ("u_storage", C.c_int32), ("b_storage", C.c_int32),
                 ("u_scale", C.c_double), ("b_scale", C.c_double)]
+
+
+class mhd_pipe_desc(C.Structure):
+    _fields_ = [("grid", mhd_grid_desc), ("n_markers", C.c_int64)]
 
 
 class mhd_params(C.Structure):
@@ -87,6 +94,21 @@ def lib() -> C.CDLL:
         L.mhd_set_profiling.argtypes = [P, C.c_int32]
         L.mhd_kernel_stats.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.mhd_destroy.argtypes = [P]
+        I4 = C.c_int32 * 4
+        L.mhd_get_tiles.argtypes = [P, I4]
+        L.mhd_set_tiles.argtypes = [P, I4]
+        PD = C.POINTER(mhd_pipe_desc)
+        L.mhd_batch_workspace_size.argtypes = [PD, C.c_int32, C.POINTER(C.c_size_t)]
+        L.mhd_batch_create.argtypes = [PD, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.POINTER(C.c_void_p)]
+        L.mhd_batch_pipe.argtypes = [P, C.c_int32, C.POINTER(C.c_void_p)]
+        L.mhd_batch_tune.argtypes = [P, C.c_int32]
+        L.mhd_batch_step.argtypes = [P, C.c_int64, C.c_int32]
+        L.mhd_batch_set_graph.argtypes = [P, C.c_int32]
+        L.mhd_batch_set_profiling.argtypes = [P, C.c_int32]
+        L.mhd_batch_kernel_stats.argtypes = [P, C.c_int32, C.POINTER(C.c_int64),
+                                             C.POINTER(C.c_double)]
+        L.mhd_batch_destroy.argtypes = [P]
         for name in EXPORTS:
             if name != "mhd_last_error":
                 getattr(L, name).restype = C.c_int32

@@ -45,6 +45,19 @@ struct SweepLaunch {
     int pair;            // 1: two x cells per lane (n_x a multiple of 128); ty = rows per tile
 };
 
+// Arguments of one magnetic sweep launch over one box.
+struct SweepArgs {
+    const void *u;
+    const void *b;
+    void *bo;
+    const float *bext;  // 3 x nx
+    int nx, ny, nz;
+    int tiles_x, tiles_y, nzc, zchunk, nblocks;
+    float kappa, u_scale, b_scale, inv_b_scale;
+};
+// Sweep arguments of a box for tile choice L (tile counts and workgroup count filled in).
+SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *bext, StepConst c, SweepLaunch L);
+
 hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c);
 hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part, StepConst c,
                            double inv_count);
@@ -73,6 +86,45 @@ hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double 
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b,
                          const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring,
                          StepConst c);
+// -------------------------------------------------------------------------------------------
+// Batched launches: one launch covers the same kernel for many boxes. Each workgroup finds its
+// box and its workgroup index within that box in a map of (box, local workgroup) pairs, then
+// reads the box's arguments from a device table of PipeStep records and runs the same body as
+// the single-box kernel, so every box gets bitwise the result of its own single-box launch.
+// -------------------------------------------------------------------------------------------
+struct PipeStep {
+    SweepArgs sw[2];          // sweep of an even / odd round (the b buffers swap every round)
+    IbArgs ib[3];             // wall correction of b after an even round, after an odd round; of u
+    void *phi[3];             // field corrected by ib[i]
+    float scale[3], inv_scale[3];
+    const void *b_last;       // b after the box's last sweep (Lorentz input)
+    const float *bext;
+    DevCtrl *ctrl;
+    float *F;
+    const void *rho, *u;      // fluid input
+    void *rho_o, *u_o;        // fluid output (input of the flow-rate sum)
+    double *flow_part;
+    double inv_count;
+    StepConst c;
+};
+struct BlockMap {             // (box, workgroup within the box) of workgroup i of a batched launch
+    int pipe, local;
+};
+hipError_t launch_ctrl_begin_batch(hipStream_t s, const PipeStep *tab, int n);
+hipError_t launch_step_end_batch(hipStream_t s, const PipeStep *tab, int n);
+hipError_t launch_mag_sweep_batch(hipStream_t s, int kinds, SweepLaunch L, const PipeStep *tab, const BlockMap *map,
+                                  int parity, int nblocks);
+hipError_t launch_ib_interp_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,
+                                  int nblocks);
+hipError_t launch_ib_spread_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,
+                                  int nblocks);
+hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks);
+hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks);
+hipError_t launch_flow_partial_batch(hipStream_t s, int kind_u, const PipeStep *tab, int n);
+// Workgroups per box of the cell-wise kernels and of the wall-correction launches.
+constexpr int kCellThreads = 256;
+constexpr int kIbThreads = 256;
+
 // float32 staging <-> storage kind (round to nearest even on the way in).
 hipError_t launch_store_kind(hipStream_t s, int kind, const float *src, void *dst, int64_t n);
 hipError_t launch_load_kind(hipStream_t s, int kind, const void *src, float *dst, int64_t n);

@@ -88,8 +88,7 @@ __constant__ int c_dir[18][3] = {{1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
 // -------------------------------------------------------------------------------------------
 // Control kernels
 // -------------------------------------------------------------------------------------------
-__global__ void k_ctrl_begin(DevCtrl *ctrl, StepConst c) {
-    if (threadIdx.x != 0) return;
+__device__ __forceinline__ void ctrl_begin_body(DevCtrl *ctrl, const StepConst &c) {
     double G;
     if (c.flow_control)
         G = ctrl->G;
@@ -99,10 +98,25 @@ __global__ void k_ctrl_begin(DevCtrl *ctrl, StepConst c) {
         G = c.G0;
     ctrl->G_step = G;
 }
+__global__ void k_ctrl_begin(DevCtrl *ctrl, StepConst c) {
+    if (threadIdx.x == 0) ctrl_begin_body(ctrl, c);
+}
+// one workgroup per box
+__global__ void k_ctrl_begin_batch(const PipeStep *tab) {
+    if (threadIdx.x == 0) ctrl_begin_body(tab[blockIdx.x].ctrl, tab[blockIdx.x].c);
+}
 
-// Fixed-order sum of the flow partials (one block), integral control law, step counter.
+// Fixed-order sum of the flow partials (one block per box), integral control law, step counter.
+template <bool BATCH>
 __global__ void __launch_bounds__(kRedThreads) k_step_end(DevCtrl *ctrl, const double *part, StepConst c,
-                                                          double inv_count) {
+                                                          double inv_count, const PipeStep *tab) {
+    if constexpr (BATCH) {
+        const PipeStep &q = tab[blockIdx.x];
+        ctrl = q.ctrl;
+        part = q.flow_part;
+        c = q.c;
+        inv_count = q.inv_count;
+    }
     __shared__ double sh[kRedThreads];
     double s = 0.0;
     if (c.flow_control)
@@ -152,18 +166,9 @@ __global__ void k_reset_records(DevCtrl *ctrl) {
 //   b*_x = avg b_x + D_y Lxy + D_z Lxz,  b*_y = avg b_y - D_x Lxy + D_z Lyz,
 //   b*_z = avg b_z - D_x Lxz - D_y Lyz.
 // -------------------------------------------------------------------------------------------
-struct SweepArgs {
-    const void *u;
-    const void *b;
-    void *bo;
-    const float *bext;  // 3 x nx
-    int nx, ny, nz;
-    int tiles_x, tiles_y, nzc, zchunk, nblocks;
-    float kappa, u_scale, b_scale, inv_b_scale;
-};
-
-template <int TX, int TY, typename TU, typename TB>
-__global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
+template <int TX, int TY, typename TU, typename TB, bool BATCH>
+__global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeStep *tab, const BlockMap *map,
+                                                      int parity, int nbatch) {
     constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
     constexpr int NSLOT = (HN + NT - 1) / NT;
     // two LDS planes: the next plane is staged while the current one is reduced
@@ -172,8 +177,15 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a) {
     // XCD-aware order: the hardware hands consecutive workgroups to the 8 XCDs in turn; give
     // each XCD a contiguous run of tiles so neighbouring tiles share halo rows in one L2.
     const int per = gridDim.x >> 3;
-    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (lb >= a.nblocks) return;
+    int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if constexpr (BATCH) {
+        if (lb >= nbatch) return;
+        const BlockMap m = map[lb];
+        a = tab[m.pipe].sw[parity];
+        lb = m.local;
+    } else {
+        if (lb >= a.nblocks) return;
+    }
     const int tix = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int tiy = rest % a.tiles_y;
@@ -406,19 +418,24 @@ struct Pair<__hip_bfloat16> {
     }
 };
 
-// The per-plane terms of one cell from the 3x3 in-plane neighbourhoods of the six staged
-// fields: f[k][r][j] = field k, row y-1+r, column x-1+j.
-template <int TY, typename TU, typename TB>
-__global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a) {
-    constexpr int NT = 64 * TY;
+template <int TY, typename TU, typename TB, bool BATCH>
+__global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
+                                                            int parity, int nbatch) {
     constexpr int HY = TY + 2;        // staged rows
     constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
     constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
     __shared__ __align__(16) float s_pl[2][6][HY * RS];
 
     const int per = gridDim.x >> 3;
-    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (lb >= a.nblocks) return;
+    int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if constexpr (BATCH) {
+        if (lb >= nbatch) return;
+        const BlockMap m = map[lb];
+        a = tab[m.pipe].sw[parity];
+        lb = m.local;
+    } else {
+        if (lb >= a.nblocks) return;
+    }
     const int tix = lb % a.tiles_x;
     const int rest = lb / a.tiles_x;
     const int tiy = rest % a.tiles_y;
@@ -697,9 +714,19 @@ __device__ __forceinline__ void ib_cell(T *phi, float scale, float inv_scale, co
     St<T>::st(phi, 2 * a.N + k, (v2 + c2) * inv_scale);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_ib_interp(const T *phi, float scale, IbArgs a) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(kIbThreads) k_ib_interp(const T *phi, float scale, IbArgs a, const PipeStep *tab,
+                                                          const BlockMap *map, int which) {
+    int blk = blockIdx.x;
+    if constexpr (BATCH) {
+        const BlockMap m = map[blk];
+        const PipeStep &q = tab[m.pipe];
+        a = q.ib[which];
+        phi = (const T *)q.phi[which];
+        scale = q.scale[which];
+        blk = m.local;
+    }
+    const int j = blk * kIbThreads + threadIdx.x;
     if (j >= a.M) return;
     float d0, d1, d2;
     ib_marker(phi, scale, a, j, d0, d1, d2);
@@ -708,9 +735,20 @@ __global__ void __launch_bounds__(256) k_ib_interp(const T *phi, float scale, Ib
     a.delta[2 * a.M + j] = d2;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_ib_spread(T *phi, float scale, float inv_scale, IbArgs a) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(kIbThreads) k_ib_spread(T *phi, float scale, float inv_scale, IbArgs a,
+                                                          const PipeStep *tab, const BlockMap *map, int which) {
+    int blk = blockIdx.x;
+    if constexpr (BATCH) {
+        const BlockMap m = map[blk];
+        const PipeStep &q = tab[m.pipe];
+        a = q.ib[which];
+        phi = (T *)q.phi[which];
+        scale = q.scale[which];
+        inv_scale = q.inv_scale[which];
+        blk = m.local;
+    }
+    const int e = blk * kIbThreads + threadIdx.x;
     if (e >= a.nband) return;
     ib_cell(phi, scale, inv_scale, a, e, a.delta, a.delta + a.M, a.delta + 2 * a.M, 0);
 }
@@ -719,11 +757,24 @@ __global__ void __launch_bounds__(256) k_ib_spread(T *phi, float scale, float in
 // Lorentz + body force (Sec. 5.1): J = curl_h b with d_a f = 3 sum_i w_i e_ia f(x + e_i),
 // F = G x + J x (B_ext + b).
 // -------------------------------------------------------------------------------------------
-template <typename TB>
-__global__ void __launch_bounds__(256) k_lorentz(const TB *b, float bs, const float *bext, const DevCtrl *ctrl,
-                                                 float *F, StepConst c) {
+template <typename TB, bool BATCH>
+__global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, float bs, const float *bext,
+                                                          const DevCtrl *ctrl, float *F, StepConst c,
+                                                          const PipeStep *tab, const BlockMap *map) {
+    int64_t blk = blockIdx.x;
+    if constexpr (BATCH) {
+        const BlockMap m = map[blk];
+        const PipeStep &q = tab[m.pipe];
+        b = (const TB *)q.b_last;
+        bs = q.c.b_scale;
+        bext = q.bext;
+        ctrl = q.ctrl;
+        F = q.F;
+        c = q.c;
+        blk = m.local;
+    }
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = blk * kCellThreads + threadIdx.x;
     if (k >= N) return;
     const int x = (int)(k % c.nx);
     const int y = (int)((k / c.nx) % c.ny);
@@ -776,11 +827,24 @@ __global__ void __launch_bounds__(256) k_lorentz(const TB *b, float bs, const fl
 __constant__ int c_pair[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0},
                                  {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
 
-template <typename TR, typename TU>
-__global__ void __launch_bounds__(256) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o, TU *u_o,
-                                               StepConst c) {
+template <typename TR, typename TU, bool BATCH>
+__global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o,
+                                                        TU *u_o, StepConst c, const PipeStep *tab,
+                                                        const BlockMap *map) {
+    int64_t blk = blockIdx.x;
+    if constexpr (BATCH) {
+        const BlockMap m = map[blk];
+        const PipeStep &q = tab[m.pipe];
+        rho = (const TR *)q.rho;
+        u = (const TU *)q.u;
+        F = q.F;
+        rho_o = (TR *)q.rho_o;
+        u_o = (TU *)q.u_o;
+        c = q.c;
+        blk = m.local;
+    }
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = blk * kCellThreads + threadIdx.x;
     if (k >= N) return;
     const int x = (int)(k % c.nx);
     const int y = (int)((k / c.nx) % c.ny);
@@ -863,13 +927,23 @@ __device__ __forceinline__ void block_sum(double (*sh)[kRedThreads], double *v) 
     }
 }
 
-template <typename TU>
-__global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, double *part, StepConst c) {
+template <typename TU, bool BATCH>
+__global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, double *part, StepConst c,
+                                                              const PipeStep *tab) {
+    int blk = blockIdx.x;
+    if constexpr (BATCH) {  // kRedBlocks workgroups per box
+        const PipeStep &q = tab[blockIdx.x / kRedBlocks];
+        if (!q.c.flow_control) return;
+        u = (const TU *)q.u_o;
+        part = q.flow_part;
+        c = q.c;
+        blk = blockIdx.x % kRedBlocks;
+    }
     __shared__ double sh[1][kRedThreads];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const double R2 = c.radius * c.radius;
     double s = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
+    for (int64_t k = (int64_t)blk * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
         const int y = (int)((k / c.nx) % c.ny);
         const int z = (int)(k / ((int64_t)c.nx * c.ny));
         const double dy = y - c.yc, dz = z - c.zc;
@@ -877,7 +951,7 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
     }
     double v[1] = {s};
     block_sum<1>(sh, v);
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0][0];
+    if (threadIdx.x == 0) part[blk] = sh[0][0];
 }
 
 // partial layout: 0 Ek, 1 Em, 2 Eb, 3 sum u_x (Omega), 4 Pp, 5 Pnu/nu, 6 PL, 7 Meta/eta, 8 Madv,
@@ -1061,7 +1135,19 @@ hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c) {
 }
 
 hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part, StepConst c, double inv_count) {
-    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(kRedThreads), 0, s, ctrl, flow_part, c, inv_count);
+    hipLaunchKernelGGL(k_step_end<false>, dim3(1), dim3(kRedThreads), 0, s, ctrl, flow_part, c, inv_count, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_begin_batch(hipStream_t s, const PipeStep *tab, int n) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ctrl_begin_batch, dim3(n), dim3(64), 0, s, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end_batch(hipStream_t s, const PipeStep *tab, int n) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step_end<true>, dim3(n), dim3(kRedThreads), 0, s, nullptr, nullptr, StepConst{}, 0.0, tab);
     return hipGetLastError();
 }
 
@@ -1070,9 +1156,7 @@ hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl) {
     return hipGetLastError();
 }
 
-template <int TX, int TY, typename TU, typename TB>
-static hipError_t sweep_tile(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
-                             int zchunk) {
+SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *bext, StepConst c, SweepLaunch L) {
     SweepArgs a;
     a.u = u;
     a.b = b;
@@ -1081,58 +1165,50 @@ static hipError_t sweep_tile(hipStream_t s, const void *u, const void *b, void *
     a.nx = c.nx;
     a.ny = c.ny;
     a.nz = c.nz;
-    a.tiles_x = (c.nx + TX - 1) / TX;
-    a.tiles_y = (c.ny + TY - 1) / TY;
-    a.zchunk = zchunk;
-    a.nzc = (c.nz + zchunk - 1) / zchunk;
+    const bool pair = L.pair && c.nx % 128 == 0;
+    const int tx = pair ? 128 : L.tx;
+    const int ty = pair ? (L.ty >= 8 ? 8 : 4) : 256 / L.tx;
+    a.tiles_x = (c.nx + tx - 1) / tx;
+    a.tiles_y = (c.ny + ty - 1) / ty;
+    a.zchunk = L.zchunk;
+    a.nzc = (c.nz + L.zchunk - 1) / L.zchunk;
     a.nblocks = a.tiles_x * a.tiles_y * a.nzc;
     a.kappa = c.kappa;
     a.u_scale = c.u_scale;
     a.b_scale = c.b_scale;
     a.inv_b_scale = c.inv_b_scale;
-    const unsigned grid = (unsigned)(((a.nblocks + 7) / 8) * 8);
-    hipLaunchKernelGGL((k_mag_sweep<TX, TY, TU, TB>), dim3(grid), dim3(TX * TY), 0, s, a);
-    return hipGetLastError();
+    return a;
 }
 
-template <int TY, typename TU, typename TB>
-static hipError_t sweep_pair_tile(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
-                                  int zchunk) {
-    SweepArgs a;
-    a.u = u;
-    a.b = b;
-    a.bo = bo;
-    a.bext = bext;
-    a.nx = c.nx;
-    a.ny = c.ny;
-    a.nz = c.nz;
-    a.tiles_x = c.nx / 128;
-    a.tiles_y = (c.ny + TY - 1) / TY;
-    a.zchunk = zchunk;
-    a.nzc = (c.nz + zchunk - 1) / zchunk;
-    a.nblocks = a.tiles_x * a.tiles_y * a.nzc;
-    a.kappa = c.kappa;
-    a.u_scale = c.u_scale;
-    a.b_scale = c.b_scale;
-    a.inv_b_scale = c.inv_b_scale;
-    const unsigned grid = (unsigned)(((a.nblocks + 7) / 8) * 8);
-    hipLaunchKernelGGL((k_mag_sweep_pair<TY, TU, TB>), dim3(grid), dim3(64 * TY), 0, s, a);
-    return hipGetLastError();
-}
+// grid of a sweep launch: a multiple of 8 so the XCD-aware remap is a permutation
+static inline unsigned sweep_grid(int nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
 
-template <typename TU, typename TB>
-static hipError_t sweep_typed(hipStream_t s, const void *u, const void *b, void *bo, const float *bext, StepConst c,
-                              SweepLaunch L) {
-    if (L.pair && c.nx % 128 == 0) {
-        if (L.ty >= 8) return sweep_pair_tile<8, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
-        return sweep_pair_tile<4, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+template <typename TU, typename TB, bool BATCH>
+static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
+                              const BlockMap *map, int parity, int nblocks) {
+    const dim3 grid(sweep_grid(nblocks));
+    if (L.pair) {
+        if (L.ty >= 8)
+            hipLaunchKernelGGL((k_mag_sweep_pair<8, TU, TB, BATCH>), grid, dim3(512), 0, s, a, tab, map, parity, nblocks);
+        else
+            hipLaunchKernelGGL((k_mag_sweep_pair<4, TU, TB, BATCH>), grid, dim3(256), 0, s, a, tab, map, parity, nblocks);
+        return hipGetLastError();
     }
     switch (L.tx) {
-        case 64: return sweep_tile<64, 4, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
-        case 32: return sweep_tile<32, 8, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
-        case 16: return sweep_tile<16, 16, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
-        default: return sweep_tile<8, 32, TU, TB>(s, u, b, bo, bext, c, L.zchunk);
+        case 64:
+            hipLaunchKernelGGL((k_mag_sweep<64, 4, TU, TB, BATCH>), grid, dim3(256), 0, s, a, tab, map, parity, nblocks);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_mag_sweep<32, 8, TU, TB, BATCH>), grid, dim3(256), 0, s, a, tab, map, parity, nblocks);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_mag_sweep<16, 16, TU, TB, BATCH>), grid, dim3(256), 0, s, a, tab, map, parity, nblocks);
+            break;
+        default:
+            hipLaunchKernelGGL((k_mag_sweep<8, 32, TU, TB, BATCH>), grid, dim3(256), 0, s, a, tab, map, parity, nblocks);
+            break;
     }
+    return hipGetLastError();
 }
 
 // Supported storage mixes: all float32; rho f16 with u f16 or bf16 and b f16; all bf16.
@@ -1140,15 +1216,32 @@ static hipError_t sweep_typed(hipStream_t s, const void *u, const void *b, void 
 #define MHD_KIND_F16 1
 #define MHD_KIND_BF16 2
 
+template <bool BATCH>
+static hipError_t sweep_kinds(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
+                              const BlockMap *map, int parity, int nblocks) {
+    const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
+    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
+        return sweep_typed<float, float, BATCH>(s, a, L, tab, map, parity, nblocks);
+    if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
+        return sweep_typed<__half, __half, BATCH>(s, a, L, tab, map, parity, nblocks);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
+        return sweep_typed<__hip_bfloat16, __half, BATCH>(s, a, L, tab, map, parity, nblocks);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
+        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH>(s, a, L, tab, map, parity, nblocks);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo, const float *bext,
                             StepConst c, SweepLaunch L) {
-    const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
-    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32) return sweep_typed<float, float>(s, u, b, bo, bext, c, L);
-    if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16) return sweep_typed<__half, __half>(s, u, b, bo, bext, c, L);
-    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16) return sweep_typed<__hip_bfloat16, __half>(s, u, b, bo, bext, c, L);
-    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
-        return sweep_typed<__hip_bfloat16, __hip_bfloat16>(s, u, b, bo, bext, c, L);
-    return hipErrorInvalidValue;
+    L.pair = L.pair && c.nx % 128 == 0;
+    const SweepArgs a = make_sweep_args(u, b, bo, bext, c, L);
+    return sweep_kinds<false>(s, kinds, a, L, nullptr, nullptr, 0, a.nblocks);
+}
+
+hipError_t launch_mag_sweep_batch(hipStream_t s, int kinds, SweepLaunch L, const PipeStep *tab, const BlockMap *map,
+                                  int parity, int nblocks) {
+    if (nblocks <= 0) return hipSuccess;
+    return sweep_kinds<true>(s, kinds, SweepArgs{}, L, tab, map, parity, nblocks);
 }
 
 #define MHD_DISPATCH1(kind, FN, ...)                                       \
@@ -1162,10 +1255,12 @@ hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void 
 template <typename T>
 static hipError_t ib_t(hipStream_t s, void *phi, float scale, float inv_scale, const IbArgs &a) {
     if (a.M <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ib_interp<T>, dim3(blocks_for(a.M, 256)), dim3(256), 0, s, (const T *)phi, scale, a);
+    hipLaunchKernelGGL((k_ib_interp<T, false>), dim3(blocks_for(a.M, kIbThreads)), dim3(kIbThreads), 0, s,
+                       (const T *)phi, scale, a, nullptr, nullptr, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.nband <= 0) return e;
-    hipLaunchKernelGGL(k_ib_spread<T>, dim3(blocks_for(a.nband, 256)), dim3(256), 0, s, (T *)phi, scale, inv_scale, a);
+    hipLaunchKernelGGL((k_ib_spread<T, false>), dim3(blocks_for(a.nband, kIbThreads)), dim3(kIbThreads), 0, s,
+                       (T *)phi, scale, inv_scale, a, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_scale, const IbArgs &a) {
@@ -1173,44 +1268,100 @@ hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_
 }
 
 template <typename T>
+static hipError_t ib_interp_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int which, int nblocks) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ib_interp<T, true>), dim3(nblocks), dim3(kIbThreads), 0, s, nullptr, 0.f, IbArgs{}, tab, map,
+                       which);
+    return hipGetLastError();
+}
+hipError_t launch_ib_interp_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,
+                                  int nblocks) {
+    MHD_DISPATCH1(kind, ib_interp_batch_t, s, tab, map, which, nblocks)
+}
+template <typename T>
+static hipError_t ib_spread_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int which, int nblocks) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ib_spread<T, true>), dim3(nblocks), dim3(kIbThreads), 0, s, nullptr, 0.f, 0.f, IbArgs{}, tab,
+                       map, which);
+    return hipGetLastError();
+}
+hipError_t launch_ib_spread_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,
+                                  int nblocks) {
+    MHD_DISPATCH1(kind, ib_spread_batch_t, s, tab, map, which, nblocks)
+}
+
+template <typename T>
 static hipError_t lorentz_t(hipStream_t s, const void *b, const float *bext, const DevCtrl *ctrl, float *F,
                             StepConst c) {
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    hipLaunchKernelGGL(k_lorentz<T>, dim3(blocks_for(N, 256)), dim3(256), 0, s, (const T *)b, c.b_scale, bext, ctrl,
-                       F, c);
+    hipLaunchKernelGGL((k_lorentz<T, false>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads), 0, s,
+                       (const T *)b, c.b_scale, bext, ctrl, F, c, nullptr, nullptr);
     return hipGetLastError();
 }
 hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const float *bext, const DevCtrl *ctrl, float *F,
                           StepConst c) {
     MHD_DISPATCH1(kind_b, lorentz_t, s, b, bext, ctrl, F, c)
 }
-
-template <typename TR, typename TU>
-static hipError_t fluid_t(hipStream_t s, const void *rho, const void *u, const float *F, void *rho_o, void *u_o,
-                          StepConst c) {
-    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    hipLaunchKernelGGL((k_fluid<TR, TU>), dim3(blocks_for(N, 256)), dim3(256), 0, s, (const TR *)rho, (const TU *)u,
-                       F, (TR *)rho_o, (TU *)u_o, c);
+template <typename T>
+static hipError_t lorentz_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int nblocks) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_lorentz<T, true>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr, 0.f, nullptr, nullptr,
+                       nullptr, StepConst{}, tab, map);
     return hipGetLastError();
+}
+hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks) {
+    MHD_DISPATCH1(kind_b, lorentz_batch_t, s, tab, map, nblocks)
+}
+
+template <typename TR, typename TU, bool BATCH>
+static hipError_t fluid_t(hipStream_t s, const void *rho, const void *u, const float *F, void *rho_o, void *u_o,
+                          StepConst c, const PipeStep *tab, const BlockMap *map, int nblocks) {
+    if (!BATCH) nblocks = (int)blocks_for((int64_t)c.nx * c.ny * c.nz, kCellThreads);
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fluid<TR, TU, BATCH>), dim3(nblocks), dim3(kCellThreads), 0, s, (const TR *)rho,
+                       (const TU *)u, F, (TR *)rho_o, (TU *)u_o, c, tab, map);
+    return hipGetLastError();
+}
+template <bool BATCH>
+static hipError_t fluid_kinds(hipStream_t s, int kinds, const void *rho, const void *u, const float *F, void *rho_o,
+                              void *u_o, StepConst c, const PipeStep *tab, const BlockMap *map, int nblocks) {
+    const int kr = kinds & 15, ku = (kinds >> 4) & 15;
+    if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32)
+        return fluid_t<float, float, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+    if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16)
+        return fluid_t<__half, __half, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+    if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16)
+        return fluid_t<__half, __hip_bfloat16, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+    if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16)
+        return fluid_t<__hip_bfloat16, __hip_bfloat16, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+    return hipErrorInvalidValue;
 }
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F, void *rho_o,
                         void *u_o, StepConst c) {
-    const int kr = kinds & 15, ku = (kinds >> 4) & 15;
-    if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32) return fluid_t<float, float>(s, rho, u, F, rho_o, u_o, c);
-    if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16) return fluid_t<__half, __half>(s, rho, u, F, rho_o, u_o, c);
-    if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16) return fluid_t<__half, __hip_bfloat16>(s, rho, u, F, rho_o, u_o, c);
-    if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16)
-        return fluid_t<__hip_bfloat16, __hip_bfloat16>(s, rho, u, F, rho_o, u_o, c);
-    return hipErrorInvalidValue;
+    return fluid_kinds<false>(s, kinds, rho, u, F, rho_o, u_o, c, nullptr, nullptr, 0);
+}
+hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks) {
+    return fluid_kinds<true>(s, kinds, nullptr, nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map, nblocks);
 }
 
 template <typename T>
 static hipError_t flow_t(hipStream_t s, const void *u, double *part, StepConst c) {
-    hipLaunchKernelGGL(k_flow_partial<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const T *)u, part, c);
+    hipLaunchKernelGGL((k_flow_partial<T, false>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const T *)u, part, c,
+                       nullptr);
     return hipGetLastError();
 }
 hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c) {
     MHD_DISPATCH1(kind_u, flow_t, s, u, part, c)
+}
+template <typename T>
+static hipError_t flow_batch_t(hipStream_t s, const PipeStep *tab, int n) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_flow_partial<T, true>), dim3(n * kRedBlocks), dim3(kRedThreads), 0, s, nullptr, nullptr,
+                       StepConst{}, tab);
+    return hipGetLastError();
+}
+hipError_t launch_flow_partial_batch(hipStream_t s, int kind_u, const PipeStep *tab, int n) {
+    MHD_DISPATCH1(kind_u, flow_batch_t, s, tab, n)
 }
 
 template <typename TR, typename TU, typename TB>

@@ -151,6 +151,7 @@ struct mhd_sim {
     bool prof = false;
     std::vector<Event2> ev_pool[MHD_K_COUNT];
     size_t ev_used[MHD_K_COUNT] = {};
+    mhd_batch *owner = nullptr;  // batch this box belongs to (it then owns the box)
 
     template <typename T>
     T *at(size_t off) const {
@@ -163,6 +164,8 @@ struct mhd_sim {
 };
 
 namespace {
+
+void batch_touch(mhd_batch *b);  // the launch plan of a batch must be rebuilt
 
 StepConst step_const(const mhd_sim *s) {
     StepConst c{};
@@ -373,6 +376,29 @@ int env_int(const char *name, int dflt) {
     return std::atoi(v);
 }
 
+bool valid_tx(int tx) { return tx == 8 || tx == 16 || tx == 32 || tx == 64; }
+
+// Default sweep tiles of a box (environment overrides for experiments: MHD_SWEEP_TX,
+// MHD_SWEEP_ZCHUNK, MHD_SWEEP_PAIR, MHD_SWEEP_PAIR_TY).
+SweepLaunch default_tiles(int nx) {
+    SweepLaunch L;
+    L.tx = nx >= 64 ? 64 : nx >= 32 ? 32 : nx >= 16 ? 16 : 8;
+    const int etx = env_int("MHD_SWEEP_TX", L.tx);
+    if (valid_tx(etx)) L.tx = etx;
+    L.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", 8));
+    L.pair = (nx % 128 == 0) && env_int("MHD_SWEEP_PAIR", 1) != 0;
+    L.ty = env_int("MHD_SWEEP_PAIR_TY", 4) >= 8 ? 8 : 4;
+    return L;
+}
+
+// The tile choice a launch really uses (the paired form needs nx % 128 == 0).
+SweepLaunch effective_tiles(const SweepLaunch &L, int nx) {
+    SweepLaunch e = L;
+    e.pair = L.pair && nx % 128 == 0;
+    e.ty = L.ty >= 8 ? 8 : 4;
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -416,16 +442,10 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
         delete s;
         return fail(MHD_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
     }
-    // tile shape: widest x tile that the box fills, 256 work-items per workgroup
+    // tile shape: widest x tile that the box fills, 256 work-items per workgroup; two x cells
+    // per lane whenever a row splits into 128-cell tiles (fewer LDS reads per cell)
     const int nx = g->nx;
-    s->sweep.tx = nx >= 64 ? 64 : nx >= 32 ? 32 : nx >= 16 ? 16 : 8;
-    s->sweep.ty = 256 / s->sweep.tx;
-    s->sweep.tx = env_int("MHD_SWEEP_TX", s->sweep.tx);
-    s->sweep.ty = 256 / s->sweep.tx;
-    s->sweep.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", 8));
-    // two x cells per lane whenever a row splits into 128-cell tiles (fewer LDS reads per cell)
-    s->sweep.pair = (nx % 128 == 0) && env_int("MHD_SWEEP_PAIR", 1) != 0;
-    if (s->sweep.pair) s->sweep.ty = env_int("MHD_SWEEP_PAIR_TY", 4) >= 8 ? 8 : 4;
+    s->sweep = default_tiles(nx);
     // initial state: rho = 1, u = 0, b = 0, t = 0, G = 0
     DevCtrl hc{};
     mhd_status st;
@@ -561,6 +581,7 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
     s->tm = tm;
     s->km = km;
     s->d = std::move(d);
+    if (s->owner) batch_touch(s->owner);
     mhd_status st = upload_scalings(s);
     if (st != MHD_OK) {  // the wall is dropped rather than left half-configured
         s->M = 0;
@@ -589,6 +610,7 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
     const mhd_params old = s->prm;
     s->prm = *p;
     s->have_params = true;
+    if (s->owner) batch_touch(s->owner);
     mhd_status st = upload_scalings(s);
     if (st != MHD_OK) {
         s->prm = old;
@@ -688,6 +710,7 @@ mhd_status mhd_set_time(mhd_sim *s, int64_t t, double G) {
 mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every) {
     g_err.clear();
     if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (s->owner) return fail(MHD_ERR_STATE, "this box belongs to a batch: step it with mhd_batch_step");
     if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called before mhd_step");
     if (n_steps < 0) return fail(MHD_ERR_INVALID_ARG, "n_steps < 0");
     for (int64_t i = 0; i < n_steps; ++i) {
@@ -749,6 +772,7 @@ mhd_status mhd_kernel_stats(mhd_sim *s, int32_t kernel, int64_t *launches, doubl
 mhd_status mhd_destroy(mhd_sim *s) {
     g_err.clear();
     if (!s) return MHD_OK;
+    if (s->owner) return fail(MHD_ERR_STATE, "this box belongs to a batch: free it with mhd_batch_destroy");
     (void)hipStreamSynchronize(s->stream);
     for (int k = 0; k < MHD_K_COUNT; ++k)
         for (auto &e : s->ev_pool[k]) {
@@ -756,6 +780,608 @@ mhd_status mhd_destroy(mhd_sim *s) {
             (void)hipEventDestroy(e.b);
         }
     delete s;
+    return MHD_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================================
+// Batched form: many boxes advanced by shared launches (see the kernels' PipeStep / BlockMap)
+// =============================================================================================
+namespace {
+
+// Upper bound of the workgroups of one box in any batched launch kind.
+int64_t sweep_blocks_bound(const mhd_grid_desc &g) {
+    int64_t m = 0;
+    for (int tx : {64, 32, 16, 8}) {
+        const int ty = 256 / tx;
+        m = std::max<int64_t>(m, (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty) * g.nz);
+    }
+    return m;
+}
+int64_t blocks_of(int64_t n, int t) { return (n + t - 1) / t; }
+int64_t map_bound(const mhd_pipe_desc &p) {
+    const int64_t N = (int64_t)p.grid.nx * p.grid.ny * p.grid.nz;
+    return sweep_blocks_bound(p.grid) + blocks_of(p.n_markers, kIbThreads) + blocks_of(27 * p.n_markers, kIbThreads) +
+           blocks_of(N, kCellThreads);
+}
+
+struct BatchLayout {
+    std::vector<size_t> pipe;  // workspace offset of every box
+    std::vector<size_t> pipe_bytes;
+    size_t tab[2] = {0, 0};    // PipeStep[n] of the two buffer phases
+    size_t map = 0;            // BlockMap[map_cap]
+    int64_t map_cap = 0;
+    size_t total = 0;
+};
+
+BatchLayout make_batch_layout(const mhd_pipe_desc *p, int n) {
+    BatchLayout L;
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t sz = make_layout(p[i].grid, p[i].n_markers).total;
+        L.pipe.push_back(off);
+        L.pipe_bytes.push_back(sz);
+        off = align256(off + sz);
+        L.map_cap += map_bound(p[i]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        L.tab[k] = off;
+        off = align256(off + (size_t)n * sizeof(PipeStep));
+    }
+    L.map = off;
+    off = align256(off + (size_t)L.map_cap * sizeof(BlockMap));
+    L.total = off;
+    return L;
+}
+
+mhd_status check_pipes(const mhd_pipe_desc *p, int32_t n) {
+    if (!p) return fail(MHD_ERR_INVALID_ARG, "pipe descriptors are NULL");
+    if (n < 1 || n > (1 << 16)) return fail(MHD_ERR_INVALID_ARG, "n = %d pipes outside [1, 65536]", n);
+    for (int i = 0; i < n; ++i) {
+        STEPCHK(check_desc(&p[i].grid));
+        if (p[i].n_markers < 0 || p[i].n_markers >= ((int64_t)1 << 26))
+            return fail(MHD_ERR_INVALID_ARG, "pipe %d: n_markers must be in [0, 2^26)", i);
+        const mhd_grid_desc &a = p[0].grid, &b = p[i].grid;
+        if (a.rho_storage != b.rho_storage || a.u_storage != b.u_storage || a.b_storage != b.b_storage)
+            return fail(MHD_ERR_UNSUPPORTED, "pipe %d: all pipes of a batch must share the storage kinds", i);
+    }
+    return MHD_OK;
+}
+
+struct BatchSlot {  // launch tables (and graph) of one state of the boxes' double buffers
+    bool valid = false;
+    int64_t version = -1;
+    std::vector<int> sig;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct BatchGroup {  // boxes sharing one sweep kernel (tile form), largest n_mag first
+    SweepLaunch L{};
+    int64_t map_base = 0;
+    std::vector<int> pipes;
+    std::vector<int> nmag;
+    std::vector<int64_t> cum;  // cum[i] = workgroups of the first i boxes
+};
+
+}  // namespace
+
+struct mhd_batch {
+    int n = 0;
+    std::vector<mhd_sim *> pipes;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    BatchLayout L;
+    int kinds = 0, kind_u = 0, kind_b = 0;
+    bool graph = true, prof = false;
+    // launch plan, rebuilt whenever parameters, markers or tiles of a box change
+    int64_t version = 0, plan_version = -1;
+    std::vector<int> order;   // boxes by n_mag, largest first
+    std::vector<int> nmag;    // n_mag of order[i]
+    int max_nmag = 0;
+    std::vector<BatchGroup> groups;
+    int64_t interp_base = 0, spread_base = 0, cell_base = 0;
+    std::vector<int64_t> cum_interp, cum_spread, cum_cells;  // over `order`
+    bool any_flow = false;
+    BatchSlot slot[2];
+    int next_slot = 0;
+    std::vector<Event2> ev_pool[MHD_K_COUNT];
+    size_t ev_used[MHD_K_COUNT] = {};
+
+    PipeStep *tab(int k) const { return reinterpret_cast<PipeStep *>(ws + L.tab[k]); }
+    BlockMap *map() const { return reinterpret_cast<BlockMap *>(ws + L.map); }
+};
+
+namespace {
+
+void batch_touch(mhd_batch *b) { b->version += 1; }
+
+// number of leading entries of a descending list that exceed r
+int active_count(const std::vector<int> &desc, int r) {
+    return (int)(std::upper_bound(desc.begin(), desc.end(), r, [](int v, int x) { return v > x; }) - desc.begin());
+}
+
+void drop_graphs(mhd_batch *b) {
+    for (auto &sl : b->slot) {
+        if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+        sl.exec = nullptr;
+        sl.valid = false;
+    }
+}
+
+mhd_status build_plan(mhd_batch *b) {
+    for (int i = 0; i < b->n; ++i)
+        if (!b->pipes[i]->have_params) return fail(MHD_ERR_STATE, "pipe %d has no parameters (mhd_set_params)", i);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->order.resize(b->n);
+    for (int i = 0; i < b->n; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return b->pipes[x]->prm.n_mag > b->pipes[y]->prm.n_mag; });
+    b->nmag.resize(b->n);
+    for (int i = 0; i < b->n; ++i) b->nmag[i] = b->pipes[b->order[i]]->prm.n_mag;
+    b->max_nmag = b->nmag[0];
+    std::vector<BlockMap> map;
+    // sweep groups, one per tile form
+    b->groups.clear();
+    auto key = [](const SweepLaunch &L) { return L.pair ? 100 + L.ty : L.tx; };
+    for (int p : b->order) {
+        mhd_sim *s = b->pipes[p];
+        const SweepLaunch e = effective_tiles(s->sweep, s->g.nx);
+        BatchGroup *g = nullptr;
+        for (auto &x : b->groups)
+            if (key(x.L) == key(e)) g = &x;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->L = e;
+        }
+        g->pipes.push_back(p);
+        g->nmag.push_back(s->prm.n_mag);
+    }
+    for (auto &g : b->groups) {
+        g.map_base = (int64_t)map.size();
+        g.cum.assign(1, 0);
+        for (int p : g.pipes) {
+            mhd_sim *s = b->pipes[p];
+            const SweepArgs a = make_sweep_args(nullptr, nullptr, nullptr, nullptr, step_const(s),
+                                                effective_tiles(s->sweep, s->g.nx));
+            for (int lb = 0; lb < a.nblocks; ++lb) map.push_back({p, lb});
+            g.cum.push_back(g.cum.back() + a.nblocks);
+        }
+    }
+    auto add_list = [&](int64_t &base, std::vector<int64_t> &cum, auto count) {
+        base = (int64_t)map.size();
+        cum.assign(1, 0);
+        for (int p : b->order) {
+            const int64_t nb = blocks_of(count(b->pipes[p]), kIbThreads);
+            for (int64_t lb = 0; lb < nb; ++lb) map.push_back({p, (int)lb});
+            cum.push_back(cum.back() + nb);
+        }
+    };
+    add_list(b->interp_base, b->cum_interp, [](mhd_sim *s) { return s->M; });
+    add_list(b->spread_base, b->cum_spread, [](mhd_sim *s) { return s->M ? s->nband : 0; });
+    add_list(b->cell_base, b->cum_cells, [](mhd_sim *s) { return s->N; });
+    if ((int64_t)map.size() > b->L.map_cap)
+        return fail(MHD_ERR_OOM, "batch launch map needs %zu entries, %lld reserved", map.size(),
+                    (long long)b->L.map_cap);
+    for (int64_t v : b->cum_cells)
+        if (v >= ((int64_t)1 << 31)) return fail(MHD_ERR_INVALID_ARG, "batch too large for one launch");
+    b->any_flow = false;
+    for (auto *s : b->pipes) b->any_flow = b->any_flow || s->prm.flow_control;
+    HIPCHK(hipMemcpyAsync(b->map(), map.data(), map.size() * sizeof(BlockMap), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->plan_version = b->version;
+    return MHD_OK;
+}
+
+IbArgs ib_args(mhd_sim *s, const float *sj, const float *wall) {
+    IbArgs a;
+    a.N = s->N;
+    a.M = (int)s->M;
+    a.nband = (int)s->nband;
+    a.tm = s->tm;
+    a.km = s->km;
+    a.tap_cell = s->at<int>(s->L.tap_cell);
+    a.tap_w = s->at<float>(s->L.tap_w);
+    a.sj = sj;
+    a.wall = wall;
+    a.band_cell = s->at<int>(s->L.band_cell);
+    a.band_mk = s->at<int>(s->L.band_mk);
+    a.band_w = s->at<float>(s->L.band_w);
+    a.delta = s->at<float>(s->L.delta);
+    return a;
+}
+
+// Launch arguments of one box for its current buffer state (one fluid step).
+PipeStep pipe_step(mhd_sim *s) {
+    PipeStep q{};
+    const StepConst c = step_const(s);
+    const SweepLaunch e = effective_tiles(s->sweep, s->g.nx);
+    const float *bext = s->at<float>(s->L.bext);
+    const int cb = s->cb, cu = s->cu, cr = s->cr;
+    q.sw[0] = make_sweep_args(s->u(cu), s->b(cb), s->b(1 - cb), bext, c, e);
+    q.sw[1] = make_sweep_args(s->u(cu), s->b(1 - cb), s->b(cb), bext, c, e);
+    const IbArgs ab = ib_args(s, s->at<float>(s->L.s_b), s->at<float>(s->L.bwall));
+    q.ib[0] = ab;
+    q.ib[1] = ab;
+    q.ib[2] = ib_args(s, s->at<float>(s->L.s_u), s->at<float>(s->L.uwall));
+    q.phi[0] = s->b(1 - cb);
+    q.phi[1] = s->b(cb);
+    q.phi[2] = s->u(1 - cu);
+    q.scale[0] = q.scale[1] = c.b_scale;
+    q.inv_scale[0] = q.inv_scale[1] = c.inv_b_scale;
+    q.scale[2] = c.u_scale;
+    q.inv_scale[2] = c.inv_u_scale;
+    q.b_last = s->b((s->prm.n_mag & 1) ? 1 - cb : cb);
+    q.bext = bext;
+    q.ctrl = s->ctrl();
+    q.F = s->at<float>(s->L.F);
+    q.rho = s->rho(cr);
+    q.u = s->u(cu);
+    q.rho_o = s->rho(1 - cr);
+    q.u_o = s->u(1 - cu);
+    q.flow_part = s->at<double>(s->L.flow_part);
+    q.inv_count = s->flow_inv_count;
+    q.c = c;
+    return q;
+}
+
+std::vector<int> buffer_sig(const mhd_batch *b) {
+    std::vector<int> v(b->n);
+    for (int i = 0; i < b->n; ++i) v[i] = b->pipes[i]->cr | (b->pipes[i]->cu << 1) | (b->pipes[i]->cb << 2);
+    return v;
+}
+
+template <typename Fn>
+mhd_status timed_b(mhd_batch *b, int k, const char *what, Fn fn) {
+    Event2 *e = nullptr;
+    if (b->prof) {
+        if (b->ev_used[k] == b->ev_pool[k].size()) {
+            Event2 x;
+            HIPCHK(hipEventCreate(&x.a));
+            HIPCHK(hipEventCreate(&x.b));
+            b->ev_pool[k].push_back(x);
+        }
+        e = &b->ev_pool[k][b->ev_used[k]++];
+        HIPCHK(hipEventRecord(e->a, b->stream));
+    }
+    hipError_t err = fn();
+    if (err != hipSuccess) return fail(MHD_ERR_HIP, "batched launch of %s failed: %s", what, hipGetErrorString(err));
+    if (e) HIPCHK(hipEventRecord(e->b, b->stream));
+    return MHD_OK;
+}
+
+// The launch sequence of one fluid step of the whole batch, arguments from table slot k.
+mhd_status issue_step(mhd_batch *b, int k) {
+    hipStream_t st = b->stream;
+    const PipeStep *tab = b->tab(k);
+    const BlockMap *map = b->map();
+    const int n = b->n;
+    STEPCHK(timed_b(b, MHD_K_CONTROL, "ctrl_begin", [&] { return launch_ctrl_begin_batch(st, tab, n); }));
+    for (int r = 0; r < b->max_nmag; ++r) {
+        for (const auto &g : b->groups) {
+            const int64_t nb = g.cum[active_count(g.nmag, r)];
+            if (nb == 0) continue;
+            STEPCHK(timed_b(b, MHD_K_MAG_SWEEP, "mag_sweep", [&] {
+                return launch_mag_sweep_batch(st, b->kinds, g.L, tab, map + g.map_base, r & 1, (int)nb);
+            }));
+        }
+        const int a = active_count(b->nmag, r);
+        const int64_t ni = b->cum_interp[a], ns = b->cum_spread[a];
+        if (ni > 0)
+            STEPCHK(timed_b(b, MHD_K_IB, "wall correction", [&] {
+                hipError_t e = launch_ib_interp_batch(st, b->kind_b, tab, map + b->interp_base, r & 1, (int)ni);
+                if (e != hipSuccess) return e;
+                return launch_ib_spread_batch(st, b->kind_b, tab, map + b->spread_base, r & 1, (int)ns);
+            }));
+    }
+    const int nc = (int)b->cum_cells[n];
+    STEPCHK(timed_b(b, MHD_K_LORENTZ, "lorentz",
+                    [&] { return launch_lorentz_batch(st, b->kind_b, tab, map + b->cell_base, nc); }));
+    STEPCHK(timed_b(b, MHD_K_FLUID, "fluid",
+                    [&] { return launch_fluid_batch(st, b->kinds, tab, map + b->cell_base, nc); }));
+    const int64_t ni = b->cum_interp[n], ns = b->cum_spread[n];
+    if (ni > 0)
+        STEPCHK(timed_b(b, MHD_K_IB, "wall correction", [&] {
+            hipError_t e = launch_ib_interp_batch(st, b->kind_u, tab, map + b->interp_base, 2, (int)ni);
+            if (e != hipSuccess) return e;
+            return launch_ib_spread_batch(st, b->kind_u, tab, map + b->spread_base, 2, (int)ns);
+        }));
+    if (b->any_flow)
+        STEPCHK(timed_b(b, MHD_K_CONTROL, "flow_partial",
+                        [&] { return launch_flow_partial_batch(st, b->kind_u, tab, n); }));
+    STEPCHK(timed_b(b, MHD_K_CONTROL, "step_end", [&] { return launch_step_end_batch(st, tab, n); }));
+    return MHD_OK;
+}
+
+// Slot holding the launch tables of the current buffer state (uploaded on first use).
+mhd_status current_slot(mhd_batch *b, int *k_out) {
+    const std::vector<int> sig = buffer_sig(b);
+    for (int k = 0; k < 2; ++k) {
+        const BatchSlot &sl = b->slot[k];
+        if (sl.valid && sl.version == b->plan_version && sl.sig == sig) {
+            *k_out = k;
+            return MHD_OK;
+        }
+    }
+    const int k = b->next_slot;
+    b->next_slot ^= 1;
+    BatchSlot &sl = b->slot[k];
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+    sl.valid = false;
+    std::vector<PipeStep> tab(b->n);
+    for (int i = 0; i < b->n; ++i) tab[i] = pipe_step(b->pipes[i]);
+    HIPCHK(hipMemcpyAsync(b->tab(k), tab.data(), tab.size() * sizeof(PipeStep), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    sl.sig = sig;
+    sl.version = b->plan_version;
+    sl.valid = true;
+    *k_out = k;
+    return MHD_OK;
+}
+
+mhd_status capture_slot(mhd_batch *b, int k) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    const mhd_status st = issue_step(b, k);
+    const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (st != MHD_OK) {
+        if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(MHD_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(MHD_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    b->slot[k].exec = exec;
+    return MHD_OK;
+}
+
+// Time of `reps` batched sweep rounds over every box (round 0: reads b, writes the scratch copy,
+// so the state is unchanged) with the current tiles.
+mhd_status time_sweep_round(mhd_batch *b, int reps, hipEvent_t e0, hipEvent_t e1, float *ms) {
+    batch_touch(b);
+    STEPCHK(build_plan(b));
+    int k = 0;
+    STEPCHK(current_slot(b, &k));
+    auto round = [&]() -> hipError_t {
+        for (const auto &g : b->groups) {
+            hipError_t e = launch_mag_sweep_batch(b->stream, b->kinds, g.L, b->tab(k), b->map() + g.map_base, 0,
+                                                  (int)g.cum.back());
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    HIPCHK(round());  // warm-up
+    HIPCHK(hipEventRecord(e0, b->stream));
+    for (int r = 0; r < reps; ++r) HIPCHK(round());
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return MHD_OK;
+}
+
+// Autotuner: boxes are grouped by nx (the tile choice depends mostly on the row length); for
+// each group in turn every valid tile choice is tried with the other groups fixed, timing the
+// whole batched sweep round, and the fastest is kept. Two passes; it starts from the current
+// choice, so the result is never slower than that as measured.
+mhd_status tune_batch(mhd_batch *b, int reps, hipEvent_t e0, hipEvent_t e1) {
+    std::map<int, std::vector<int>> cls;
+    for (int i = 0; i < b->n; ++i) cls[b->pipes[i]->g.nx].push_back(i);
+    float best = 0.f;
+    STEPCHK(time_sweep_round(b, reps, e0, e1, &best));
+    for (int pass = 0; pass < 2; ++pass) {
+        for (auto &kv : cls) {
+            const int nx = kv.first;
+            int nz_max = 1;
+            for (int i : kv.second) nz_max = std::max(nz_max, b->pipes[i]->g.nz);
+            std::vector<SweepLaunch> cand;
+            for (int zc : {4, 8, 16}) {
+                if (zc > 2 * nz_max && zc != 4) continue;
+                if (nx % 128 == 0)
+                    for (int ty : {4, 8}) cand.push_back({64, ty, zc, 1});
+                for (int tx : {64, 32, 16, 8})
+                    if (tx <= std::max(8, nx)) cand.push_back({tx, 4, zc, 0});
+            }
+            const SweepLaunch keep = b->pipes[kv.second[0]]->sweep;
+            SweepLaunch best_L = keep;
+            for (const SweepLaunch &L : cand) {
+                for (int i : kv.second) b->pipes[i]->sweep = L;
+                float ms = 0.f;
+                STEPCHK(time_sweep_round(b, reps, e0, e1, &ms));
+                if (ms < best) {
+                    best = ms;
+                    best_L = L;
+                }
+            }
+            for (int i : kv.second) b->pipes[i]->sweep = best_L;
+        }
+    }
+    return MHD_OK;
+}
+
+void free_batch(mhd_batch *b) {
+    (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (int k = 0; k < MHD_K_COUNT; ++k)
+        for (auto &e : b->ev_pool[k]) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    for (auto *s : b->pipes) {
+        s->owner = nullptr;
+        (void)mhd_destroy(s);
+    }
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhd_status mhd_get_tiles(mhd_sim *s, int32_t tiles[4]) {
+    g_err.clear();
+    if (!s || !tiles) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    tiles[0] = s->sweep.tx;
+    tiles[1] = s->sweep.zchunk;
+    tiles[2] = s->sweep.pair;
+    tiles[3] = s->sweep.ty >= 8 ? 8 : 4;
+    return MHD_OK;
+}
+
+mhd_status mhd_set_tiles(mhd_sim *s, const int32_t tiles[4]) {
+    g_err.clear();
+    if (!s || !tiles) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (!valid_tx(tiles[0])) return fail(MHD_ERR_INVALID_ARG, "x tile %d not in {8, 16, 32, 64}", tiles[0]);
+    if (tiles[1] < 1) return fail(MHD_ERR_INVALID_ARG, "z chunk must be >= 1");
+    if (tiles[2] != 0 && tiles[2] != 1) return fail(MHD_ERR_INVALID_ARG, "paired form flag must be 0 or 1");
+    if (tiles[3] != 4 && tiles[3] != 8) return fail(MHD_ERR_INVALID_ARG, "rows of the paired form must be 4 or 8");
+    s->sweep.tx = tiles[0];
+    s->sweep.zchunk = tiles[1];
+    s->sweep.pair = tiles[2];
+    s->sweep.ty = tiles[3];
+    if (s->owner) batch_touch(s->owner);
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_workspace_size(const mhd_pipe_desc *pipes, int32_t n, size_t *bytes) {
+    g_err.clear();
+    STEPCHK(check_pipes(pipes, n));
+    if (!bytes) return fail(MHD_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = make_batch_layout(pipes, n).total;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_create(const mhd_pipe_desc *pipes, int32_t n, void *dev_workspace, size_t bytes,
+                            void *hip_stream, mhd_batch **out) {
+    g_err.clear();
+    if (!out) return fail(MHD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    STEPCHK(check_pipes(pipes, n));
+    if (!dev_workspace) return fail(MHD_ERR_INVALID_ARG, "device workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return fail(MHD_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    const BatchLayout L = make_batch_layout(pipes, n);
+    if (bytes < L.total) return fail(MHD_ERR_OOM, "workspace has %zu bytes, %zu needed", bytes, L.total);
+    mhd_batch *b = new (std::nothrow) mhd_batch();
+    if (!b) return fail(MHD_ERR_OOM, "host allocation failed");
+    b->n = n;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->ws = static_cast<char *>(dev_workspace);
+    b->L = L;
+    b->graph = b->stream != nullptr;
+    const mhd_grid_desc &g0 = pipes[0].grid;
+    b->kinds = pack_kinds(g0.rho_storage, g0.u_storage, g0.b_storage);
+    b->kind_u = g0.u_storage;
+    b->kind_b = g0.b_storage;
+    for (int i = 0; i < n; ++i) {
+        mhd_sim *s = nullptr;
+        const mhd_status st = mhd_create(&pipes[i].grid, pipes[i].n_markers, b->ws + L.pipe[i], L.pipe_bytes[i],
+                                         hip_stream, &s);
+        if (st != MHD_OK) {
+            const std::string msg = g_err;
+            free_batch(b);
+            return fail(st, "pipe %d: %s", i, msg.c_str());
+        }
+        s->owner = b;
+        b->pipes.push_back(s);
+    }
+    *out = b;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_pipe(mhd_batch *b, int32_t i, mhd_sim **out) {
+    g_err.clear();
+    if (!b || !out) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (i < 0 || i >= b->n) return fail(MHD_ERR_INVALID_ARG, "pipe %d outside [0, %d)", i, b->n);
+    *out = b->pipes[i];
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_tune(mhd_batch *b, int32_t reps) {
+    g_err.clear();
+    if (!b) return fail(MHD_ERR_INVALID_ARG, "batch is NULL");
+    if (reps <= 0) reps = 5;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->pipes[i]->have_params) return fail(MHD_ERR_STATE, "pipe %d has no parameters (mhd_set_params)", i);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    mhd_status st = tune_batch(b, reps, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    batch_touch(b);
+    return st;
+}
+
+mhd_status mhd_batch_step(mhd_batch *b, int64_t n_steps, int32_t budget_every) {
+    g_err.clear();
+    if (!b) return fail(MHD_ERR_INVALID_ARG, "batch is NULL");
+    if (n_steps < 0) return fail(MHD_ERR_INVALID_ARG, "n_steps < 0");
+    if (n_steps == 0) return MHD_OK;
+    if (b->plan_version != b->version) STEPCHK(build_plan(b));
+    const bool use_graph = b->graph && !b->prof && b->stream != nullptr;
+    for (int64_t i = 0; i < n_steps; ++i) {
+        int k = 0;
+        STEPCHK(current_slot(b, &k));
+        if (use_graph) {
+            if (!b->slot[k].exec) STEPCHK(capture_slot(b, k));
+            HIPCHK(hipGraphLaunch(b->slot[k].exec, b->stream));
+        } else {
+            STEPCHK(issue_step(b, k));
+        }
+        for (auto *s : b->pipes) {
+            if (s->prm.n_mag & 1) s->cb = 1 - s->cb;
+            s->cr = 1 - s->cr;
+            s->cu = 1 - s->cu;
+            s->t_host += 1;
+        }
+        if (budget_every > 0)
+            for (auto *s : b->pipes)
+                if (s->t_host % budget_every == 0) STEPCHK(record_budget(s));
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_set_graph(mhd_batch *b, int32_t enable) {
+    g_err.clear();
+    if (!b) return fail(MHD_ERR_INVALID_ARG, "batch is NULL");
+    if (enable && !b->stream) return fail(MHD_ERR_INVALID_ARG, "graphs need a non-NULL stream");
+    b->graph = enable != 0;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_set_profiling(mhd_batch *b, int32_t enable) {
+    g_err.clear();
+    if (!b) return fail(MHD_ERR_INVALID_ARG, "batch is NULL");
+    b->prof = enable != 0;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_kernel_stats(mhd_batch *b, int32_t kernel, int64_t *launches, double *total_ms) {
+    g_err.clear();
+    if (!b || !launches || !total_ms) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (kernel < 0 || kernel >= MHD_K_COUNT) return fail(MHD_ERR_INVALID_ARG, "unknown kernel id %d", kernel);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < b->ev_used[kernel]; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev_pool[kernel][i].a, b->ev_pool[kernel][i].b));
+        tot += ms;
+    }
+    *launches = (int64_t)b->ev_used[kernel];
+    *total_ms = tot;
+    b->ev_used[kernel] = 0;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_destroy(mhd_batch *b) {
+    g_err.clear();
+    if (!b) return MHD_OK;
+    free_batch(b);
     return MHD_OK;
 }
 

@@ -71,3 +71,44 @@ def test_create_rejects_missing_workspace_without_touching_a_gpu():
     h = C.c_void_p()
     st = _abi.lib().mhd_create(C.byref(_desc()), 0, None, 0, None, C.byref(h))
     assert st == _abi.MHD_ERR_INVALID_ARG and not h.value
+
+
+def _pipe(nx=8, ny=32, nz=32, m=0, **kw):
+    return _abi.mhd_pipe_desc(_desc(nx, ny, nz, **kw), m)
+
+
+def test_pipe_desc_layout():
+    assert C.sizeof(_abi.mhd_pipe_desc) == C.sizeof(_abi.mhd_grid_desc) + 8
+
+
+def test_batch_workspace_covers_its_boxes():
+    pipes = [_pipe(8, 32, 32, 704), _pipe(128, 20, 20, 5632), _pipe(37, 21, 13, 0)]
+    total = pkg.mhd_batch_workspace_size(pipes)
+    singles = sum(mhd_workspace_size(p.grid, p.n_markers) for p in pipes)
+    assert total > singles
+    assert pkg.mhd_batch_workspace_size(pipes[:1]) < total
+
+
+@pytest.mark.parametrize("pipes,status", [
+    ([], _abi.MHD_ERR_INVALID_ARG),
+    ([_pipe(), _pipe(r=1, u=1, b=1, us=0.05, bs=1.0)], _abi.MHD_ERR_UNSUPPORTED),
+    ([_pipe(), _pipe(nx=0)], _abi.MHD_ERR_INVALID_ARG),
+    ([_pipe(m=-1)], _abi.MHD_ERR_INVALID_ARG),
+])
+def test_batch_workspace_rejects_bad_pipes(pipes, status):
+    with pytest.raises(MhdError) as e:
+        pkg.mhd_batch_workspace_size(pipes)
+    assert e.value.status == status
+
+
+def test_batch_create_rejects_missing_workspace_without_touching_a_gpu():
+    arr = (_abi.mhd_pipe_desc * 1)(_pipe())
+    h = C.c_void_p()
+    st = _abi.lib().mhd_batch_create(arr, 1, None, 0, None, C.byref(h))
+    assert st == _abi.MHD_ERR_INVALID_ARG and not h.value
+
+
+def test_tile_calls_reject_null_sim():
+    t = (C.c_int32 * 4)(64, 8, 0, 4)
+    assert _abi.lib().mhd_set_tiles(None, t) == _abi.MHD_ERR_INVALID_ARG
+    assert _abi.lib().mhd_get_tiles(None, t) == _abi.MHD_ERR_INVALID_ARG

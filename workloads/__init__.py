@@ -175,3 +175,48 @@ def large_pipe(Rm=1e-2, **kw) -> Workload:
     """512 x 256 x 256 box, R = 120, 754 markers per plane, uniform B0, Ha = 30, Re = 5000."""
     return pipe_workload(f"pipe512x256x256_R120_Ha30_Rm{Rm:g}", 5, 512, 256, 256, 120.0, 5000.0,
                          30.0, Rm, **kw)
+
+
+def batch_pipes(n: int = 64, key: int = 4, R_range=(16.0, 64.0), lengths=(32, 64, 128, 256),
+                Ha_range=(1.0, 50.0), Rm_range=(1e-4, 1.0), Re_range=(50.0, 1000.0),
+                noise: float = 1e-4, n_mag_cap: int = 270):
+    """Independent pipes of uneven size and physics for the batched form.
+
+    Pipe i: R ~ U(R_range), length L drawn from `lengths`, box L x (2 ceil(R) + 4)^2 with the axis
+    at the box centre, markers L * round(2 pi R); Ha and Rm log-uniform, Re uniform, mapped to
+    (nu, eta, B0) with L = R, U = U0; n_mag = min(ceil(6 eta), cap); the imposed field is uniform
+    or (probability 1/2) a tanh fringe centred at L/2 with width 8. The fields are not generated
+    here (a 64-pipe batch holds ~60 M cells): `batch_fields(w)` gives rho = 1, u ~ U(+-noise),
+    b = 0 for one of them.
+    """
+    g = rng_for(key)
+    out = []
+    for i in range(n):
+        R = float(g.uniform(*R_range))
+        L = int(g.choice(lengths))
+        Ha = float(math.exp(g.uniform(math.log(Ha_range[0]), math.log(Ha_range[1]))))
+        Rm = float(math.exp(g.uniform(math.log(Rm_range[0]), math.log(Rm_range[1]))))
+        Re = float(g.uniform(*Re_range))
+        fringe = bool(g.uniform() < 0.5)
+        field_seed = int(g.integers(0, 2**62))
+        side = 2 * int(math.ceil(R)) + 4
+        nu, eta, B0 = map_params(Re, Ha, Rm, R)
+        yc = zc = side // 2
+        p = Params(nu=nu, eta=eta, n_mag=n_mag_for(eta, n_mag_cap), G0=poiseuille_G(nu, R),
+                   bext_kind=BEXT_TANH_FRINGE_Y if fringe else BEXT_UNIFORM_Y, B0=B0,
+                   fringe_x0=L / 2.0, fringe_w=8.0, yc=float(yc), zc=float(zc), avg_radius=R,
+                   u_bulk_target=U0)
+        X = pipe_markers(L, R, yc, zc)
+        w = Workload(f"batch{i}_L{L}_R{R:.1f}_Ha{Ha:.2g}_Rm{Rm:.2g}_Re{Re:.0f}", L, side, side, R,
+                     p, X, None, None, None)
+        w.field_seed = field_seed
+        w.noise = noise
+        out.append(w)
+    return out
+
+
+def batch_fields(w: Workload):
+    """(rho, u, b) of a pipe from `batch_pipes`: rho = 1, u ~ U(+-noise) per component, b = 0."""
+    g = np.random.default_rng(w.field_seed)
+    u = g.uniform(-w.noise, w.noise, size=(3, w.nz, w.ny, w.nx))
+    return np.ones((w.nz, w.ny, w.nx)), u, np.zeros((3, w.nz, w.ny, w.nx))

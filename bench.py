@@ -10,8 +10,15 @@ value = MLUPS = box cells x fluid steps / wall time / 1e6 (inputs resident in HB
 roofline = the magnetic sweep kernel (the dominant one): 36 algorithmic bytes per cell
 (read u and b, write b*, float32) per launch over its HIP-event-timed average duration.
 cpu_baseline = the FP64 oracle on this host, timed on a bounded sample of the same workload.
+batched = the batched form on 64 independent pipes of uneven size and physics (~74 M cells,
+~2.3 M markers, tiles autotuned), MLUPS over all their cells (an extra object, not `value`).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+HBM traffic of the sweep (rocprofv3 counters, scaled by a plain copy of known size):
+  rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --steps 1 \
+      --warmup 0 --profile-steps 1 --no-cpu --no-batch --calib-copy-mib 1024
+  (the same with WRITE_SIZE into D2), then
+  python3 bench.py --traffic-summary D1 D2 --calib-copy-mib 1024
 """
 import argparse
 import hashlib
@@ -26,7 +33,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 36  # read u (12 B) + b (12 B), write b* (12 B), float32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mag_sweep_fringe128_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2211_09370_amd", "csrc", "mhd_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2211_09370_amd", "csrc", "mhd_sweep.hip")
 
 
 def log(*a):
@@ -53,6 +60,102 @@ def read_traffic():
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _counter_rows(d, counter):
+    """(kernel name, value) of every dispatch in the rocprofv3 counter CSVs under directory d."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_summary(fetch_dir, write_dir, copy_mib):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep, scaled by what the same
+    counters read for a plain copy of copy_mib MiB (the largest torch copy dispatch), written to
+    the traffic file together with the hash of the kernel source they were taken on."""
+    out = {}
+    for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _counter_rows(d, counter)
+        sweep = [v for k, v in rows if "k_mag_sweep" in k]
+        copy = [v for k, v in rows if ("copy" in k.lower() or "elementwise" in k.lower())]
+        if not sweep or not copy:
+            raise SystemExit(f"no sweep or copy dispatches with {counter} under {d}")
+        expect_kib = copy_mib * 1024.0
+        scale = expect_kib / max(copy)
+        out[tag] = dict(raw_kib=sum(sweep) / len(sweep), n=len(sweep), copy_kib=max(copy), scale=scale)
+    fetch_b = out["fetch"]["raw_kib"] * out["fetch"]["scale"] * 1024.0
+    write_b = out["write"]["raw_kib"] * out["write"]["scale"] * 1024.0
+    import workloads as W
+
+    w = W.fringe_pipe()
+    alg = SWEEP_BYTES_PER_CELL * w.n_cells
+    lines = [
+        "# HBM-side traffic of the magnetic sweep on the 128^3 fringe pipe (float32), per launch.",
+        "# rocprofv3 --pmc FETCH_SIZE / --pmc WRITE_SIZE (KiB per dispatch, averaged over the sweep",
+        "# dispatches), each scaled by the ratio of the known size of a plain torch copy to what the",
+        "# same counter reads for it. Commands:",
+        f"#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --steps 1 "
+        f"--warmup 0 --profile-steps 1 --no-cpu --no-batch --calib-copy-mib {copy_mib}",
+        "#   (the same with --pmc WRITE_SIZE into D2)",
+        f"#   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib {copy_mib}",
+        f"fetch_kib_raw = {out['fetch']['raw_kib']:.1f}",
+        f"fetch_dispatches = {out['fetch']['n']}",
+        f"copy_fetch_kib_raw = {out['fetch']['copy_kib']:.1f}",
+        f"fetch_scale = {out['fetch']['scale']:.4f}",
+        f"write_kib_raw = {out['write']['raw_kib']:.1f}",
+        f"write_dispatches = {out['write']['n']}",
+        f"copy_write_kib_raw = {out['write']['copy_kib']:.1f}",
+        f"write_scale = {out['write']['scale']:.4f}",
+        f"algorithmic_bytes_per_launch = {alg}",
+        f"hbm_bytes_per_launch = {fetch_b + write_b:.0f}",
+        f"traffic_over_algorithmic = {(fetch_b + write_b) / alg:.4f}",
+        f"kernel_source_sha256_16 = {kernel_hash()}",
+    ]
+    open(TRAFFIC_FILE, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def batched_leg(steps):
+    """The batched form on 64 seeded pipes: autotuned tiles, graph replay, MLUPS over all cells."""
+    import torch
+
+    import workloads as W
+    from paper_2211_09370_amd import MHD_K_MAG_SWEEP, Batch
+
+    ps = W.batch_pipes()
+    cells = sum(w.n_cells for w in ps)
+    sweep_cells = sum(w.n_cells * w.params.n_mag for w in ps)
+    markers = sum(w.markers.shape[1] for w in ps)
+    B = Batch([(w.nx, w.ny, w.nz, w.markers.shape[1]) for w in ps])
+    for p, w in zip(B.pipes, ps):
+        p.set_markers(w.markers)
+        p.set_params(w.params)
+        p.set_field("u", W.batch_fields(w)[1])
+    B.tune(3)
+    B.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    B.set_profiling(True)
+    B.step(1)
+    n, ms = B.kernel_stats(MHD_K_MAG_SWEEP)
+    B.set_profiling(False)
+    B.close()
+    log(f"bench: batched {len(ps)} pipes, {steps} steps in {sec:.3f} s")
+    return {"workload": f"{len(ps)} pipes, R U[16,64], L in {{32,64,128,256}}, Ha log-U[1,50], "
+                        f"Rm log-U[1e-4,1], Re U[50,1000], uniform or fringe field",
+            "value": round(cells * steps / sec / 1e6, 3), "unit": "MLUPS", "steps": steps,
+            "ms_per_step": round(sec * 1e3 / steps, 3), "cells": cells, "markers": markers,
+            "sweep_cells_per_step": sweep_cells, "graph": True, "tiles": "autotuned",
+            "sweep_alg_GBs": round(SWEEP_BYTES_PER_CELL * sweep_cells / (ms * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(w):
@@ -88,7 +191,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--calib-copy-mib", type=int, default=0)
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.calib_copy_mib or 1024)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
               "the multi-GPU axial slab design is described but not built", file=sys.stderr)
@@ -100,6 +210,15 @@ def main():
     from paper_2211_09370_amd import MHD_K_MAG_SWEEP, Sim
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:  # plain copy of known size, for counter calibration
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     w = W.fringe_pipe()
     M = w.markers.shape[1]
     log(f"bench: {w.name} N={w.n_cells} M={M} n_mag={w.params.n_mag}")
@@ -143,6 +262,10 @@ def main():
     state_ok = bool(np.isfinite(sim.get_field("u")).all())
     sim.close()
 
+    batched = None
+    if not args.no_batch:
+        batched = batched_leg(args.batch_steps)
+
     cpu = None
     if not args.no_cpu:
         log("bench: timing the oracle on the host")
@@ -170,6 +293,7 @@ def main():
                      "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes},
         "sweep_glups": round(w.n_cells * (w.params.n_mag + 1) * args.steps / sec / 1e9, 3),
         "finite": state_ok,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -61,8 +61,10 @@ SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *b
 hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c);
 hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part, StepConst c,
                            double inv_count);
+// e0 / e1 (optional): events stamped at the start and end of the sweep kernel itself.
 hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo,
-                            const float *bext, StepConst c, SweepLaunch L);
+                            const float *bext, StepConst c, SweepLaunch L, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
 // Wall correction data (device pointers), markers in the library's internal order.
 struct IbArgs {
     int64_t N;
@@ -113,7 +115,7 @@ struct BlockMap {             // (box, workgroup within the box) of workgroup i 
 hipError_t launch_ctrl_begin_batch(hipStream_t s, const PipeStep *tab, int n);
 hipError_t launch_step_end_batch(hipStream_t s, const PipeStep *tab, int n);
 hipError_t launch_mag_sweep_batch(hipStream_t s, int kinds, SweepLaunch L, const PipeStep *tab, const BlockMap *map,
-                                  int parity, int nblocks);
+                                  int parity, int nblocks, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_ib_interp_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,
                                   int nblocks);
 hipError_t launch_ib_spread_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,

@@ -323,10 +323,13 @@ mhd_status one_step(mhd_sim *s) {
     // 1. magnetic iteration, wall correction after every sweep
     for (int m = 0; m < s->prm.n_mag; ++m) {
         const int nb = 1 - s->cb;
-        STEPCHK(timed(s, MHD_K_MAG_SWEEP, "mag_sweep", [&] {
-            return launch_mag_sweep(st, s->kinds, s->u(s->cu), s->b(s->cb), s->b(nb), s->at<float>(s->L.bext), c,
-                                    s->sweep);
-        }));
+        {  // timed by events the launch stamps at kernel start / end
+            Event2 *e = s->prof ? &next_event(s, MHD_K_MAG_SWEEP) : nullptr;
+            const hipError_t err = launch_mag_sweep(st, s->kinds, s->u(s->cu), s->b(s->cb), s->b(nb),
+                                                    s->at<float>(s->L.bext), c, s->sweep, e ? e->a : nullptr,
+                                                    e ? e->b : nullptr);
+            if (err != hipSuccess) return fail(MHD_ERR_HIP, "launch of mag_sweep failed: %s", hipGetErrorString(err));
+        }
         STEPCHK(ib_correct(s, s->g.b_storage, s->b(nb), c.b_scale, c.inv_b_scale, s->at<float>(s->L.s_b),
                            s->at<float>(s->L.bwall)));
         s->cb = nb;
@@ -1033,17 +1036,21 @@ std::vector<int> buffer_sig(const mhd_batch *b) {
     return v;
 }
 
+Event2 *next_event_b(mhd_batch *b, int k) {
+    if (b->ev_used[k] == b->ev_pool[k].size()) {
+        Event2 x;
+        if (hipEventCreate(&x.a) != hipSuccess || hipEventCreate(&x.b) != hipSuccess) return nullptr;
+        b->ev_pool[k].push_back(x);
+    }
+    return &b->ev_pool[k][b->ev_used[k]++];
+}
+
 template <typename Fn>
 mhd_status timed_b(mhd_batch *b, int k, const char *what, Fn fn) {
     Event2 *e = nullptr;
     if (b->prof) {
-        if (b->ev_used[k] == b->ev_pool[k].size()) {
-            Event2 x;
-            HIPCHK(hipEventCreate(&x.a));
-            HIPCHK(hipEventCreate(&x.b));
-            b->ev_pool[k].push_back(x);
-        }
-        e = &b->ev_pool[k][b->ev_used[k]++];
+        e = next_event_b(b, k);
+        if (!e) return fail(MHD_ERR_HIP, "hipEventCreate failed");
         HIPCHK(hipEventRecord(e->a, b->stream));
     }
     hipError_t err = fn();
@@ -1063,9 +1070,11 @@ mhd_status issue_step(mhd_batch *b, int k) {
         for (const auto &g : b->groups) {
             const int64_t nb = g.cum[active_count(g.nmag, r)];
             if (nb == 0) continue;
-            STEPCHK(timed_b(b, MHD_K_MAG_SWEEP, "mag_sweep", [&] {
-                return launch_mag_sweep_batch(st, b->kinds, g.L, tab, map + g.map_base, r & 1, (int)nb);
-            }));
+            Event2 *e = nullptr;
+            if (b->prof && !(e = next_event_b(b, MHD_K_MAG_SWEEP))) return fail(MHD_ERR_HIP, "hipEventCreate failed");
+            const hipError_t err = launch_mag_sweep_batch(st, b->kinds, g.L, tab, map + g.map_base, r & 1, (int)nb,
+                                                          e ? e->a : nullptr, e ? e->b : nullptr);
+            if (err != hipSuccess) return fail(MHD_ERR_HIP, "batched launch of mag_sweep failed: %s", hipGetErrorString(err));
         }
         const int a = active_count(b->nmag, r);
         const int64_t ni = b->cum_interp[a], ns = b->cum_spread[a];

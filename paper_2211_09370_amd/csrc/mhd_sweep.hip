@@ -1,0 +1,627 @@
+// gfx950 magnetic sweep of the quasi-static induction iteration (arXiv:2211.09370, Sec. 5.7):
+// the single-cell-per-lane and paired (two x cells per lane) plane-marching kernels, each in a
+// single-box and a batched instantiation, and their host-side launchers.
+#include <hip/hip_ext.h>
+
+#include <type_traits>
+
+#include "mhd_device.h"
+
+namespace mhd {
+
+// -------------------------------------------------------------------------------------------
+// Magnetic sweep (Sec. 5.7): tau_m = 1, particle speed c = 6 eta, so c_i / c_s^2 = e_i / (2 eta).
+//
+//   b*_a(x) = sum_i w_i [ b_a(x - e_i) + kappa sum_c e_ic Lam_ac(x - e_i) ],
+//   Lam_ac = u_c B_a - u_a B_c,  B = B_ext + b,  kappa = 1 / (2 eta).
+//
+// Written per plane: a workgroup owns a TX x TY column of cells and marches along z over a
+// chunk of planes. Each new plane (with a one-cell x/y halo) is staged in LDS as
+// (b_x, b_y, b_z, kappa Lam_xy, kappa Lam_xz, kappa Lam_yz); every thread forms from its 3x3
+// in-plane neighbourhood the plane's contributions to the outputs at z-1, z and z+1
+// (A, B, C below) and keeps the running sums in registers, so each field value is read from
+// memory once per plane and every neighbour access is an LDS read.
+//
+// With D_c[f](x) = sum_i w_i e_ic f(x - e_i) and the in-plane sums
+//   P0 = c/3 + (faces)/18 + (corners)/36,  P1 = c/18 + (faces)/36,
+//   Q0x = (xm - xp)/18 + (mm + mp - pm - pp)/36,  Q1x = (xm - xp)/36   (Q*y likewise in y),
+// one has avg[f](z) = P0(z) + P1(z-1) + P1(z+1), D_x[f](z) = Q0x(z) + Q1x(z-1) + Q1x(z+1),
+// D_y likewise and D_z[f](z) = P1(z-1) - P1(z+1); then
+//   b*_x = avg b_x + D_y Lxy + D_z Lxz,  b*_y = avg b_y - D_x Lxy + D_z Lyz,
+//   b*_z = avg b_z - D_x Lxz - D_y Lyz.
+// -------------------------------------------------------------------------------------------
+template <int TX, int TY, typename TU, typename TB, bool BATCH>
+__global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeStep *tab, const BlockMap *map,
+                                                      int parity, int nbatch) {
+    constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    constexpr int NSLOT = (HN + NT - 1) / NT;
+    // two LDS planes: the next plane is staged while the current one is reduced
+    __shared__ float s_pl[2][6][HN];
+
+    // XCD-aware order: the hardware hands consecutive workgroups to the 8 XCDs in turn; give
+    // each XCD a contiguous run of tiles so neighbouring tiles share halo rows in one L2.
+    const int per = gridDim.x >> 3;
+    int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if constexpr (BATCH) {
+        if (lb >= nbatch) return;
+        const BlockMap m = map[lb];
+        a = tab[m.pipe].sw[parity];
+        lb = m.local;
+    } else {
+        if (lb >= a.nblocks) return;
+    }
+    const int tix = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int tiy = rest % a.tiles_y;
+    const int tiz = rest / a.tiles_y;
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int z0 = tiz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned N = (unsigned)nx * ny * nz;  // 3 N < 2^31: 32-bit offsets from uniform bases
+    const unsigned plane = (unsigned)nx * ny;
+
+    const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * (size_t)N;
+    const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * (size_t)N;
+    TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * (size_t)N;
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool own = gx < nx && gy < ny;
+
+    // halo slots handled by this thread: fixed (x, y) for the whole march
+    unsigned sxy[NSLOT];
+    float sbe[NSLOT][3];
+    bool sval[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int i = tid + s * NT;
+        sval[s] = i < HN;
+        const int hx = i % HX, hy = i / HX;
+        const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
+        sxy[s] = (unsigned)(hxg + nx * hyg);
+        sbe[s][0] = sval[s] ? a.bext[hxg] : 0.f;
+        sbe[s][1] = sval[s] ? a.bext[nx + hxg] : 0.f;
+        sbe[s][2] = sval[s] ? a.bext[2 * nx + hxg] : 0.f;
+    }
+
+    // raw stored values of the next plane: converted only when they are written to LDS, so the
+    // loads stay in flight while the current plane is reduced
+    TU ru[NSLOT][3];
+    TB rb[NSLOT][3];
+    auto load_plane = [&](int p) {
+        const unsigned off = (unsigned)wrapi(p, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (sval[s]) {
+                const unsigned ku = (off + sxy[s]) * (unsigned)sizeof(TU);
+                const unsigned kb = (off + sxy[s]) * (unsigned)sizeof(TB);
+                ru[s][0] = ld_off(u0, ku);
+                ru[s][1] = ld_off(u1, ku);
+                ru[s][2] = ld_off(u2, ku);
+                rb[s][0] = ld_off(b0, kb);
+                rb[s][1] = ld_off(b1, kb);
+                rb[s][2] = ld_off(b2, kb);
+            }
+        }
+    };
+
+    const int c0 = (ly + 1) * HX + (lx + 1);
+    const float kap = a.kappa;
+    constexpr float W6 = 1.0f / 6.0f;  // WF + 4 WE: weight of a neighbouring plane as a whole
+    // running sums of the plane contributions (difference form), and the column's own values
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    float ap0 = 0.f, ap1 = 0.f, ap2 = 0.f;
+    float cm0 = 0.f, cm1 = 0.f, cm2 = 0.f;  // b at (x, y, z-1)
+    float cc0 = 0.f, cc1 = 0.f, cc2 = 0.f;  // b at (x, y, z)
+
+    // stage the raw values in the registers into LDS buffer S as (b, kappa Lam)
+    auto stage = [&](auto buf) {
+        constexpr int S = decltype(buf)::value;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            if (sval[s]) {
+                const int i = tid + s * NT;
+                const float bx = St<TB>::val(rb[s][0], a.b_scale);
+                const float by = St<TB>::val(rb[s][1], a.b_scale);
+                const float bz = St<TB>::val(rb[s][2], a.b_scale);
+                const float Bx = bx + sbe[s][0];
+                const float By = by + sbe[s][1];
+                const float Bz = bz + sbe[s][2];
+                const float ux = St<TU>::val(ru[s][0], a.u_scale);
+                const float uy = St<TU>::val(ru[s][1], a.u_scale);
+                const float uz = St<TU>::val(ru[s][2], a.u_scale);
+                s_pl[S][0][i] = bx;
+                s_pl[S][1][i] = by;
+                s_pl[S][2][i] = bz;
+                s_pl[S][3][i] = kap * (uy * Bx - ux * By);
+                s_pl[S][4][i] = kap * (uz * Bx - ux * Bz);
+                s_pl[S][5][i] = kap * (uz * By - uy * Bz);
+            }
+        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+
+    // plane r = p - (z0 - 1) is reduced from LDS buffer r % 2; while it is, the next plane is
+    // staged into the other buffer and the one after that is requested into the registers
+    load_plane(z0 - 1);
+    stage(I0{});
+    load_plane(z0);
+    __syncthreads();
+    auto body = [&](auto par, int p) {
+        constexpr int P = decltype(par)::value;  // parity of plane p
+        using Q = std::integral_constant<int, 1 - P>;
+        // plane p+1 goes from the registers to the other LDS buffer (its last readers passed
+        // the previous barrier); the registers then request plane p+2
+        if (p < z1) {
+            stage(Q{});
+            if (p + 2 <= z1) load_plane(p + 2);
+        }
+        const int cur = P;
+        const float *s_bx = s_pl[cur][0], *s_by = s_pl[cur][1], *s_bz = s_pl[cur][2];
+        const float *s_lxy = s_pl[cur][3], *s_lxz = s_pl[cur][4], *s_lyz = s_pl[cur][5];
+        if (own) {
+            // b components: centre value and in-plane sums of differences to it
+            //   dP0 = sum_faces WF (f - c) + sum_corners WE (f - c),  dP1 = sum_faces WE (f - c)
+            float c_x, c_y, c_z, dP0x, dP1x, dP0y, dP1y, dP0z, dP1z;
+#define MHD_PLANE_DIFFS(F, C, DP0, DP1)                                                              \
+    {                                                                                                \
+        const float *f = F;                                                                          \
+        C = f[c0];                                                                                   \
+        const float fs = ((f[c0 - 1] - C) + (f[c0 + 1] - C)) + ((f[c0 - HX] - C) + (f[c0 + HX] - C)); \
+        const float cs = ((f[c0 - HX - 1] - C) + (f[c0 - HX + 1] - C)) +                              \
+                         ((f[c0 + HX - 1] - C) + (f[c0 + HX + 1] - C));                               \
+        DP0 = WF * fs + WE * cs;                                                                     \
+        DP1 = WE * fs;                                                                               \
+    }
+            MHD_PLANE_DIFFS(s_bx, c_x, dP0x, dP1x)
+            MHD_PLANE_DIFFS(s_by, c_y, dP0y, dP1y)
+            MHD_PLANE_DIFFS(s_bz, c_z, dP0z, dP1z)
+            // kappa Lam_xy: Q0x, Q1x, Q0y, Q1y (differences across the cell)
+            float Q0xA, Q1xA, Q0yA, Q1yA;
+            {
+                const float *f = s_lxy;
+                const float dx = f[c0 - 1] - f[c0 + 1], dy = f[c0 - HX] - f[c0 + HX];
+                const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
+                Q0xA = WF * dx + WE * ((mm - pm) + (mp - pp));
+                Q1xA = WE * dx;
+                Q0yA = WF * dy + WE * ((mm - mp) + (pm - pp));
+                Q1yA = WE * dy;
+            }
+            // kappa Lam_xz: P1, Q0x, Q1x and kappa Lam_yz: P1, Q0y, Q1y. These flux terms are
+            // of order b / R, so plain weighted sums keep their rounding below that of b.
+            float P1B, Q0xB, Q1xB;
+            {
+                const float *f = s_lxz;
+                const float xm = f[c0 - 1], xp = f[c0 + 1];
+                const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
+                P1B = WF * f[c0] + WE * ((xm + xp) + (f[c0 - HX] + f[c0 + HX]));
+                Q0xB = WF * (xm - xp) + WE * ((mm - pm) + (mp - pp));
+                Q1xB = WE * (xm - xp);
+            }
+            float P1C, Q0yC, Q1yC;
+            {
+                const float *f = s_lyz;
+                const float ym = f[c0 - HX], yp = f[c0 + HX];
+                const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
+                P1C = WF * f[c0] + WE * ((f[c0 - 1] + f[c0 + 1]) + (ym + yp));
+                Q0yC = WF * (ym - yp) + WE * ((mm - mp) + (pm - pp));
+                Q1yC = WE * (ym - yp);
+            }
+            // contributions of this plane to the outputs at z+1 (A), z (B), z-1 (C)
+            const float A0 = dP1x + Q1yA + P1B, B0 = dP0x + Q0yA, C0 = dP1x + Q1yA - P1B;
+            const float A1 = dP1y - Q1xA + P1C, B1 = dP0y - Q0xA, C1 = dP1y - Q1xA - P1C;
+            const float A2 = dP1z - Q1xB - Q1yC, B2 = dP0z - Q0xB - Q0yC;
+            if (p >= z0 + 1) {
+                // output plane p-1: b* = b_c + increment, the increment built from differences
+                const float d0 = (acc0 + C0) + W6 * ((cm0 - cc0) + (c_x - cc0));
+                const float d1 = (acc1 + C1) + W6 * ((cm1 - cc1) + (c_y - cc1));
+                const float d2 = (acc2 + A2) + W6 * ((cm2 - cc2) + (c_z - cc2));
+                const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(gx + nx * gy)) * (unsigned)sizeof(TB);
+                st_off(o0, k, St<TB>::from(cc0 + d0, a.inv_b_scale));
+                st_off(o1, k, St<TB>::from(cc1 + d1, a.inv_b_scale));
+                st_off(o2, k, St<TB>::from(cc2 + d2, a.inv_b_scale));
+            }
+            acc0 = ap0 + B0;
+            acc1 = ap1 + B1;
+            acc2 = ap2 + B2;
+            ap0 = A0;
+            ap1 = A1;
+            ap2 = A2;
+            cm0 = cc0;
+            cm1 = cc1;
+            cm2 = cc2;
+            cc0 = c_x;
+            cc1 = c_y;
+            cc2 = c_z;
+        }
+        __syncthreads();  // plane p+1 is staged; buffer `cur` may be overwritten next
+    };
+    for (int p = z0 - 1; p <= z1; p += 2) {
+        body(I0{}, p);
+        if (p + 1 <= z1) body(I1{}, p + 1);
+    }
+#undef MHD_PLANE_DIFFS
+}
+
+// -------------------------------------------------------------------------------------------
+// Paired magnetic sweep for boxes with n_x a multiple of 128: the same plane march and the same
+// per-cell arithmetic as k_mag_sweep, but every lane owns two neighbouring x cells, so a wave
+// covers a 128-cell row. Rows are loaded and stored as 8-byte (float32) or 4-byte (16-bit)
+// pairs — half the memory instructions per cell — and a lane reads the four values x-1 .. x+2
+// of a row from LDS with one 8-byte and two 4-byte reads serving both of its cells.
+// -------------------------------------------------------------------------------------------
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using raw = float2;
+    static __device__ __forceinline__ float lo(raw v, float) { return v.x; }
+    static __device__ __forceinline__ float hi(raw v, float) { return v.y; }
+    static __device__ __forceinline__ raw make(float a, float b, float) { return make_float2(a, b); }
+};
+template <>
+struct Pair<__half> {
+    using raw = __half2;
+    static __device__ __forceinline__ float lo(raw v, float s) { return __low2float(v) * s; }
+    static __device__ __forceinline__ float hi(raw v, float s) { return __high2float(v) * s; }
+    static __device__ __forceinline__ raw make(float a, float b, float inv) {
+        return __halves2half2(__float2half_rn(a * inv), __float2half_rn(b * inv));
+    }
+};
+template <>
+struct Pair<__hip_bfloat16> {
+    using raw = unsigned;  // low half = element x, high half = element x + 1
+    static __device__ __forceinline__ float lo(raw v, float s) { return __uint_as_float(v << 16) * s; }
+    static __device__ __forceinline__ float hi(raw v, float s) { return __uint_as_float(v & 0xffff0000u) * s; }
+    static __device__ __forceinline__ raw make(float a, float b, float inv) {
+        const __hip_bfloat16 x = __float2bfloat16(a * inv), y = __float2bfloat16(b * inv);
+        return (unsigned)__bfloat16_as_ushort(x) | ((unsigned)__bfloat16_as_ushort(y) << 16);
+    }
+};
+
+template <int TY, typename TU, typename TB, bool BATCH>
+__global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
+                                                            int parity, int nbatch) {
+    constexpr int HY = TY + 2;        // staged rows
+    constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
+    constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
+    __shared__ __align__(16) float s_pl[2][6][HY * RS];
+
+    const int per = gridDim.x >> 3;
+    int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if constexpr (BATCH) {
+        if (lb >= nbatch) return;
+        const BlockMap m = map[lb];
+        a = tab[m.pipe].sw[parity];
+        lb = m.local;
+    } else {
+        if (lb >= a.nblocks) return;
+    }
+    const int tix = lb % a.tiles_x;
+    const int rest = lb / a.tiles_x;
+    const int tiy = rest % a.tiles_y;
+    const int tiz = rest / a.tiles_y;
+    const int x0 = tix * 128, y0 = tiy * TY;
+    const int z0 = tiz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, a.nz);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned N = (unsigned)nx * ny * nz;
+    const unsigned plane = (unsigned)nx * ny;
+    const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * (size_t)N;
+    const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * (size_t)N;
+    TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * (size_t)N;
+    using PU = Pair<TU>;
+    using PB = Pair<TB>;
+    using RU = typename PU::raw;
+    using RB = typename PB::raw;
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int xa = x0 + 2 * l;            // this lane's cells: xa, xa + 1 (always inside: nx % 128 == 0)
+    const int gy = y0 + w;
+    const bool own = gy < ny;
+    const float kap = a.kappa;
+    // B_ext of this lane's pair of columns and of the two halo columns
+    const float bea[3] = {a.bext[xa], a.bext[nx + xa], a.bext[2 * nx + xa]};
+    const float beb[3] = {a.bext[xa + 1], a.bext[nx + xa + 1], a.bext[2 * nx + xa + 1]};
+
+    // row loads: round r stages row hy = w + r * TY (if < HY) at columns xa, xa + 1
+    unsigned rowoff[NR];
+    bool rowval[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int hy = w + r * TY;
+        rowval[r] = hy < HY;
+        rowoff[r] = (unsigned)(xa + nx * wrapi(y0 - 1 + hy, ny));
+    }
+    // halo columns: lanes 0 .. 2*HY-1 of the last wave, lane -> (row hy = lane / 2, side)
+    const bool hval = (w == TY - 1) && (l < 2 * HY);
+    const int hhy = l >> 1, hside = l & 1;
+    const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
+    const unsigned hoff = (unsigned)(hx + nx * wrapi(y0 - 1 + min(hhy, HY - 1), ny));
+    const int hidx = min(hhy, HY - 1) * RS + (hside ? 129 : 0);
+    const float hbe[3] = {a.bext[hx], a.bext[nx + hx], a.bext[2 * nx + hx]};
+
+    RU ru[NR][3];
+    RB rb[NR][3];
+    TU hu[3];
+    TB hb[3];
+    auto load_plane = [&](int p) {
+        const unsigned off = (unsigned)wrapi(p, nz) * plane;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (rowval[r]) {
+                const unsigned ku = (off + rowoff[r]) * (unsigned)sizeof(TU);
+                const unsigned kb = (off + rowoff[r]) * (unsigned)sizeof(TB);
+                ru[r][0] = ld_off(reinterpret_cast<const RU *>(u0), ku);
+                ru[r][1] = ld_off(reinterpret_cast<const RU *>(u1), ku);
+                ru[r][2] = ld_off(reinterpret_cast<const RU *>(u2), ku);
+                rb[r][0] = ld_off(reinterpret_cast<const RB *>(b0), kb);
+                rb[r][1] = ld_off(reinterpret_cast<const RB *>(b1), kb);
+                rb[r][2] = ld_off(reinterpret_cast<const RB *>(b2), kb);
+            }
+        }
+        if (hval) {
+            const unsigned ku = (off + hoff) * (unsigned)sizeof(TU), kb = (off + hoff) * (unsigned)sizeof(TB);
+            hu[0] = ld_off(u0, ku);
+            hu[1] = ld_off(u1, ku);
+            hu[2] = ld_off(u2, ku);
+            hb[0] = ld_off(b0, kb);
+            hb[1] = ld_off(b1, kb);
+            hb[2] = ld_off(b2, kb);
+        }
+    };
+    auto put = [&](int buf, int idx, float bx, float by, float bz, float ux, float uy, float uz, const float *be) {
+        const float Bx = bx + be[0], By = by + be[1], Bz = bz + be[2];
+        s_pl[buf][0][idx] = bx;
+        s_pl[buf][1][idx] = by;
+        s_pl[buf][2][idx] = bz;
+        s_pl[buf][3][idx] = kap * (uy * Bx - ux * By);
+        s_pl[buf][4][idx] = kap * (uz * Bx - ux * Bz);
+        s_pl[buf][5][idx] = kap * (uz * By - uy * Bz);
+    };
+    auto stage = [&](auto bufc) {
+        constexpr int S = decltype(bufc)::value;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (rowval[r]) {
+                const int idx = (w + r * TY) * RS + 1 + 2 * l;
+                const float us = a.u_scale, bs = a.b_scale;
+                put(S, idx, PB::lo(rb[r][0], bs), PB::lo(rb[r][1], bs), PB::lo(rb[r][2], bs), PU::lo(ru[r][0], us),
+                    PU::lo(ru[r][1], us), PU::lo(ru[r][2], us), bea);
+                put(S, idx + 1, PB::hi(rb[r][0], bs), PB::hi(rb[r][1], bs), PB::hi(rb[r][2], bs), PU::hi(ru[r][0], us),
+                    PU::hi(ru[r][1], us), PU::hi(ru[r][2], us), beb);
+            }
+        }
+        if (hval)
+            put(S, hidx, St<TB>::val(hb[0], a.b_scale), St<TB>::val(hb[1], a.b_scale), St<TB>::val(hb[2], a.b_scale),
+                St<TU>::val(hu[0], a.u_scale), St<TU>::val(hu[1], a.u_scale), St<TU>::val(hu[2], a.u_scale), hbe);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+
+    constexpr float W6 = 1.0f / 6.0f;
+    float acc[2][3] = {}, ap[2][3] = {}, cm[2][3] = {}, cc[2][3] = {};
+
+    load_plane(z0 - 1);
+    stage(I0{});
+    load_plane(z0);
+    __syncthreads();
+    auto body = [&](auto par, int p) {
+        constexpr int P = decltype(par)::value;
+        using Q = std::integral_constant<int, 1 - P>;
+        if (p < z1) {
+            stage(Q{});
+            if (p + 2 <= z1) load_plane(p + 2);
+        }
+        if (own) {
+            // per field: rows y-1, y, y+1 at columns xa-1 .. xa+2 (two aligned 8-byte reads per
+            // row), reduced at once into the plane terms of both cells
+            float A[2][3], B[2][3], C[2][2], cen[2][3];
+            auto rows = [&](int k, float (&v)[3][4]) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float *row = &s_pl[P][k][(w + r) * RS + 2 * l];
+                    const float2 lo = *reinterpret_cast<const float2 *>(row);
+                    const float2 hi = *reinterpret_cast<const float2 *>(row + 2);
+                    v[r][0] = lo.x;
+                    v[r][1] = lo.y;
+                    v[r][2] = hi.x;
+                    v[r][3] = hi.y;
+                }
+            };
+            {  // b components
+                float v[3][4];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    rows(k, v);
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float c = v[1][1 + e];
+                        const float fs = ((v[1][e] - c) + (v[1][e + 2] - c)) + ((v[0][1 + e] - c) + (v[2][1 + e] - c));
+                        const float cs = ((v[0][e] - c) + (v[0][e + 2] - c)) + ((v[2][e] - c) + (v[2][e + 2] - c));
+                        const float dP0 = WF * fs + WE * cs, dP1 = WE * fs;
+                        cen[e][k] = c;
+                        A[e][k] = dP1;
+                        B[e][k] = dP0;
+                        if (k < 2) C[e][k] = dP1;
+                    }
+                }
+            }
+            {  // kappa Lam_xy: Q0x, Q1x, Q0y, Q1y
+                float v[3][4];
+                rows(3, v);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float dx = v[1][e] - v[1][e + 2], dy = v[0][1 + e] - v[2][1 + e];
+                    const float Q0x = WF * dx + WE * ((v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]));
+                    const float Q1x = WE * dx;
+                    const float Q0y = WF * dy + WE * ((v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]));
+                    const float Q1y = WE * dy;
+                    A[e][0] += Q1y;
+                    B[e][0] += Q0y;
+                    C[e][0] += Q1y;
+                    A[e][1] -= Q1x;
+                    B[e][1] -= Q0x;
+                    C[e][1] -= Q1x;
+                }
+            }
+            {  // kappa Lam_xz: P1, Q0x, Q1x
+                float v[3][4];
+                rows(4, v);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float dx = v[1][e] - v[1][e + 2];
+                    const float P1 = WF * v[1][1 + e] + WE * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
+                    const float Q0x = WF * dx + WE * ((v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]));
+                    const float Q1x = WE * dx;
+                    A[e][0] += P1;
+                    C[e][0] -= P1;
+                    A[e][2] -= Q1x;
+                    B[e][2] -= Q0x;
+                }
+            }
+            {  // kappa Lam_yz: P1, Q0y, Q1y
+                float v[3][4];
+                rows(5, v);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float dy = v[0][1 + e] - v[2][1 + e];
+                    const float P1 = WF * v[1][1 + e] + WE * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
+                    const float Q0y = WF * dy + WE * ((v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]));
+                    const float Q1y = WE * dy;
+                    A[e][1] += P1;
+                    C[e][1] -= P1;
+                    A[e][2] -= Q1y;
+                    B[e][2] -= Q0y;
+                }
+            }
+            float out[2][3];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                // output plane p-1: b* = b_c + increment (differences only); C2 = A2
+                out[e][0] = cc[e][0] + ((acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0])));
+                out[e][1] = cc[e][1] + ((acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1])));
+                out[e][2] = cc[e][2] + ((acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2])));
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    acc[e][q] = ap[e][q] + B[e][q];
+                    ap[e][q] = A[e][q];
+                    cm[e][q] = cc[e][q];
+                    cc[e][q] = cen[e][q];
+                }
+            }
+            if (p >= z0 + 1) {
+                const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);
+                st_off(reinterpret_cast<RB *>(o0), k, PB::make(out[0][0], out[1][0], a.inv_b_scale));
+                st_off(reinterpret_cast<RB *>(o1), k, PB::make(out[0][1], out[1][1], a.inv_b_scale));
+                st_off(reinterpret_cast<RB *>(o2), k, PB::make(out[0][2], out[1][2], a.inv_b_scale));
+            }
+        }
+        __syncthreads();
+    };
+    for (int p = z0 - 1; p <= z1; p += 2) {
+        body(I0{}, p);
+        if (p + 1 <= z1) body(I1{}, p + 1);
+    }
+}
+
+// ===========================================================================================
+// Host-side launchers of the sweep
+// ===========================================================================================
+SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *bext, StepConst c, SweepLaunch L) {
+    SweepArgs a;
+    a.u = u;
+    a.b = b;
+    a.bo = bo;
+    a.bext = bext;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    const bool pair = L.pair && c.nx % 128 == 0;
+    const int tx = pair ? 128 : L.tx;
+    const int ty = pair ? (L.ty >= 8 ? 8 : 4) : 256 / L.tx;
+    a.tiles_x = (c.nx + tx - 1) / tx;
+    a.tiles_y = (c.ny + ty - 1) / ty;
+    a.zchunk = L.zchunk;
+    a.nzc = (c.nz + L.zchunk - 1) / L.zchunk;
+    a.nblocks = a.tiles_x * a.tiles_y * a.nzc;
+    a.kappa = c.kappa;
+    a.u_scale = c.u_scale;
+    a.b_scale = c.b_scale;
+    a.inv_b_scale = c.inv_b_scale;
+    return a;
+}
+
+// grid of a sweep launch: a multiple of 8 so the XCD-aware remap is a permutation
+static inline unsigned sweep_grid(int nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
+
+// Sweeps are launched through hipExtLaunchKernelGGL: when profiling, its start / stop events
+// are stamped when the kernel itself starts and ends (no event packets around the launch).
+template <typename TU, typename TB, bool BATCH>
+static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
+                              const BlockMap *map, int parity, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid(sweep_grid(nblocks));
+    if (L.pair) {
+        if (L.ty >= 8)
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
+                                  parity, nblocks);
+        else
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  parity, nblocks);
+        return hipGetLastError();
+    }
+    switch (L.tx) {
+        case 64:
+            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  parity, nblocks);
+            break;
+        case 32:
+            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  parity, nblocks);
+            break;
+        case 16:
+            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  parity, nblocks);
+            break;
+        default:
+            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  parity, nblocks);
+            break;
+    }
+    return hipGetLastError();
+}
+
+
+template <bool BATCH>
+static hipError_t sweep_kinds(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
+                              const BlockMap *map, int parity, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+    const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
+    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
+        return sweep_typed<float, float, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+    if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
+        return sweep_typed<__half, __half, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
+        return sweep_typed<__hip_bfloat16, __half, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
+        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo, const float *bext,
+                            StepConst c, SweepLaunch L, hipEvent_t e0, hipEvent_t e1) {
+    L.pair = L.pair && c.nx % 128 == 0;
+    const SweepArgs a = make_sweep_args(u, b, bo, bext, c, L);
+    return sweep_kinds<false>(s, kinds, a, L, nullptr, nullptr, 0, a.nblocks, e0, e1);
+}
+
+hipError_t launch_mag_sweep_batch(hipStream_t s, int kinds, SweepLaunch L, const PipeStep *tab, const BlockMap *map,
+                                  int parity, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+    if (nblocks <= 0) return hipSuccess;
+    return sweep_kinds<true>(s, kinds, SweepArgs{}, L, tab, map, parity, nblocks, e0, e1);
+}
+
+}  // namespace mhd

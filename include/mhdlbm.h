@@ -39,15 +39,21 @@ typedef int32_t mhd_status;
 #define MHD_ERR_UNSUPPORTED (-6) /* valid request outside this build (e.g. tau >= 1)        */
 
 /* Storage kind of a field in device memory. Arithmetic is always float32. 16-bit kinds store
- * offsets: rho as rho - 1, u as u / u_scale, b as b / b_scale. */
-typedef enum { MHD_STORE_F32 = 0, MHD_STORE_F16 = 1, MHD_STORE_BF16 = 2 } mhd_storage;
+ * offsets: rho as rho - 1, u as u / u_scale, b as b / b_scale.
+ * MHD_STORE_F16_SPLIT (b only, with rho and u float32): b = (hi + lo) b_scale with two float16
+ * arrays; hi is re-quantised once per fluid step (first sweep) and the sweeps update lo, so the
+ * 16-bit rounding is relative to the change of b rather than to b. The sweeps then read a float16
+ * copy of u (u / u_scale) that the fluid step and its wall correction keep current.
+ * Built mixes (rho, u, b): all F32; F16, F16, F16; F16, BF16, F16; all BF16; F32, F32, F16_SPLIT. */
+typedef enum { MHD_STORE_F32 = 0, MHD_STORE_F16 = 1, MHD_STORE_BF16 = 2, MHD_STORE_F16_SPLIT = 3 } mhd_storage;
 
 typedef struct {
     int32_t nx, ny, nz;    /* box size in cells; nx, ny, nz >= 1                         */
     int32_t rho_storage;   /* mhd_storage of the density offset rho - 1                  */
     int32_t u_storage;     /* mhd_storage of the velocity                               */
     int32_t b_storage;     /* mhd_storage of the induced field                          */
-    double u_scale;        /* velocity scale of 16-bit storage (> 0; ignored for F32)    */
+    double u_scale;        /* velocity scale of 16-bit storage and of the split form's
+                              float16 copy of u (> 0; else ignored)                    */
     double b_scale;        /* induced-field scale of 16-bit storage (> 0; ignored for F32) */
 } mhd_grid_desc;
 

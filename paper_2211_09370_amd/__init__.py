@@ -16,7 +16,8 @@ from . import _abi
 from ._abi import (MHD_BEXT_NONE, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_UNIFORM_Y, MHD_FIELD_B_INDUCED,
                    MHD_FIELD_RHO, MHD_FIELD_U, MHD_K_BUDGET, MHD_K_CONTROL, MHD_K_FLUID,
                    MHD_K_IB, MHD_K_LORENTZ, MHD_K_MAG_SWEEP,
-                   MHD_STORE_BF16, MHD_STORE_F16, MHD_STORE_F32, MhdError, mhd_budget,
+                   MHD_STORE_BF16, MHD_STORE_F16, MHD_STORE_F16_SPLIT, MHD_STORE_F32, MhdError,
+                   mhd_budget,
                    mhd_grid_desc, mhd_params, mhd_pipe_desc)
 
 __all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
@@ -28,7 +29,8 @@ __all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_
            "mhd_batch_kernel_stats", "mhd_batch_destroy", "mhd_last_error", "BUDGET_FIELDS"]
 
 BUDGET_FIELDS = [f for f, _ in mhd_budget._fields_]
-_STORAGE = {"f32": MHD_STORE_F32, "f16": MHD_STORE_F16, "bf16": MHD_STORE_BF16}
+_STORAGE = {"f32": MHD_STORE_F32, "f16": MHD_STORE_F16, "bf16": MHD_STORE_BF16,
+            "f16split": MHD_STORE_F16_SPLIT}
 _FIELDS = {"rho": MHD_FIELD_RHO, "u": MHD_FIELD_U, "b": MHD_FIELD_B_INDUCED}
 _D = C.POINTER(C.c_double)
 

@@ -21,7 +21,7 @@ MHD_ERR_UNSUPPORTED = -6
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "UNSTABLE", -5: "STATE",
                 -6: "UNSUPPORTED"}
 
-MHD_STORE_F32, MHD_STORE_F16, MHD_STORE_BF16 = 0, 1, 2
+MHD_STORE_F32, MHD_STORE_F16, MHD_STORE_BF16, MHD_STORE_F16_SPLIT = 0, 1, 2, 3
 MHD_BEXT_NONE, MHD_BEXT_UNIFORM_Y, MHD_BEXT_TANH_FRINGE_Y = 0, 1, 2
 MHD_FIELD_RHO, MHD_FIELD_U, MHD_FIELD_B_INDUCED = 0, 1, 2
 (MHD_K_MAG_SWEEP, MHD_K_IB, MHD_K_LORENTZ, MHD_K_FLUID, MHD_K_BUDGET, MHD_K_CONTROL,

@@ -66,9 +66,11 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 #define WF (1.0f / 18.0f)
 #define WE (1.0f / 36.0f)
 
-// Supported storage mixes: all float32; rho f16 with u f16 or bf16 and b f16; all bf16.
+// Supported storage mixes: all float32; rho f16 with u f16 or bf16 and b f16; all bf16;
+// rho and u float32 with b float16 split.
 #define MHD_KIND_F32 0
 #define MHD_KIND_F16 1
 #define MHD_KIND_BF16 2
+#define MHD_KIND_F16_SPLIT 3  // b only, with rho and u float32 (u read by the sweeps as a float16 copy)
 
 }  // namespace mhd

@@ -27,6 +27,7 @@ struct StepConst {
     float kappa;       // 1 / (2 eta)
     float tau;         // 3 nu + 1/2
     float u_scale, inv_u_scale, b_scale, inv_b_scale;
+    float copy_scale, inv_copy_scale;  // split form: scale of the float16 copy of u
     double nu, eta;
     double G0, G1, period;
     double yc, zc, radius;
@@ -47,9 +48,11 @@ struct SweepLaunch {
 
 // Arguments of one magnetic sweep launch over one box.
 struct SweepArgs {
-    const void *u;
-    const void *b;
-    void *bo;
+    const void *u;      // velocity as the sweep reads it (the float16 copy in the split form)
+    const void *b;      // b (split form: its lo part)
+    void *bo;           // output b (split form: lo part)
+    const void *bh;     // split form: hi part of b (else NULL)
+    void *bho;          // split form, first sweep of a step: re-split hi output (else NULL)
     const float *bext;  // 3 x nx
     int nx, ny, nz;
     int tiles_x, tiles_y, nzc, zchunk, nblocks;
@@ -61,9 +64,9 @@ SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *b
 hipError_t launch_ctrl_begin(hipStream_t s, DevCtrl *ctrl, StepConst c);
 hipError_t launch_step_end(hipStream_t s, DevCtrl *ctrl, const double *flow_part, StepConst c,
                            double inv_count);
+// One sweep with arguments a (from make_sweep_args, split-form fields filled in by the caller).
 // e0 / e1 (optional): events stamped at the start and end of the sweep kernel itself.
-hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo,
-                            const float *bext, StepConst c, SweepLaunch L, hipEvent_t e0 = nullptr,
+hipError_t launch_mag_sweep(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
 // Wall correction data (device pointers), markers in the library's internal order.
 struct IbArgs {
@@ -77,16 +80,21 @@ struct IbArgs {
     const int *band_mk;    // [km][nband] marker of each gather entry (padding: a valid marker)
     const float *band_w;   // [km][nband] weight of each gather entry (0 for padding)
     float *delta;          // [3][M] Lagrangian corrections
+    const void *phi_hi;    // split form: hi part of the field, added in the interpolation (else NULL)
+    void *copy;            // float16 copy of the field refreshed at corrected cells (else NULL)
+    float copy_inv;        // 1 / scale of that copy
 };
 // Interpolation launch, then spreading launch.
 hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_scale, const IbArgs &a);
-hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const float *bext,
+// b_hi: hi part of b in the split form (else NULL).
+hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *b_hi, const float *bext,
                           const DevCtrl *ctrl, float *F, StepConst c);
+// u_copy: float16 copy of the new u (u / u_scale) for the split form's sweeps (else NULL).
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,
-                        void *rho_o, void *u_o, StepConst c);
+                        void *rho_o, void *u_o, void *u_copy, StepConst c);
 hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c);
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b,
-                         const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring,
+                         const void *b_hi, const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring,
                          StepConst c);
 // -------------------------------------------------------------------------------------------
 // Batched launches: one launch covers the same kernel for many boxes. Each workgroup finds its
@@ -95,11 +103,14 @@ hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *
 // the single-box kernel, so every box gets bitwise the result of its own single-box launch.
 // -------------------------------------------------------------------------------------------
 struct PipeStep {
-    SweepArgs sw[2];          // sweep of an even / odd round (the b buffers swap every round)
+    SweepArgs sw[3];          // sweep of round 0, of an odd round, of an even round >= 2 (the b
+                              // buffers swap every round; round 0 also re-splits the split form)
     IbArgs ib[3];             // wall correction of b after an even round, after an odd round; of u
     void *phi[3];             // field corrected by ib[i]
     float scale[3], inv_scale[3];
     const void *b_last;       // b after the box's last sweep (Lorentz input)
+    const void *b_hi;         // split form: hi part of b during and after the sweeps (else NULL)
+    void *u_copy;             // split form: float16 copy of u written by the fluid kernel (else NULL)
     const float *bext;
     DevCtrl *ctrl;
     float *F;
@@ -109,6 +120,7 @@ struct PipeStep {
     double inv_count;
     StepConst c;
 };
+static_assert(sizeof(PipeStep) % 8 == 0, "PipeStep is copied as an array");
 struct BlockMap {             // (box, workgroup within the box) of workgroup i of a batched launch
     int pipe, local;
 };
@@ -130,6 +142,8 @@ constexpr int kIbThreads = 256;
 // float32 staging <-> storage kind (round to nearest even on the way in).
 hipError_t launch_store_kind(hipStream_t s, int kind, const float *src, void *dst, int64_t n);
 hipError_t launch_load_kind(hipStream_t s, int kind, const void *src, float *dst, int64_t n);
+// float32 staging -> float16 hi = fp16(v), lo = fp16(v - hi) (values already divided by the scale).
+hipError_t launch_store_split(hipStream_t s, const float *src, void *hi, void *lo, int64_t n);
 hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl);
 
 // Packs the three storage kinds (rho, u, b) into one dispatch code.

@@ -104,13 +104,25 @@ template <typename T>
 __device__ __forceinline__ void ib_marker(const T *phi, float scale, const IbArgs &a, int j, float &d0, float &d1,
                                           float &d2) {
     float I0 = 0.f, I1 = 0.f, I2 = 0.f;
+    const T *hi = (const T *)a.phi_hi;
+    if (hi) {  // split form: the field is (hi + lo) scale
 #pragma unroll 9
-    for (int t = 0; t < a.tm; ++t) {
-        const int64_t k = a.tap_cell[(int64_t)t * a.M + j];
-        const float w = a.tap_w[(int64_t)t * a.M + j];
-        I0 += w * (St<T>::ld(phi, k) * scale);
-        I1 += w * (St<T>::ld(phi, a.N + k) * scale);
-        I2 += w * (St<T>::ld(phi, 2 * a.N + k) * scale);
+        for (int t = 0; t < a.tm; ++t) {
+            const int64_t k = a.tap_cell[(int64_t)t * a.M + j];
+            const float w = a.tap_w[(int64_t)t * a.M + j];
+            I0 += w * ((St<T>::ld(phi, k) + St<T>::ld(hi, k)) * scale);
+            I1 += w * ((St<T>::ld(phi, a.N + k) + St<T>::ld(hi, a.N + k)) * scale);
+            I2 += w * ((St<T>::ld(phi, 2 * a.N + k) + St<T>::ld(hi, 2 * a.N + k)) * scale);
+        }
+    } else {
+#pragma unroll 9
+        for (int t = 0; t < a.tm; ++t) {
+            const int64_t k = a.tap_cell[(int64_t)t * a.M + j];
+            const float w = a.tap_w[(int64_t)t * a.M + j];
+            I0 += w * (St<T>::ld(phi, k) * scale);
+            I1 += w * (St<T>::ld(phi, a.N + k) * scale);
+            I2 += w * (St<T>::ld(phi, 2 * a.N + k) * scale);
+        }
     }
     const float s = a.sj[j];
     d0 = s * (a.wall[j] - I0);
@@ -136,6 +148,12 @@ __device__ __forceinline__ void ib_cell(T *phi, float scale, float inv_scale, co
     St<T>::st(phi, k, (v0 + c0) * inv_scale);
     St<T>::st(phi, a.N + k, (v1 + c1) * inv_scale);
     St<T>::st(phi, 2 * a.N + k, (v2 + c2) * inv_scale);
+    if (a.copy) {  // float16 copy of the corrected field (the split form's u for the sweeps)
+        __half *cp = (__half *)a.copy;
+        cp[k] = __float2half_rn((v0 + c0) * a.copy_inv);
+        cp[a.N + k] = __float2half_rn((v1 + c1) * a.copy_inv);
+        cp[2 * a.N + k] = __float2half_rn((v2 + c2) * a.copy_inv);
+    }
 }
 
 template <typename T, bool BATCH>
@@ -181,8 +199,8 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_spread(T *phi, float scale, f
 // Lorentz + body force (Sec. 5.1): J = curl_h b with d_a f = 3 sum_i w_i e_ia f(x + e_i),
 // F = G x + J x (B_ext + b).
 // -------------------------------------------------------------------------------------------
-template <typename TB, bool BATCH>
-__global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, float bs, const float *bext,
+template <typename TB, bool BATCH, bool SPLIT>
+__global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB *bh, float bs, const float *bext,
                                                           const DevCtrl *ctrl, float *F, StepConst c,
                                                           const PipeStep *tab, const BlockMap *map) {
     int64_t blk = blockIdx.x;
@@ -190,6 +208,7 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, float bs,
         const BlockMap m = map[blk];
         const PipeStep &q = tab[m.pipe];
         b = (const TB *)q.b_last;
+        bh = (const TB *)q.b_hi;
         bs = q.c.b_scale;
         bext = q.bext;
         ctrl = q.ctrl;
@@ -203,13 +222,20 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, float bs,
     const int x = (int)(k % c.nx);
     const int y = (int)((k / c.nx) % c.ny);
     const int z = (int)(k / ((int64_t)c.nx * c.ny));
+    // value of component a at cell i (the split form adds its hi part)
+    auto bv = [&](int64_t i) {
+        if constexpr (SPLIT)
+            return St<TB>::ld(b, i) + St<TB>::ld(bh, i);
+        else
+            return St<TB>::ld(b, i);
+    };
     float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // g[a][c] = d_c b_a
 #pragma unroll
     for (int i = 0; i < 18; ++i) {
         const int ex = c_dir[i][0], ey = c_dir[i][1], ez = c_dir[i][2];
         const float w = 3.0f * (i < 6 ? WF : WE);
         const int64_t kn = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
-        const float v0 = St<TB>::ld(b, kn) * bs, v1 = St<TB>::ld(b, N + kn) * bs, v2 = St<TB>::ld(b, 2 * N + kn) * bs;
+        const float v0 = bv(kn) * bs, v1 = bv(N + kn) * bs, v2 = bv(2 * N + kn) * bs;
         const float e3[3] = {(float)ex, (float)ey, (float)ez};
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
@@ -220,9 +246,9 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, float bs,
         }
     }
     const float Jx = g[2][1] - g[1][2], Jy = g[0][2] - g[2][0], Jz = g[1][0] - g[0][1];
-    const float Bx = St<TB>::ld(b, k) * bs + bext[x];
-    const float By = St<TB>::ld(b, N + k) * bs + bext[c.nx + x];
-    const float Bz = St<TB>::ld(b, 2 * N + k) * bs + bext[2 * c.nx + x];
+    const float Bx = bv(k) * bs + bext[x];
+    const float By = bv(N + k) * bs + bext[c.nx + x];
+    const float Bz = bv(2 * N + k) * bs + bext[2 * c.nx + x];
     const float G = (float)ctrl->G_step;
     F[k] = G + (Jy * Bz - Jz * By);
     F[N + k] = Jz * Bx - Jx * Bz;
@@ -253,7 +279,7 @@ __constant__ int c_pair[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1,
 
 template <typename TR, typename TU, bool BATCH>
 __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o,
-                                                        TU *u_o, StepConst c, const PipeStep *tab,
+                                                        TU *u_o, __half *u_copy, StepConst c, const PipeStep *tab,
                                                         const BlockMap *map) {
     int64_t blk = blockIdx.x;
     if constexpr (BATCH) {
@@ -264,6 +290,7 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         F = q.F;
         rho_o = (TR *)q.rho_o;
         u_o = (TU *)q.u_o;
+        u_copy = (__half *)q.u_copy;
         c = q.c;
         blk = m.local;
     }
@@ -327,9 +354,16 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
     const float Dm2 = (m2 - tcF * g2) + F[2 * N + k];
     const float inv = 1.0f / (1.0f + dnew);
     St<TR>::st(rho_o, k, dnew);
-    St<TU>::st(u_o, k, (ux0 + (Dm0 - dr * ux0) * inv) * c.inv_u_scale);
-    St<TU>::st(u_o, N + k, (uy0 + (Dm1 - dr * uy0) * inv) * c.inv_u_scale);
-    St<TU>::st(u_o, 2 * N + k, (uz0 + (Dm2 - dr * uz0) * inv) * c.inv_u_scale);
+    const float un0 = ux0 + (Dm0 - dr * ux0) * inv, un1 = uy0 + (Dm1 - dr * uy0) * inv,
+                un2 = uz0 + (Dm2 - dr * uz0) * inv;
+    St<TU>::st(u_o, k, un0 * c.inv_u_scale);
+    St<TU>::st(u_o, N + k, un1 * c.inv_u_scale);
+    St<TU>::st(u_o, 2 * N + k, un2 * c.inv_u_scale);
+    if (u_copy) {  // split form: float16 copy u / u_scale for the sweeps
+        u_copy[k] = __float2half_rn(un0 * c.inv_copy_scale);
+        u_copy[N + k] = __float2half_rn(un1 * c.inv_copy_scale);
+        u_copy[2 * N + k] = __float2half_rn(un2 * c.inv_copy_scale);
+    }
 }
 
 // -------------------------------------------------------------------------------------------
@@ -382,7 +416,8 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
 // 9 sum |J|^2, 10 mass, 11 Q sum, 12 n_omega, 13 max |u|^2, 14 nonfinite, 15 unused
 template <typename TR, typename TU, typename TB>
 __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, const TU *u, const TB *b,
-                                                                const float *bext, double *part, StepConst c) {
+                                                                const TB *bh, const float *bext, double *part,
+                                                                StepConst c) {
     __shared__ double sh[13][kRedThreads];
     __shared__ double shm[kRedThreads];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
@@ -403,6 +438,7 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
         for (int a = 0; a < 3; ++a) {
             uu[a] = (double)St<TU>::ld(u, a * N + k) * us;
             bb[a] = (double)St<TB>::ld(b, a * N + k) * bs;
+            if (bh) bb[a] += (double)St<TB>::ld(bh, a * N + k) * bs;
             B[a] = bb[a] + (double)bext[a * c.nx + x];
         }
         const double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
@@ -425,6 +461,7 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
             for (int a = 0; a < 3; ++a) {
                 un[a] = (double)St<TU>::ld(u, a * N + kn) * us;
                 bn[a] = (double)St<TB>::ld(b, a * N + kn) * bs;
+                if (bh) bn[a] += (double)St<TB>::ld(bh, a * N + kn) * bs;
                 Bn[a] = bn[a] + (double)bext[a * c.nx + xn];
             }
             for (int a = 0; a < 3; ++a) {
@@ -542,6 +579,13 @@ __global__ void k_store(const float *src, T *dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         St<T>::st(dst, i, src[i]);
 }
+__global__ void k_store_split(const float *src, __half *hi, __half *lo, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const __half h = __float2half_rn(src[i]);
+        hi[i] = h;
+        lo[i] = __float2half_rn(src[i] - __half2float(h));
+    }
+}
 template <typename T>
 __global__ void k_load(const T *src, float *dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -583,7 +627,8 @@ hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl) {
 #define MHD_DISPATCH1(kind, FN, ...)                                       \
     switch (kind) {                                                        \
         case MHD_KIND_F32: return FN<float>(__VA_ARGS__);                  \
-        case MHD_KIND_F16: return FN<__half>(__VA_ARGS__);                 \
+        case MHD_KIND_F16:                                                 \
+        case MHD_KIND_F16_SPLIT: return FN<__half>(__VA_ARGS__);           \
         case MHD_KIND_BF16: return FN<__hip_bfloat16>(__VA_ARGS__);        \
         default: return hipErrorInvalidValue;                              \
     }
@@ -626,58 +671,73 @@ hipError_t launch_ib_spread_batch(hipStream_t s, int kind, const PipeStep *tab, 
     MHD_DISPATCH1(kind, ib_spread_batch_t, s, tab, map, which, nblocks)
 }
 
-template <typename T>
-static hipError_t lorentz_t(hipStream_t s, const void *b, const float *bext, const DevCtrl *ctrl, float *F,
-                            StepConst c) {
+template <typename T, bool SPLIT>
+static hipError_t lorentz_t(hipStream_t s, const void *b, const void *bh, const float *bext, const DevCtrl *ctrl,
+                            float *F, StepConst c) {
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    hipLaunchKernelGGL((k_lorentz<T, false>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads), 0, s,
-                       (const T *)b, c.b_scale, bext, ctrl, F, c, nullptr, nullptr);
+    hipLaunchKernelGGL((k_lorentz<T, false, SPLIT>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads), 0, s,
+                       (const T *)b, (const T *)bh, c.b_scale, bext, ctrl, F, c, nullptr, nullptr);
     return hipGetLastError();
 }
-hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const float *bext, const DevCtrl *ctrl, float *F,
-                          StepConst c) {
-    MHD_DISPATCH1(kind_b, lorentz_t, s, b, bext, ctrl, F, c)
+hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *b_hi, const float *bext,
+                          const DevCtrl *ctrl, float *F, StepConst c) {
+    switch (kind_b) {
+        case MHD_KIND_F32: return lorentz_t<float, false>(s, b, b_hi, bext, ctrl, F, c);
+        case MHD_KIND_F16: return lorentz_t<__half, false>(s, b, b_hi, bext, ctrl, F, c);
+        case MHD_KIND_BF16: return lorentz_t<__hip_bfloat16, false>(s, b, b_hi, bext, ctrl, F, c);
+        case MHD_KIND_F16_SPLIT: return lorentz_t<__half, true>(s, b, b_hi, bext, ctrl, F, c);
+        default: return hipErrorInvalidValue;
+    }
 }
-template <typename T>
+template <typename T, bool SPLIT>
 static hipError_t lorentz_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int nblocks) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_lorentz<T, true>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr, 0.f, nullptr, nullptr,
-                       nullptr, StepConst{}, tab, map);
+    hipLaunchKernelGGL((k_lorentz<T, true, SPLIT>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr, nullptr, 0.f,
+                       nullptr, nullptr, nullptr, StepConst{}, tab, map);
     return hipGetLastError();
 }
 hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks) {
-    MHD_DISPATCH1(kind_b, lorentz_batch_t, s, tab, map, nblocks)
+    switch (kind_b) {
+        case MHD_KIND_F32: return lorentz_batch_t<float, false>(s, tab, map, nblocks);
+        case MHD_KIND_F16: return lorentz_batch_t<__half, false>(s, tab, map, nblocks);
+        case MHD_KIND_BF16: return lorentz_batch_t<__hip_bfloat16, false>(s, tab, map, nblocks);
+        case MHD_KIND_F16_SPLIT: return lorentz_batch_t<__half, true>(s, tab, map, nblocks);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename TR, typename TU, bool BATCH>
 static hipError_t fluid_t(hipStream_t s, const void *rho, const void *u, const float *F, void *rho_o, void *u_o,
-                          StepConst c, const PipeStep *tab, const BlockMap *map, int nblocks) {
+                          void *u_copy, StepConst c, const PipeStep *tab, const BlockMap *map, int nblocks) {
     if (!BATCH) nblocks = (int)blocks_for((int64_t)c.nx * c.ny * c.nz, kCellThreads);
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_fluid<TR, TU, BATCH>), dim3(nblocks), dim3(kCellThreads), 0, s, (const TR *)rho,
-                       (const TU *)u, F, (TR *)rho_o, (TU *)u_o, c, tab, map);
+                       (const TU *)u, F, (TR *)rho_o, (TU *)u_o, (__half *)u_copy, c, tab, map);
     return hipGetLastError();
 }
 template <bool BATCH>
 static hipError_t fluid_kinds(hipStream_t s, int kinds, const void *rho, const void *u, const float *F, void *rho_o,
-                              void *u_o, StepConst c, const PipeStep *tab, const BlockMap *map, int nblocks) {
+                              void *u_o, void *u_copy, StepConst c, const PipeStep *tab, const BlockMap *map,
+                              int nblocks) {
     const int kr = kinds & 15, ku = (kinds >> 4) & 15;
     if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32)
-        return fluid_t<float, float, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+        return fluid_t<float, float, BATCH>(s, rho, u, F, rho_o, u_o, u_copy, c, tab, map, nblocks);
     if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16)
-        return fluid_t<__half, __half, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+        return fluid_t<__half, __half, BATCH>(s, rho, u, F, rho_o, u_o, u_copy, c, tab, map, nblocks);
     if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16)
-        return fluid_t<__half, __hip_bfloat16, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+        return fluid_t<__half, __hip_bfloat16, BATCH>(s, rho, u, F, rho_o, u_o, u_copy, c, tab, map, nblocks);
     if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16)
-        return fluid_t<__hip_bfloat16, __hip_bfloat16, BATCH>(s, rho, u, F, rho_o, u_o, c, tab, map, nblocks);
+        return fluid_t<__hip_bfloat16, __hip_bfloat16, BATCH>(s, rho, u, F, rho_o, u_o, u_copy, c, tab, map,
+                                                              nblocks);
     return hipErrorInvalidValue;
 }
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F, void *rho_o,
-                        void *u_o, StepConst c) {
-    return fluid_kinds<false>(s, kinds, rho, u, F, rho_o, u_o, c, nullptr, nullptr, 0);
+                        void *u_o, void *u_copy, StepConst c) {
+    return fluid_kinds<false>(s, kinds, rho, u, F, rho_o, u_o, u_copy, c, nullptr, nullptr, 0);
 }
 hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks) {
-    return fluid_kinds<true>(s, kinds, nullptr, nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map, nblocks);
+    return fluid_kinds<true>(s, kinds, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map,
+                             nblocks);
 }
 
 template <typename T>
@@ -701,26 +761,29 @@ hipError_t launch_flow_partial_batch(hipStream_t s, int kind_u, const PipeStep *
 }
 
 template <typename TR, typename TU, typename TB>
-static hipError_t budget_t(hipStream_t s, const void *rho, const void *u, const void *b, const float *bext,
-                           DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
+static hipError_t budget_t(hipStream_t s, const void *rho, const void *u, const void *b, const void *bh,
+                           const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
     hipLaunchKernelGGL((k_budget_partial<TR, TU, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const TR *)rho,
-                       (const TU *)u, (const TB *)b, bext, part, c);
+                       (const TU *)u, (const TB *)b, (const TB *)bh, bext, part, c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(kRedThreads), 0, s, part, ctrl, ring, c);
     return hipGetLastError();
 }
-hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b, const float *bext,
-                         DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
+hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b, const void *b_hi,
+                         const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
     const int kr = kinds & 15, ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
     if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
-        return budget_t<float, float, float>(s, rho, u, b, bext, ctrl, part, ring, c);
+        return budget_t<float, float, float>(s, rho, u, b, nullptr, bext, ctrl, part, ring, c);
+    if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)
+        return budget_t<float, float, __half>(s, rho, u, b, b_hi, bext, ctrl, part, ring, c);
     if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
-        return budget_t<__half, __half, __half>(s, rho, u, b, bext, ctrl, part, ring, c);
+        return budget_t<__half, __half, __half>(s, rho, u, b, nullptr, bext, ctrl, part, ring, c);
     if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
-        return budget_t<__half, __hip_bfloat16, __half>(s, rho, u, b, bext, ctrl, part, ring, c);
+        return budget_t<__half, __hip_bfloat16, __half>(s, rho, u, b, nullptr, bext, ctrl, part, ring, c);
     if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
-        return budget_t<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>(s, rho, u, b, bext, ctrl, part, ring, c);
+        return budget_t<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>(s, rho, u, b, nullptr, bext, ctrl, part, ring,
+                                                                         c);
     return hipErrorInvalidValue;
 }
 
@@ -742,6 +805,12 @@ static hipError_t load_t(hipStream_t s, const void *src, float *dst, int64_t n) 
 }
 hipError_t launch_load_kind(hipStream_t s, int kind, const void *src, float *dst, int64_t n) {
     MHD_DISPATCH1(kind, load_t, s, src, dst, n)
+}
+
+hipError_t launch_store_split(hipStream_t s, const float *src, void *hi, void *lo, int64_t n) {
+    hipLaunchKernelGGL(k_store_split, dim3((unsigned)std::min<int64_t>(blocks_for(n, 256), 65536)), dim3(256), 0, s,
+                       src, (__half *)hi, (__half *)lo, n);
+    return hipGetLastError();
 }
 
 }  // namespace mhd

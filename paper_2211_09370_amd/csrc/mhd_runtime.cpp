@@ -41,6 +41,7 @@ mhd_status fail(mhd_status st, const char *fmt, ...) {
     } while (0)
 
 size_t kind_bytes(int k) { return k == MHD_STORE_F32 ? 4 : 2; }
+bool is_split(const mhd_grid_desc &g) { return g.b_storage == MHD_STORE_F16_SPLIT; }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -49,7 +50,7 @@ constexpr int64_t kBandSlots = 64;
 
 // Byte offsets of every region of the caller's workspace.
 struct Layout {
-    size_t rho[2], u[2], b[2], F, bext, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
+    size_t rho[2], u[2], b[2], bh[2], u16, F, bext, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
     size_t band_cell, band_mk, band_w, red_part, flow_part, ring, total;
 };
 
@@ -67,6 +68,10 @@ Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     for (int i = 0; i < 2; ++i) L.rho[i] = take(N * kind_bytes(g.rho_storage));
     for (int i = 0; i < 2; ++i) L.u[i] = take(3 * N * kind_bytes(g.u_storage));
     for (int i = 0; i < 2; ++i) L.b[i] = take(3 * N * kind_bytes(g.b_storage));
+    if (is_split(g)) {  // hi parts of b and the float16 copy of u
+        for (int i = 0; i < 2; ++i) L.bh[i] = take(3 * N * 2);
+        L.u16 = take(3 * N * 2);
+    }
     L.F = take(3 * N * sizeof(float));
     L.bext = take(3 * (size_t)g.nx * sizeof(float));
     L.ctrl = take(sizeof(DevCtrl));
@@ -93,15 +98,15 @@ mhd_status check_desc(const mhd_grid_desc *g) {
     const int64_t N = (int64_t)g->nx * g->ny * g->nz;
     if (3 * N >= (int64_t)1 << 31) return fail(MHD_ERR_INVALID_ARG, "3*nx*ny*nz must stay below 2^31");
     for (int k : {g->rho_storage, g->u_storage, g->b_storage})
-        if (k < MHD_STORE_F32 || k > MHD_STORE_BF16) return fail(MHD_ERR_INVALID_ARG, "unknown storage kind %d", k);
+        if (k < MHD_STORE_F32 || k > MHD_STORE_F16_SPLIT) return fail(MHD_ERR_INVALID_ARG, "unknown storage kind %d", k);
     const int r = g->rho_storage, u = g->u_storage, b = g->b_storage;
     const bool ok = (r == 0 && u == 0 && b == 0) || (r == 1 && u == 1 && b == 1) || (r == 1 && u == 2 && b == 1) ||
-                    (r == 2 && u == 2 && b == 2);
+                    (r == 2 && u == 2 && b == 2) || (r == 0 && u == 0 && b == 3);
     if (!ok)
         return fail(MHD_ERR_UNSUPPORTED,
-                    "storage mix (rho %d, u %d, b %d) not built: use all f32, f16/f16/f16, f16/bf16/f16 or all bf16", r,
-                    u, b);
-    if (u != 0 && !(g->u_scale > 0.0)) return fail(MHD_ERR_INVALID_ARG, "u_scale must be > 0 for 16-bit u");
+                    "storage mix (rho %d, u %d, b %d) not built: use all f32, f16/f16/f16, f16/bf16/f16, all bf16 or "
+                    "f32/f32/f16-split", r, u, b);
+    if ((u != 0 || b == 3) && !(g->u_scale > 0.0)) return fail(MHD_ERR_INVALID_ARG, "u_scale must be > 0 for 16-bit u");
     if (b != 0 && !(g->b_scale > 0.0)) return fail(MHD_ERR_INVALID_ARG, "b_scale must be > 0 for 16-bit b");
     return MHD_OK;
 }
@@ -136,8 +141,8 @@ struct mhd_sim {
     char *ws = nullptr;
     Layout L{};
     int kinds = 0;
-    // ping-pong state
-    int cr = 0, cu = 0, cb = 0;
+    // ping-pong state (ch: hi part of b in the split form)
+    int cr = 0, cu = 0, cb = 0, ch = 0;
     // host state
     bool have_params = false;
     mhd_params prm{};
@@ -160,6 +165,9 @@ struct mhd_sim {
     void *rho(int i) const { return ws + L.rho[i]; }
     void *u(int i) const { return ws + L.u[i]; }
     void *b(int i) const { return ws + L.b[i]; }
+    bool split() const { return g.b_storage == MHD_STORE_F16_SPLIT; }
+    void *bh(int i) const { return split() ? ws + L.bh[i] : nullptr; }
+    void *u16() const { return split() ? ws + L.u16 : nullptr; }
     DevCtrl *ctrl() const { return at<DevCtrl>(L.ctrl); }
 };
 
@@ -179,6 +187,8 @@ StepConst step_const(const mhd_sim *s) {
     c.inv_u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.u_scale);
     c.b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.b_scale;
     c.inv_b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.b_scale);
+    c.copy_scale = s->split() ? (float)s->g.u_scale : 1.0f;
+    c.inv_copy_scale = s->split() ? (float)(1.0 / s->g.u_scale) : 1.0f;
     c.nu = p.nu;
     c.eta = p.eta;
     c.G0 = p.G0;
@@ -260,7 +270,18 @@ mhd_status fill_field(mhd_sim *s, mhd_field f, const double *host, bool zero) {
     for (int64_t i = 0; i < n; ++i) tmp[i] = zero ? 0.f : (float)((host[i] - offset) / scale);
     float *stage = s->at<float>(s->L.F);  // 3N floats, free between steps
     HIPCHK(hipMemcpyAsync(stage, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(launch_store_kind(s->stream, kind, stage, dst, n));
+    if (f == MHD_FIELD_B_INDUCED && s->split()) {
+        HIPCHK(launch_store_split(s->stream, stage, s->bh(s->ch), dst, n));
+    } else {
+        HIPCHK(launch_store_kind(s->stream, kind, stage, dst, n));
+    }
+    if (f == MHD_FIELD_U && s->split()) {  // float16 copy u / u_scale read by the sweeps
+        HIPCHK(hipStreamSynchronize(s->stream));
+        const double inv = 1.0 / s->g.u_scale;
+        for (int64_t i = 0; i < n; ++i) tmp[i] = zero ? 0.f : (float)(host[i] * inv);
+        HIPCHK(hipMemcpyAsync(stage, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, s->stream));
+        HIPCHK(launch_store_kind(s->stream, MHD_STORE_F16, stage, s->u16(), n));
+    }
     HIPCHK(hipStreamSynchronize(s->stream));
     return MHD_OK;
 }
@@ -296,9 +317,12 @@ mhd_status timed(mhd_sim *s, int k, const char *what, Fn fn) {
     } while (0)
 
 mhd_status ib_correct(mhd_sim *s, int kind, void *phi, float scale, float inv_scale, const float *sj,
-                      const float *wall) {
+                      const float *wall, const void *phi_hi, void *copy, float copy_inv) {
     if (s->M == 0) return MHD_OK;
     IbArgs a;
+    a.phi_hi = phi_hi;
+    a.copy = copy;
+    a.copy_inv = copy_inv;
     a.N = s->N;
     a.M = (int)s->M;
     a.nband = (int)s->nband;
@@ -324,28 +348,35 @@ mhd_status one_step(mhd_sim *s) {
     for (int m = 0; m < s->prm.n_mag; ++m) {
         const int nb = 1 - s->cb;
         {  // timed by events the launch stamps at kernel start / end
+            SweepArgs a = make_sweep_args(s->split() ? s->u16() : s->u(s->cu), s->b(s->cb), s->b(nb),
+                                          s->at<float>(s->L.bext), c, s->sweep);
+            if (s->split()) {  // first sweep of the step re-splits b into a new hi and lo
+                a.u_scale = c.copy_scale;
+                a.bh = s->bh(s->ch);
+                if (m == 0) a.bho = s->bh(1 - s->ch);
+            }
             Event2 *e = s->prof ? &next_event(s, MHD_K_MAG_SWEEP) : nullptr;
-            const hipError_t err = launch_mag_sweep(st, s->kinds, s->u(s->cu), s->b(s->cb), s->b(nb),
-                                                    s->at<float>(s->L.bext), c, s->sweep, e ? e->a : nullptr,
-                                                    e ? e->b : nullptr);
+            const hipError_t err = launch_mag_sweep(st, s->kinds, a, s->sweep, e ? e->a : nullptr, e ? e->b : nullptr);
             if (err != hipSuccess) return fail(MHD_ERR_HIP, "launch of mag_sweep failed: %s", hipGetErrorString(err));
+            if (s->split() && m == 0) s->ch = 1 - s->ch;
         }
         STEPCHK(ib_correct(s, s->g.b_storage, s->b(nb), c.b_scale, c.inv_b_scale, s->at<float>(s->L.s_b),
-                           s->at<float>(s->L.bwall)));
+                           s->at<float>(s->L.bwall), s->bh(s->ch), nullptr, 0.f));
         s->cb = nb;
     }
     // 2. Lorentz + body force from the new b
     float *F = s->at<float>(s->L.F);
     STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
-        return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->at<float>(s->L.bext), s->ctrl(), F, c);
+        return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->bh(s->ch), s->at<float>(s->L.bext), s->ctrl(), F,
+                              c);
     }));
     // 3. fluid predictor, 4. velocity wall correction
     const int nr = 1 - s->cr, nu = 1 - s->cu;
     STEPCHK(timed(s, MHD_K_FLUID, "fluid", [&] {
-        return launch_fluid(st, s->kinds, s->rho(s->cr), s->u(s->cu), F, s->rho(nr), s->u(nu), c);
+        return launch_fluid(st, s->kinds, s->rho(s->cr), s->u(s->cu), F, s->rho(nr), s->u(nu), s->u16(), c);
     }));
     STEPCHK(ib_correct(s, s->g.u_storage, s->u(nu), c.u_scale, c.inv_u_scale, s->at<float>(s->L.s_u),
-                       s->at<float>(s->L.uwall)));
+                       s->at<float>(s->L.uwall), nullptr, s->u16(), c.inv_copy_scale));
     s->cr = nr;
     s->cu = nu;
     // 5. flow-rate control sum (float64, fixed order) and step counter
@@ -362,8 +393,9 @@ mhd_status one_step(mhd_sim *s) {
 mhd_status record_budget(mhd_sim *s) {
     const StepConst c = step_const(s);
     return timed(s, MHD_K_BUDGET, "budget", [&] {
-        return launch_budget(s->stream, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->at<float>(s->L.bext),
-                             s->ctrl(), s->at<double>(s->L.red_part), s->at<mhd_budget>(s->L.ring), c);
+        return launch_budget(s->stream, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->bh(s->ch),
+                             s->at<float>(s->L.bext), s->ctrl(), s->at<double>(s->L.red_part),
+                             s->at<mhd_budget>(s->L.ring), c);
     });
 }
 
@@ -679,6 +711,12 @@ mhd_status mhd_get_field(mhd_sim *s, mhd_field f, double *host) {
     HIPCHK(hipMemcpyAsync(tmp.data(), stage, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     for (int64_t i = 0; i < n; ++i) host[i] = (double)tmp[i] * scale + offset;
+    if (f == MHD_FIELD_B_INDUCED && s->split()) {  // b = (hi + lo) b_scale
+        HIPCHK(launch_load_kind(s->stream, MHD_STORE_F16, s->bh(s->ch), stage, n));
+        HIPCHK(hipMemcpyAsync(tmp.data(), stage, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        for (int64_t i = 0; i < n; ++i) host[i] += (double)tmp[i] * scale;
+    }
     DevCtrl h;
     STEPCHK(read_ctrl(s, &h));
     if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a budget pass found non-finite values or |u| >= c_s");
@@ -980,6 +1018,9 @@ mhd_status build_plan(mhd_batch *b) {
 
 IbArgs ib_args(mhd_sim *s, const float *sj, const float *wall) {
     IbArgs a;
+    a.phi_hi = nullptr;
+    a.copy = nullptr;
+    a.copy_inv = 0.f;
     a.N = s->N;
     a.M = (int)s->M;
     a.nband = (int)s->nband;
@@ -1002,13 +1043,26 @@ PipeStep pipe_step(mhd_sim *s) {
     const StepConst c = step_const(s);
     const SweepLaunch e = effective_tiles(s->sweep, s->g.nx);
     const float *bext = s->at<float>(s->L.bext);
-    const int cb = s->cb, cu = s->cu, cr = s->cr;
-    q.sw[0] = make_sweep_args(s->u(cu), s->b(cb), s->b(1 - cb), bext, c, e);
-    q.sw[1] = make_sweep_args(s->u(cu), s->b(1 - cb), s->b(cb), bext, c, e);
-    const IbArgs ab = ib_args(s, s->at<float>(s->L.s_b), s->at<float>(s->L.bwall));
+    const int cb = s->cb, cu = s->cu, cr = s->cr, ch = s->ch;
+    const void *us = s->split() ? s->u16() : s->u(cu);
+    q.sw[0] = make_sweep_args(us, s->b(cb), s->b(1 - cb), bext, c, e);
+    q.sw[1] = make_sweep_args(us, s->b(1 - cb), s->b(cb), bext, c, e);
+    q.sw[2] = q.sw[0];
+    if (s->split()) {  // round 0 re-splits hi(ch) -> hi(1 - ch); later rounds read the new hi
+        for (auto &w : q.sw) {
+            w.u_scale = c.copy_scale;
+            w.bh = s->bh(1 - ch);
+        }
+        q.sw[0].bh = s->bh(ch);
+        q.sw[0].bho = s->bh(1 - ch);
+    }
+    IbArgs ab = ib_args(s, s->at<float>(s->L.s_b), s->at<float>(s->L.bwall));
+    ab.phi_hi = s->bh(1 - ch);
     q.ib[0] = ab;
     q.ib[1] = ab;
     q.ib[2] = ib_args(s, s->at<float>(s->L.s_u), s->at<float>(s->L.uwall));
+    q.ib[2].copy = s->u16();
+    q.ib[2].copy_inv = c.inv_copy_scale;
     q.phi[0] = s->b(1 - cb);
     q.phi[1] = s->b(cb);
     q.phi[2] = s->u(1 - cu);
@@ -1017,6 +1071,8 @@ PipeStep pipe_step(mhd_sim *s) {
     q.scale[2] = c.u_scale;
     q.inv_scale[2] = c.inv_u_scale;
     q.b_last = s->b((s->prm.n_mag & 1) ? 1 - cb : cb);
+    q.b_hi = s->split() ? s->bh(1 - ch) : nullptr;
+    q.u_copy = s->u16();
     q.bext = bext;
     q.ctrl = s->ctrl();
     q.F = s->at<float>(s->L.F);
@@ -1032,7 +1088,8 @@ PipeStep pipe_step(mhd_sim *s) {
 
 std::vector<int> buffer_sig(const mhd_batch *b) {
     std::vector<int> v(b->n);
-    for (int i = 0; i < b->n; ++i) v[i] = b->pipes[i]->cr | (b->pipes[i]->cu << 1) | (b->pipes[i]->cb << 2);
+    for (int i = 0; i < b->n; ++i)
+        v[i] = b->pipes[i]->cr | (b->pipes[i]->cu << 1) | (b->pipes[i]->cb << 2) | (b->pipes[i]->ch << 3);
     return v;
 }
 
@@ -1072,7 +1129,8 @@ mhd_status issue_step(mhd_batch *b, int k) {
             if (nb == 0) continue;
             Event2 *e = nullptr;
             if (b->prof && !(e = next_event_b(b, MHD_K_MAG_SWEEP))) return fail(MHD_ERR_HIP, "hipEventCreate failed");
-            const hipError_t err = launch_mag_sweep_batch(st, b->kinds, g.L, tab, map + g.map_base, r & 1, (int)nb,
+            const int which = r == 0 ? 0 : (r & 1) ? 1 : 2;
+            const hipError_t err = launch_mag_sweep_batch(st, b->kinds, g.L, tab, map + g.map_base, which, (int)nb,
                                                           e ? e->a : nullptr, e ? e->b : nullptr);
             if (err != hipSuccess) return fail(MHD_ERR_HIP, "batched launch of mag_sweep failed: %s", hipGetErrorString(err));
         }
@@ -1344,6 +1402,7 @@ mhd_status mhd_batch_step(mhd_batch *b, int64_t n_steps, int32_t budget_every) {
         }
         for (auto *s : b->pipes) {
             if (s->prm.n_mag & 1) s->cb = 1 - s->cb;
+            if (s->split()) s->ch = 1 - s->ch;
             s->cr = 1 - s->cr;
             s->cu = 1 - s->cu;
             s->t_host += 1;

@@ -29,10 +29,20 @@ namespace mhd {
 // D_y likewise and D_z[f](z) = P1(z-1) - P1(z+1); then
 //   b*_x = avg b_x + D_y Lxy + D_z Lxz,  b*_y = avg b_y - D_x Lxy + D_z Lyz,
 //   b*_z = avg b_z - D_x Lxz - D_y Lyz.
+//
+// Units: the sweep works on stored values (b / b_scale, u / u_scale), with B_ext divided by
+// b_scale once per workgroup and kappa multiplied by u_scale, which keeps the same map (it is
+// linear in (b, B_ext)) and leaves no per-value scaling: staging and output are plain
+// conversions and additions (float32 storage has both scales 1).
+//
+// SPLIT: b is held as two float16 arrays, b = (hi + lo) b_scale. hi is fixed within a fluid
+// step; the sweep stages hi + lo and writes lo* = lo + increment, so the 16-bit rounding is
+// relative to lo, not to b. The first sweep of a step (a.bho set) re-splits v = hi + lo +
+// increment into a new hi = fp16(v) and lo = fp16(v - hi).
 // -------------------------------------------------------------------------------------------
-template <int TX, int TY, typename TU, typename TB, bool BATCH>
+template <int TX, int TY, typename TU, typename TB, bool BATCH, bool SPLIT>
 __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeStep *tab, const BlockMap *map,
-                                                      int parity, int nbatch) {
+                                                      int which, int nbatch) {
     constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
     constexpr int NSLOT = (HN + NT - 1) / NT;
     // two LDS planes: the next plane is staged while the current one is reduced
@@ -45,7 +55,7 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
     if constexpr (BATCH) {
         if (lb >= nbatch) return;
         const BlockMap m = map[lb];
-        a = tab[m.pipe].sw[parity];
+        a = tab[m.pipe].sw[which];
         lb = m.local;
     } else {
         if (lb >= a.nblocks) return;
@@ -64,6 +74,8 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
     const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * (size_t)N;
     const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * (size_t)N;
     TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * (size_t)N;
+    const TB *bh0 = (const TB *)a.bh, *bh1 = bh0 + N, *bh2 = bh0 + 2 * (size_t)N;  // SPLIT: hi part
+    const bool resplit = SPLIT && a.bho != nullptr;
 
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -81,15 +93,16 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
         const int hx = i % HX, hy = i / HX;
         const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
         sxy[s] = (unsigned)(hxg + nx * hyg);
-        sbe[s][0] = sval[s] ? a.bext[hxg] : 0.f;
-        sbe[s][1] = sval[s] ? a.bext[nx + hxg] : 0.f;
-        sbe[s][2] = sval[s] ? a.bext[2 * nx + hxg] : 0.f;
+        sbe[s][0] = sval[s] ? a.bext[hxg] * a.inv_b_scale : 0.f;
+        sbe[s][1] = sval[s] ? a.bext[nx + hxg] * a.inv_b_scale : 0.f;
+        sbe[s][2] = sval[s] ? a.bext[2 * nx + hxg] * a.inv_b_scale : 0.f;
     }
 
     // raw stored values of the next plane: converted only when they are written to LDS, so the
     // loads stay in flight while the current plane is reduced
     TU ru[NSLOT][3];
     TB rb[NSLOT][3];
+    TB rh[NSLOT][3];
     auto load_plane = [&](int p) {
         const unsigned off = (unsigned)wrapi(p, nz) * plane;
 #pragma unroll
@@ -103,12 +116,17 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
                 rb[s][0] = ld_off(b0, kb);
                 rb[s][1] = ld_off(b1, kb);
                 rb[s][2] = ld_off(b2, kb);
+                if constexpr (SPLIT) {
+                    rh[s][0] = ld_off(bh0, kb);
+                    rh[s][1] = ld_off(bh1, kb);
+                    rh[s][2] = ld_off(bh2, kb);
+                }
             }
         }
     };
 
     const int c0 = (ly + 1) * HX + (lx + 1);
-    const float kap = a.kappa;
+    const float kap = a.kappa * a.u_scale;
     constexpr float W6 = 1.0f / 6.0f;  // WF + 4 WE: weight of a neighbouring plane as a whole
     // running sums of the plane contributions (difference form), and the column's own values
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
@@ -123,15 +141,20 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
         for (int s = 0; s < NSLOT; ++s) {
             if (sval[s]) {
                 const int i = tid + s * NT;
-                const float bx = St<TB>::val(rb[s][0], a.b_scale);
-                const float by = St<TB>::val(rb[s][1], a.b_scale);
-                const float bz = St<TB>::val(rb[s][2], a.b_scale);
+                float bx = St<TB>::cvt(rb[s][0]);
+                float by = St<TB>::cvt(rb[s][1]);
+                float bz = St<TB>::cvt(rb[s][2]);
+                if constexpr (SPLIT) {
+                    bx += St<TB>::cvt(rh[s][0]);
+                    by += St<TB>::cvt(rh[s][1]);
+                    bz += St<TB>::cvt(rh[s][2]);
+                }
                 const float Bx = bx + sbe[s][0];
                 const float By = by + sbe[s][1];
                 const float Bz = bz + sbe[s][2];
-                const float ux = St<TU>::val(ru[s][0], a.u_scale);
-                const float uy = St<TU>::val(ru[s][1], a.u_scale);
-                const float uz = St<TU>::val(ru[s][2], a.u_scale);
+                const float ux = St<TU>::cvt(ru[s][0]);
+                const float uy = St<TU>::cvt(ru[s][1]);
+                const float uz = St<TU>::cvt(ru[s][2]);
                 s_pl[S][0][i] = bx;
                 s_pl[S][1][i] = by;
                 s_pl[S][2][i] = bz;
@@ -158,6 +181,22 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
         if (p < z1) {
             stage(Q{});
             if (p + 2 <= z1) load_plane(p + 2);
+        }
+        // SPLIT: the stored lo (and, re-splitting, hi) of this column's output cell, requested
+        // now and used after the reduction
+        const unsigned ko = ((unsigned)(p - 1) * plane + (unsigned)(gx + nx * gy)) * (unsigned)sizeof(TB);
+        TB lc[3], hc[3];
+        if constexpr (SPLIT) {
+            if (own && p >= z0 + 1) {
+                lc[0] = ld_off(b0, ko);
+                lc[1] = ld_off(b1, ko);
+                lc[2] = ld_off(b2, ko);
+                if (resplit) {
+                    hc[0] = ld_off(bh0, ko);
+                    hc[1] = ld_off(bh1, ko);
+                    hc[2] = ld_off(bh2, ko);
+                }
+            }
         }
         const int cur = P;
         const float *s_bx = s_pl[cur][0], *s_by = s_pl[cur][1], *s_bz = s_pl[cur][2];
@@ -219,10 +258,27 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
                 const float d0 = (acc0 + C0) + W6 * ((cm0 - cc0) + (c_x - cc0));
                 const float d1 = (acc1 + C1) + W6 * ((cm1 - cc1) + (c_y - cc1));
                 const float d2 = (acc2 + A2) + W6 * ((cm2 - cc2) + (c_z - cc2));
-                const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(gx + nx * gy)) * (unsigned)sizeof(TB);
-                st_off(o0, k, St<TB>::from(cc0 + d0, a.inv_b_scale));
-                st_off(o1, k, St<TB>::from(cc1 + d1, a.inv_b_scale));
-                st_off(o2, k, St<TB>::from(cc2 + d2, a.inv_b_scale));
+                if constexpr (SPLIT) {
+                    const float d[3] = {d0, d1, d2};
+                    TB *oo[3] = {o0, o1, o2};
+                    TB *ho = (TB *)a.bho;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const float lo = St<TB>::cvt(lc[q]);
+                        if (resplit) {
+                            const float v = (St<TB>::cvt(hc[q]) + lo) + d[q];
+                            const TB hi = St<TB>::from(v, 1.0f);
+                            st_off(ho + q * (size_t)N, ko, hi);
+                            st_off(oo[q], ko, St<TB>::from(v - St<TB>::cvt(hi), 1.0f));
+                        } else {
+                            st_off(oo[q], ko, St<TB>::from(lo + d[q], 1.0f));
+                        }
+                    }
+                } else {
+                    st_off(o0, ko, St<TB>::from(cc0 + d0, 1.0f));
+                    st_off(o1, ko, St<TB>::from(cc1 + d1, 1.0f));
+                    st_off(o2, ko, St<TB>::from(cc2 + d2, 1.0f));
+                }
             }
             acc0 = ap0 + B0;
             acc1 = ap1 + B1;
@@ -282,9 +338,9 @@ struct Pair<__hip_bfloat16> {
     }
 };
 
-template <int TY, typename TU, typename TB, bool BATCH>
+template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT>
 __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
-                                                            int parity, int nbatch) {
+                                                            int which, int nbatch) {
     constexpr int HY = TY + 2;        // staged rows
     constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
     constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
@@ -295,7 +351,7 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     if constexpr (BATCH) {
         if (lb >= nbatch) return;
         const BlockMap m = map[lb];
-        a = tab[m.pipe].sw[parity];
+        a = tab[m.pipe].sw[which];
         lb = m.local;
     } else {
         if (lb >= a.nblocks) return;
@@ -313,6 +369,8 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const TU *u0 = (const TU *)a.u, *u1 = u0 + N, *u2 = u0 + 2 * (size_t)N;
     const TB *b0 = (const TB *)a.b, *b1 = b0 + N, *b2 = b0 + 2 * (size_t)N;
     TB *o0 = (TB *)a.bo, *o1 = o0 + N, *o2 = o0 + 2 * (size_t)N;
+    const TB *bh0 = (const TB *)a.bh, *bh1 = bh0 + N, *bh2 = bh0 + 2 * (size_t)N;  // SPLIT: hi part
+    const bool resplit = SPLIT && a.bho != nullptr;
     using PU = Pair<TU>;
     using PB = Pair<TB>;
     using RU = typename PU::raw;
@@ -323,10 +381,11 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const int xa = x0 + 2 * l;            // this lane's cells: xa, xa + 1 (always inside: nx % 128 == 0)
     const int gy = y0 + w;
     const bool own = gy < ny;
-    const float kap = a.kappa;
-    // B_ext of this lane's pair of columns and of the two halo columns
-    const float bea[3] = {a.bext[xa], a.bext[nx + xa], a.bext[2 * nx + xa]};
-    const float beb[3] = {a.bext[xa + 1], a.bext[nx + xa + 1], a.bext[2 * nx + xa + 1]};
+    const float kap = a.kappa * a.u_scale;
+    const float ib = a.inv_b_scale;
+    // B_ext / b_scale of this lane's pair of columns and of the two halo columns
+    const float bea[3] = {a.bext[xa] * ib, a.bext[nx + xa] * ib, a.bext[2 * nx + xa] * ib};
+    const float beb[3] = {a.bext[xa + 1] * ib, a.bext[nx + xa + 1] * ib, a.bext[2 * nx + xa + 1] * ib};
 
     // row loads: round r stages row hy = w + r * TY (if < HY) at columns xa, xa + 1
     unsigned rowoff[NR];
@@ -343,12 +402,14 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
     const unsigned hoff = (unsigned)(hx + nx * wrapi(y0 - 1 + min(hhy, HY - 1), ny));
     const int hidx = min(hhy, HY - 1) * RS + (hside ? 129 : 0);
-    const float hbe[3] = {a.bext[hx], a.bext[nx + hx], a.bext[2 * nx + hx]};
+    const float hbe[3] = {a.bext[hx] * ib, a.bext[nx + hx] * ib, a.bext[2 * nx + hx] * ib};
 
     RU ru[NR][3];
     RB rb[NR][3];
+    RB rq[NR][3];  // SPLIT: hi part of the rows
     TU hu[3];
     TB hb[3];
+    TB hq[3];      // SPLIT: hi part of the halo column
     auto load_plane = [&](int p) {
         const unsigned off = (unsigned)wrapi(p, nz) * plane;
 #pragma unroll
@@ -362,6 +423,11 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                 rb[r][0] = ld_off(reinterpret_cast<const RB *>(b0), kb);
                 rb[r][1] = ld_off(reinterpret_cast<const RB *>(b1), kb);
                 rb[r][2] = ld_off(reinterpret_cast<const RB *>(b2), kb);
+                if constexpr (SPLIT) {
+                    rq[r][0] = ld_off(reinterpret_cast<const RB *>(bh0), kb);
+                    rq[r][1] = ld_off(reinterpret_cast<const RB *>(bh1), kb);
+                    rq[r][2] = ld_off(reinterpret_cast<const RB *>(bh2), kb);
+                }
             }
         }
         if (hval) {
@@ -372,6 +438,11 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
             hb[0] = ld_off(b0, kb);
             hb[1] = ld_off(b1, kb);
             hb[2] = ld_off(b2, kb);
+            if constexpr (SPLIT) {
+                hq[0] = ld_off(bh0, kb);
+                hq[1] = ld_off(bh1, kb);
+                hq[2] = ld_off(bh2, kb);
+            }
         }
     };
     auto put = [&](int buf, int idx, float bx, float by, float bz, float ux, float uy, float uz, const float *be) {
@@ -389,16 +460,32 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
         for (int r = 0; r < NR; ++r) {
             if (rowval[r]) {
                 const int idx = (w + r * TY) * RS + 1 + 2 * l;
-                const float us = a.u_scale, bs = a.b_scale;
-                put(S, idx, PB::lo(rb[r][0], bs), PB::lo(rb[r][1], bs), PB::lo(rb[r][2], bs), PU::lo(ru[r][0], us),
-                    PU::lo(ru[r][1], us), PU::lo(ru[r][2], us), bea);
-                put(S, idx + 1, PB::hi(rb[r][0], bs), PB::hi(rb[r][1], bs), PB::hi(rb[r][2], bs), PU::hi(ru[r][0], us),
-                    PU::hi(ru[r][1], us), PU::hi(ru[r][2], us), beb);
+                constexpr float us = 1.0f, bs = 1.0f;  // stored units
+                float b[2][3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    b[0][q] = PB::lo(rb[r][q], bs);
+                    b[1][q] = PB::hi(rb[r][q], bs);
+                    if constexpr (SPLIT) {
+                        b[0][q] += PB::lo(rq[r][q], bs);
+                        b[1][q] += PB::hi(rq[r][q], bs);
+                    }
+                }
+                put(S, idx, b[0][0], b[0][1], b[0][2], PU::lo(ru[r][0], us), PU::lo(ru[r][1], us),
+                    PU::lo(ru[r][2], us), bea);
+                put(S, idx + 1, b[1][0], b[1][1], b[1][2], PU::hi(ru[r][0], us), PU::hi(ru[r][1], us),
+                    PU::hi(ru[r][2], us), beb);
             }
         }
-        if (hval)
-            put(S, hidx, St<TB>::val(hb[0], a.b_scale), St<TB>::val(hb[1], a.b_scale), St<TB>::val(hb[2], a.b_scale),
-                St<TU>::val(hu[0], a.u_scale), St<TU>::val(hu[1], a.u_scale), St<TU>::val(hu[2], a.u_scale), hbe);
+        if (hval) {
+            float b[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                b[q] = St<TB>::cvt(hb[q]);
+                if constexpr (SPLIT) b[q] += St<TB>::cvt(hq[q]);
+            }
+            put(S, hidx, b[0], b[1], b[2], St<TU>::cvt(hu[0]), St<TU>::cvt(hu[1]), St<TU>::cvt(hu[2]), hbe);
+        }
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
@@ -416,6 +503,21 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
         if (p < z1) {
             stage(Q{});
             if (p + 2 <= z1) load_plane(p + 2);
+        }
+        // SPLIT: stored lo (and, re-splitting, hi) of the output pair, requested now
+        const unsigned ko = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);
+        RB lc[3], hc[3];
+        if constexpr (SPLIT) {
+            if (own && p >= z0 + 1) {
+                lc[0] = ld_off(reinterpret_cast<const RB *>(b0), ko);
+                lc[1] = ld_off(reinterpret_cast<const RB *>(b1), ko);
+                lc[2] = ld_off(reinterpret_cast<const RB *>(b2), ko);
+                if (resplit) {
+                    hc[0] = ld_off(reinterpret_cast<const RB *>(bh0), ko);
+                    hc[1] = ld_off(reinterpret_cast<const RB *>(bh1), ko);
+                    hc[2] = ld_off(reinterpret_cast<const RB *>(bh2), ko);
+                }
+            }
         }
         if (own) {
             // per field: rows y-1, y, y+1 at columns xa-1 .. xa+2 (two aligned 8-byte reads per
@@ -503,9 +605,14 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 // output plane p-1: b* = b_c + increment (differences only); C2 = A2
-                out[e][0] = cc[e][0] + ((acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0])));
-                out[e][1] = cc[e][1] + ((acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1])));
-                out[e][2] = cc[e][2] + ((acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2])));
+                out[e][0] = (acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0]));
+                out[e][1] = (acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1]));
+                out[e][2] = (acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2]));
+                if constexpr (!SPLIT) {
+                    out[e][0] += cc[e][0];
+                    out[e][1] += cc[e][1];
+                    out[e][2] += cc[e][2];
+                }
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     acc[e][q] = ap[e][q] + B[e][q];
@@ -515,10 +622,29 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                 }
             }
             if (p >= z0 + 1) {
-                const unsigned k = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);
-                st_off(reinterpret_cast<RB *>(o0), k, PB::make(out[0][0], out[1][0], a.inv_b_scale));
-                st_off(reinterpret_cast<RB *>(o1), k, PB::make(out[0][1], out[1][1], a.inv_b_scale));
-                st_off(reinterpret_cast<RB *>(o2), k, PB::make(out[0][2], out[1][2], a.inv_b_scale));
+                RB *oo[3] = {reinterpret_cast<RB *>(o0), reinterpret_cast<RB *>(o1), reinterpret_cast<RB *>(o2)};
+                if constexpr (SPLIT) {
+                    // out holds the increments: lo* = lo + increment, or a re-split of hi + lo + increment
+                    RB *ho = reinterpret_cast<RB *>(a.bho);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        constexpr float bs = 1.0f, inv = 1.0f;  // stored units
+                        const float l0 = PB::lo(lc[q], bs), l1 = PB::hi(lc[q], bs);
+                        if (resplit) {
+                            const float v0 = (PB::lo(hc[q], bs) + l0) + out[0][q];
+                            const float v1 = (PB::hi(hc[q], bs) + l1) + out[1][q];
+                            const RB hn = PB::make(v0, v1, inv);
+                            st_off(ho + q * (size_t)(N / 2), ko, hn);
+                            st_off(oo[q], ko, PB::make(v0 - PB::lo(hn, bs), v1 - PB::hi(hn, bs), inv));
+                        } else {
+                            st_off(oo[q], ko, PB::make(l0 + out[0][q], l1 + out[1][q], inv));
+                        }
+                    }
+                } else {
+                    st_off(oo[0], ko, PB::make(out[0][0], out[1][0], 1.0f));
+                    st_off(oo[1], ko, PB::make(out[0][1], out[1][1], 1.0f));
+                    st_off(oo[2], ko, PB::make(out[0][2], out[1][2], 1.0f));
+                }
             }
         }
         __syncthreads();
@@ -537,6 +663,8 @@ SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *b
     a.u = u;
     a.b = b;
     a.bo = bo;
+    a.bh = nullptr;
+    a.bho = nullptr;
     a.bext = bext;
     a.nx = c.nx;
     a.ny = c.ny;
@@ -561,35 +689,35 @@ static inline unsigned sweep_grid(int nblocks) { return (unsigned)(((nblocks + 7
 
 // Sweeps are launched through hipExtLaunchKernelGGL: when profiling, its start / stop events
 // are stamped when the kernel itself starts and ends (no event packets around the launch).
-template <typename TU, typename TB, bool BATCH>
+template <typename TU, typename TB, bool BATCH, bool SPLIT>
 static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
-                              const BlockMap *map, int parity, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+                              const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(sweep_grid(nblocks));
     if (L.pair) {
         if (L.ty >= 8)
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
-                                  parity, nblocks);
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
+                                  which, nblocks);
         else
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
-                                  parity, nblocks);
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  which, nblocks);
         return hipGetLastError();
     }
     switch (L.tx) {
         case 64:
-            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
-                                  parity, nblocks);
+            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  which, nblocks);
             break;
         case 32:
-            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
-                                  parity, nblocks);
+            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  which, nblocks);
             break;
         case 16:
-            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
-                                  parity, nblocks);
+            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  which, nblocks);
             break;
         default:
-            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
-                                  parity, nblocks);
+            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+                                  which, nblocks);
             break;
     }
     return hipGetLastError();
@@ -598,30 +726,31 @@ static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, 
 
 template <bool BATCH>
 static hipError_t sweep_kinds(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
-                              const BlockMap *map, int parity, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+                              const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
     if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
-        return sweep_typed<float, float, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+        return sweep_typed<float, float, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
     if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
-        return sweep_typed<__half, __half, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+        return sweep_typed<__half, __half, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
     if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
-        return sweep_typed<__hip_bfloat16, __half, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+        return sweep_typed<__hip_bfloat16, __half, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
     if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
-        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH>(s, a, L, tab, map, parity, nblocks, e0, e1);
+        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
+    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)  // reads the float16 copy of u
+        return sweep_typed<__half, __half, BATCH, true>(s, a, L, tab, map, which, nblocks, e0, e1);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_mag_sweep(hipStream_t s, int kinds, const void *u, const void *b, void *bo, const float *bext,
-                            StepConst c, SweepLaunch L, hipEvent_t e0, hipEvent_t e1) {
-    L.pair = L.pair && c.nx % 128 == 0;
-    const SweepArgs a = make_sweep_args(u, b, bo, bext, c, L);
-    return sweep_kinds<false>(s, kinds, a, L, nullptr, nullptr, 0, a.nblocks, e0, e1);
+hipError_t launch_mag_sweep(hipStream_t s, int kinds, const SweepArgs &a0, SweepLaunch L, hipEvent_t e0,
+                            hipEvent_t e1) {
+    L.pair = L.pair && a0.nx % 128 == 0;
+    return sweep_kinds<false>(s, kinds, a0, L, nullptr, nullptr, 0, a0.nblocks, e0, e1);
 }
 
 hipError_t launch_mag_sweep_batch(hipStream_t s, int kinds, SweepLaunch L, const PipeStep *tab, const BlockMap *map,
-                                  int parity, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+                                  int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     if (nblocks <= 0) return hipSuccess;
-    return sweep_kinds<true>(s, kinds, SweepArgs{}, L, tab, map, parity, nblocks, e0, e1);
+    return sweep_kinds<true>(s, kinds, SweepArgs{}, L, tab, map, which, nblocks, e0, e1);
 }
 
 }  // namespace mhd

@@ -39,7 +39,8 @@ def setup(sim, w, markers):
 
 
 STORE = {"f32": {}, "f16": dict(rho_storage="f16", u_storage="f16", b_storage="f16",
-                                 u_scale=0.05, b_scale=0.01)}
+                                 u_scale=0.05, b_scale=0.01),
+         "f16split": dict(b_storage="f16split", u_scale=0.05, b_scale=0.01)}
 
 
 def make_batch(spec, storage="f32"):
@@ -70,7 +71,7 @@ def assert_same(p, s, label):
     assert p.time() == s.time(), (label, p.time(), s.time())
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16split"])
 def test_batch_matches_single_boxes_bitwise(storage):
     print("case batch vs single", storage, flush=True)
     spec = batch_spec()

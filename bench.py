@@ -12,11 +12,14 @@ roofline = the magnetic sweep kernel (the dominant one): 36 algorithmic bytes pe
 cpu_baseline = the FP64 oracle on this host, timed on a bounded sample of the same workload.
 batched = the batched form on 64 independent pipes of uneven size and physics (~74 M cells,
 ~2.3 M markers, tiles autotuned), MLUPS over all their cells (an extra object, not `value`).
+precision = float32 against the split float16 form (b in float16 hi + lo, float16 copy of u for
+the sweeps) on the 512 x 256 x 256 pipe at 270 sweeps per step, with the split form's per-field
+error against the stored FP64 oracle run of the 8 x 32 x 32 pipe after 2000 steps.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-precision]
 HBM traffic of the sweep (rocprofv3 counters, scaled by a plain copy of known size):
   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --steps 1 \
-      --warmup 0 --profile-steps 1 --no-cpu --no-batch --calib-copy-mib 1024
+      --warmup 0 --profile-steps 1 --no-cpu --no-batch --no-precision --calib-copy-mib 1024
   (the same with WRITE_SIZE into D2), then
   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib 1024
 """
@@ -101,7 +104,7 @@ def traffic_summary(fetch_dir, write_dir, copy_mib):
         "# dispatches), each scaled by the ratio of the known size of a plain torch copy to what the",
         "# same counter reads for it. Commands:",
         f"#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --steps 1 "
-        f"--warmup 0 --profile-steps 1 --no-cpu --no-batch --calib-copy-mib {copy_mib}",
+        f"--warmup 0 --profile-steps 1 --no-cpu --no-batch --no-precision --calib-copy-mib {copy_mib}",
         "#   (the same with --pmc WRITE_SIZE into D2)",
         f"#   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib {copy_mib}",
         f"fetch_kib_raw = {out['fetch']['raw_kib']:.1f}",
@@ -158,6 +161,66 @@ def batched_leg(steps):
             "sweep_alg_GBs": round(SWEEP_BYTES_PER_CELL * sweep_cells / (ms * 1e-3) / 1e9, 1)}
 
 
+def precision_leg(steps, with_error=True):
+    """MLUPS of float32 and of the split float16 form on the large pipe, and the split form's
+    per-field error after 2000 steps of the small pipe against the stored oracle run."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2211_09370_amd import Sim
+
+    w = W.large_pipe(Rm=1e-2)
+    B_ind = 1e-2 * w.params.B0  # induced-field scale Rm B0
+    forms = {"f32": {}, "f16split": dict(b_storage="f16split", u_scale=W.U0, b_scale=B_ind)}
+    out = {"workload": w.name, "box": [w.nx, w.ny, w.nz], "n_mag": w.params.n_mag,
+           "markers": int(w.markers.shape[1]), "steps": steps}
+    for name, st in forms.items():
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], **st)
+        sim.set_markers(w.markers)
+        sim.set_params(w.params)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name + "_MLUPS"] = round(w.n_cells * steps / sec / 1e6, 3)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        log(f"bench: precision {name} {steps} steps in {sec:.3f} s")
+    out["speedup_f16split_over_f32"] = round(out["f16split_MLUPS"] / out["f32_MLUPS"], 4)
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_pipe8x32x32_2000steps.npz")
+    if with_error and os.path.exists(gold):
+        ref = np.load(gold)
+        ws = W.small_pipe()
+        sim = Sim(ws.nx, ws.ny, ws.nz, ws.markers.shape[1], b_storage="f16split", u_scale=W.U0,
+                  b_scale=1e-3 * ws.params.B0)
+        sim.set_markers(ws.markers)
+        sim.set_params(ws.params)
+        sim.set_field("rho", ws.rho)
+        sim.set_field("u", ws.u)
+        sim.set_field("b", ws.b)
+        sim.step(int(ref["steps"]))
+
+        def e(a, r):
+            return float(np.abs(a - r).max() / np.abs(r).max())
+
+        rs = max(np.abs(ref["rho"] - 1).max(), math.sqrt(3) * np.abs(ref["u"]).max())
+        out["f16split_error_vs_oracle"] = {
+            "case": "8x32x32 pipe, Ha 5, 2000 steps, max-normalised",
+            "u": e(sim.get_field("u"), ref["u"]), "b": e(sim.get_field("b"), ref["b"]),
+            "rho": float(np.abs(sim.get_field("rho") - ref["rho"]).max() / rs)}
+        sim.close()
+    return out
+
+
 def cpu_baseline(w):
     """Oracle on the full 128^3 workload: one fluid step with 2 and one with 32 sweeps give the
     cost of a sweep and of the rest of a step; MLUPS is then scaled to 270 sweeps per step."""
@@ -192,6 +255,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--precision-steps", type=int, default=3)
+    ap.add_argument("--no-precision-error", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -265,6 +331,9 @@ def main():
     batched = None
     if not args.no_batch:
         batched = batched_leg(args.batch_steps)
+    precision = None
+    if not args.no_precision:
+        precision = precision_leg(args.precision_steps, not args.no_precision_error)
 
     cpu = None
     if not args.no_cpu:
@@ -294,6 +363,7 @@ def main():
         "sweep_glups": round(w.n_cells * (w.params.n_mag + 1) * args.steps / sec / 1e9, 3),
         "finite": state_ok,
         "batched": batched,
+        "precision": precision,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -83,6 +83,12 @@ typedef struct {
     int32_t reserved0;
     double u_bulk_target; /* target bulk velocity over r <= R                               */
     double k_c;           /* control gain: G += k_c (8 nu / R^2) (target - U_b) per step    */
+    double alpha;         /* accelerated magnetic iteration (Sec. 5.8, eq. "magnetic field
+                             quasi-static acelerated"): rest population (w_0 - 1 + alpha) b,
+                             gathered sum divided by alpha, i.e. b' = b + (S(b) - b) / alpha
+                             with S the plain sweep; same fixed point, slow modes converge
+                             1/alpha times faster. 0 or 1: plain sweep. Must be >= 4/9 (the
+                             D3Q19 averaging symbol is >= 1/9, so smaller alpha diverges). */
 } mhd_params;
 
 typedef enum { MHD_FIELD_RHO = 0, MHD_FIELD_U = 1, MHD_FIELD_B_INDUCED = 2 } mhd_field;
@@ -98,6 +104,9 @@ typedef struct {
     double G;       /* body force used by that step                                       */
     double E_k, E_m, E_b, P_in, P_p, P_nu, P_L, M_eta, M_adv, joule, mass, Q, u_max;
     double n_omega; /* number of cells in Omega                                            */
+    double res_mag; /* induction residual (Sec. 5.8 eq. "Error l2 decay"): root mean square
+                       over Omega of |eta lap b - div(u B - B u)|; the paper normalises it by
+                       its value at the first iteration                                      */
 } mhd_budget;
 
 typedef struct mhd_sim mhd_sim;
@@ -126,8 +135,8 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
                            const double *b_wall);
 
 /* Parameters (copied). INVALID_ARG if tau = 3 nu + 1/2 <= 1/2, eta <= 0, n_mag < 1, a fringe
- * width <= 0, or (with markers set) 1 + d_j (lambda - 1) <= 0 for some marker (the scaling
- * of Sec. 5.5 / 5.6 would be singular or negative). UNSUPPORTED if tau >= 1. */
+ * width <= 0, 0 < alpha < 4/9, or (with markers set) 1 + d_j (lambda - 1) <= 0 for some marker
+ * (the scaling of Sec. 5.5 / 5.6 would be singular or negative). UNSUPPORTED if tau >= 1. */
 mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p);
 
 /* Copy a field in / out (host float64, layout above; rho has 1 component, u and b 3).

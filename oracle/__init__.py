@@ -28,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 BUDGET_NAMES = ("E_k", "E_m", "E_b", "P_in", "P_p", "P_nu", "P_L", "M_eta", "M_adv", "joule",
-                "mass", "Q", "u_max", "n_omega", "G", "nonfinite")
+                "mass", "Q", "u_max", "n_omega", "G", "nonfinite", "res_mag")
 
 
 class OrcParams(C.Structure):
@@ -39,7 +39,8 @@ class OrcParams(C.Structure):
                 ("bext_kind", C.c_int), ("B0", C.c_double), ("fringe_x0", C.c_double),
                 ("fringe_w", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
                 ("radius", C.c_double), ("flow_control", C.c_int), ("u_target", C.c_double),
-                ("k_c", C.c_double), ("ib_u", C.c_int), ("ib_b", C.c_int)]
+                ("k_c", C.c_double), ("ib_u", C.c_int), ("ib_b", C.c_int),
+                ("alpha", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -91,7 +92,7 @@ def make_params(nx, ny, nz, prm=None, *, ib_u=1, ib_b=1, **over) -> OrcParams:
     """Build OrcParams from a workloads.Params-like object (attribute names match) + overrides."""
     fields = dict(nu=0.1, eta=1.0, n_mag=1, lambda_u=1.0, lambda_b=0.0, G0=0.0, G1=0.0, period=0.0,
                   bext_kind=0, B0=0.0, fringe_x0=0.0, fringe_w=1.0, yc=0.0, zc=0.0, radius=0.0,
-                  flow_control=0, u_target=0.0, k_c=0.1)
+                  flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0)
     if prm is not None:
         for k in list(fields):
             src = {"radius": "avg_radius", "u_target": "u_bulk_target"}.get(k, k)
@@ -172,7 +173,7 @@ def fluid(p: OrcParams, rho, u, F):
 
 def budgets(p: OrcParams, rho, u, b, G) -> dict:
     rho, u, b = _f64(rho), _f64(u), _f64(b)
-    out = np.zeros(16)
+    out = np.zeros(len(BUDGET_NAMES))
     lib().orc_budgets(C.byref(p), _ptr(rho), _ptr(u), _ptr(b), float(G), _ptr(out))
     return dict(zip(BUDGET_NAMES, out.tolist()))
 

@@ -58,6 +58,7 @@ typedef struct {
     int flow_control;
     double u_target, k_c;
     int ib_u, ib_b; /* 1 = apply the wall correction for u / for b */
+    double alpha;   /* accelerated magnetic iteration (Sec. 5.8); <= 0 means 1 (plain sweep) */
 } orc_params;
 
 /* D3Q19 velocity set and weights (textbook values; the paper's own table is D3Q27). */
@@ -148,6 +149,9 @@ static inline void load3(const double *f, int64_t N, int64_t k, double v[3]) {
 void orc_mag_sweep(const orc_params *p, const double *u, const double *b, double *bout) {
     const int64_t N = ncells(p);
     const double c = 6.0 * p->eta;
+    /* Sec. 5.8, eq. "magnetic field quasi-static acelerated": the rest population becomes
+     * (w_0 - 1 + alpha) b and the gathered sum is divided by alpha (alpha = 1: Sec. 5.7). */
+    const double alpha = p->alpha > 0.0 ? p->alpha : 1.0;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
@@ -162,10 +166,12 @@ void orc_mag_sweep(const orc_params *p, const double *u, const double *b, double
                     orc_bext(p, wrap(sx, p->nx), wrap(sy, p->ny), wrap(sz, p->nz), Be);
                     for (int a = 0; a < 3; ++a) Bs[a] = Be[a] + bs[a];
                     geq(i, c, us, bs, Bs, g);
+                    if (i == 0)
+                        for (int a = 0; a < 3; ++a) g[a] += (alpha - 1.0) * bs[a];
                     for (int a = 0; a < 3; ++a) acc[a] += g[a];
                 }
                 int64_t k0 = cell(p, x, y, z);
-                for (int a = 0; a < 3; ++a) bout[a * N + k0] = acc[a];
+                for (int a = 0; a < 3; ++a) bout[a * N + k0] = acc[a] / alpha;
             }
 }
 
@@ -501,7 +507,7 @@ void orc_step(orc_ctx *c, double *rho, double *u, double *b, int64_t n, int64_t 
 void orc_budgets(const orc_params *p, const double *rho, const double *u, const double *b, double G,
                  double *out) {
     const int64_t N = ncells(p);
-    double Ek = 0, Em = 0, Eb = 0, Pin = 0, Pp = 0, Pnu = 0, PL = 0, Meta = 0, Madv = 0, Jl = 0;
+    double Ek = 0, Em = 0, Eb = 0, Pin = 0, Pp = 0, Pnu = 0, PL = 0, Meta = 0, Madv = 0, Jl = 0, Res = 0;
     double mass = 0, Q = 0, umax2 = 0;
     int64_t nom = 0;
     int nonfinite = 0;
@@ -550,7 +556,8 @@ void orc_budgets(const orc_params *p, const double *rho, const double *u, const 
                     Pp += -uu[a] * gp[a];
                     Pnu += p->nu * uu[a] * lap_iso(p, u + a * N, x, y, z);
                     PL += uu[a] * JxB[a];
-                    Meta += p->eta * B[a] * lap_iso(p, b + a * N, x, y, z);
+                    const double lapb = lap_iso(p, b + a * N, x, y, z);
+                    Meta += p->eta * B[a] * lapb;
                     double div = 0.0;
                     for (int cc = 0; cc < 3; ++cc) {
                         double g[3];
@@ -558,6 +565,8 @@ void orc_budgets(const orc_params *p, const double *rho, const double *u, const 
                         div += g[cc];
                     }
                     Madv += -B[a] * div;
+                    /* Sec. 5.8 eq. "Error l2 decay": eta lap b - div(u B - B u) */
+                    Res += (p->eta * lapb - div) * (p->eta * lapb - div);
                     Jl += p->eta * J[a] * J[a];
                 }
             }
@@ -580,6 +589,7 @@ void orc_budgets(const orc_params *p, const double *rho, const double *u, const 
     out[13] = (double)nom;
     out[14] = G;
     out[15] = (double)nonfinite;
+    out[16] = sqrt(Res * inv); /* root mean square over Omega of the induction residual */
 }
 
 int orc_num_threads(void) {

@@ -53,7 +53,7 @@ class mhd_params(C.Structure):
                 ("B0", C.c_double), ("fringe_x0", C.c_double), ("fringe_w", C.c_double),
                 ("yc", C.c_double), ("zc", C.c_double), ("avg_radius", C.c_double),
                 ("flow_control", C.c_int32), ("reserved0", C.c_int32),
-                ("u_bulk_target", C.c_double), ("k_c", C.c_double)]
+                ("u_bulk_target", C.c_double), ("k_c", C.c_double), ("alpha", C.c_double)]
 
 
 class mhd_budget(C.Structure):
@@ -61,7 +61,8 @@ class mhd_budget(C.Structure):
                 ("E_b", C.c_double), ("P_in", C.c_double), ("P_p", C.c_double),
                 ("P_nu", C.c_double), ("P_L", C.c_double), ("M_eta", C.c_double),
                 ("M_adv", C.c_double), ("joule", C.c_double), ("mass", C.c_double),
-                ("Q", C.c_double), ("u_max", C.c_double), ("n_omega", C.c_double)]
+                ("Q", C.c_double), ("u_max", C.c_double), ("n_omega", C.c_double),
+                ("res_mag", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)

@@ -28,6 +28,7 @@ struct StepConst {
     float tau;         // 3 nu + 1/2
     float u_scale, inv_u_scale, b_scale, inv_b_scale;
     float copy_scale, inv_copy_scale;  // split form: scale of the float16 copy of u
+    float omega;                       // 1 / alpha of the accelerated magnetic iteration
     double nu, eta;
     double G0, G1, period;
     double yc, zc, radius;
@@ -57,6 +58,7 @@ struct SweepArgs {
     int nx, ny, nz;
     int tiles_x, tiles_y, nzc, zchunk, nblocks;
     float kappa, u_scale, b_scale, inv_b_scale;
+    float omega;        // b' = b + omega (S(b) - b); 1 for the plain sweep
 };
 // Sweep arguments of a box for tile choice L (tile counts and workgroup count filled in).
 SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *bext, StepConst c, SweepLaunch L);

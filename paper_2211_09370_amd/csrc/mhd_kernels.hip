@@ -413,20 +413,21 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
 }
 
 // partial layout: 0 Ek, 1 Em, 2 Eb, 3 sum u_x (Omega), 4 Pp, 5 Pnu/nu, 6 PL, 7 Meta/eta, 8 Madv,
-// 9 sum |J|^2, 10 mass, 11 Q sum, 12 n_omega, 13 max |u|^2, 14 nonfinite, 15 unused
+// 9 sum |J|^2, 10 mass, 11 Q sum, 12 n_omega, 13 sum |eta lap b - div(uB - Bu)|^2 (the induction
+// residual of Sec. 5.8), 14 max |u|^2, 15 nonfinite
 template <typename TR, typename TU, typename TB>
 __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, const TU *u, const TB *b,
                                                                 const TB *bh, const float *bext, double *part,
                                                                 StepConst c) {
-    __shared__ double sh[13][kRedThreads];
+    __shared__ double sh[14][kRedThreads];
     __shared__ double shm[kRedThreads];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const double us = c.u_scale, bs = c.b_scale;
     const double R2 = c.radius * c.radius;
     const double Ro = c.radius - 2.0, Ro2 = Ro * Ro;
-    double v[13];
+    double v[14];
 #pragma unroll
-    for (int q = 0; q < 13; ++q) v[q] = 0.0;
+    for (int q = 0; q < 14; ++q) v[q] = 0.0;
     double umax2 = 0.0;
     double nonfin = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
@@ -489,9 +490,11 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
             v[7] += B[a] * lb[a];
             v[8] += -B[a] * divL[a];
             v[9] += J[a] * J[a];
+            const double res = c.eta * lb[a] - divL[a];
+            v[13] += res * res;
         }
     }
-    block_sum<13>(sh, v);
+    block_sum<14>(sh, v);
     // max |u|^2 and "any non-finite" in the same fixed tree
     __shared__ double shf[kRedThreads];
     shm[threadIdx.x] = umax2;
@@ -506,29 +509,28 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
     }
     if (threadIdx.x == 0) {
         double *o = part + (int64_t)blockIdx.x * kBudgetVals;
-        for (int q = 0; q < 13; ++q) o[q] = sh[q][0];
-        o[13] = shm[0];
-        o[14] = shf[0];
-        o[15] = 0.0;
+        for (int q = 0; q < 14; ++q) o[q] = sh[q][0];
+        o[14] = shm[0];
+        o[15] = shf[0];
     }
 }
 
 __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part, DevCtrl *ctrl, mhd_budget *ring,
                                                               StepConst c) {
-    __shared__ double sh[13][kRedThreads];
+    __shared__ double sh[14][kRedThreads];
     __shared__ double shm[kRedThreads], shf[kRedThreads];
-    double v[13];
+    double v[14];
 #pragma unroll
-    for (int q = 0; q < 13; ++q) v[q] = 0.0;
+    for (int q = 0; q < 14; ++q) v[q] = 0.0;
     double m = 0.0, f = 0.0;
     for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) {
         const double *p = part + (int64_t)i * kBudgetVals;
 #pragma unroll
-        for (int q = 0; q < 13; ++q) v[q] += p[q];
-        m = fmax(m, p[13]);
-        f = fmax(f, p[14]);
+        for (int q = 0; q < 14; ++q) v[q] += p[q];
+        m = fmax(m, p[14]);
+        f = fmax(f, p[15]);
     }
-    block_sum<13>(sh, v);
+    block_sum<14>(sh, v);
     shm[threadIdx.x] = m;
     shf[threadIdx.x] = f;
     __syncthreads();
@@ -559,6 +561,7 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part
         r.Q = sh[11][0] / (double)c.nx;
         r.u_max = sqrt(shm[0]);
         r.n_omega = n;
+        r.res_mag = sqrt(sh[13][0] * inv);
         // |u| >= c_s = 1/sqrt(3) or a non-finite value marks the run unstable
         if (shf[0] != 0.0 || !(shm[0] < 1.0 / 3.0) || !isfinite(sh[0][0])) ctrl->status |= 1;
         const int idx = ctrl->n_records;

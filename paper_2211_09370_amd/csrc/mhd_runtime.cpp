@@ -187,6 +187,7 @@ StepConst step_const(const mhd_sim *s) {
     c.inv_u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.u_scale);
     c.b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.b_scale;
     c.inv_b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.b_scale);
+    c.omega = (float)(1.0 / (p.alpha > 0.0 ? p.alpha : 1.0));
     c.copy_scale = s->split() ? (float)s->g.u_scale : 1.0f;
     c.inv_copy_scale = s->split() ? (float)(1.0 / s->g.u_scale) : 1.0f;
     c.nu = p.nu;
@@ -638,8 +639,11 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
     if (p->bext_kind == MHD_BEXT_TANH_FRINGE_Y && !(p->fringe_w > 0.0))
         return fail(MHD_ERR_INVALID_ARG, "fringe_w must be > 0");
     if (p->flow_control && !(p->avg_radius > 0.0)) return fail(MHD_ERR_INVALID_ARG, "flow control needs avg_radius > 0");
+    if (p->alpha != 0.0 && !(p->alpha >= 4.0 / 9.0))
+        return fail(MHD_ERR_INVALID_ARG, "alpha = %g: the accelerated sweep needs alpha >= 4/9 (or 0 for the plain sweep)",
+                    p->alpha);
     for (double v : {p->nu, p->eta, p->lambda_u, p->lambda_b, p->G0, p->G1, p->period, p->B0, p->fringe_x0, p->fringe_w,
-                     p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c})
+                     p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c, p->alpha})
         if (!std::isfinite(v)) return fail(MHD_ERR_INVALID_ARG, "non-finite parameter");
     const bool first = !s->have_params;
     const mhd_params old = s->prm;

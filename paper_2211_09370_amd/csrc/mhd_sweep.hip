@@ -35,6 +35,9 @@ namespace mhd {
 // linear in (b, B_ext)) and leaves no per-value scaling: staging and output are plain
 // conversions and additions (float32 storage has both scales 1).
 //
+// Accelerated iteration (Sec. 5.8): with rest weight w_0 - 1 + alpha and the sum divided by
+// alpha, the update is b + (b* - b) / alpha, i.e. the increment above times omega = 1 / alpha.
+//
 // SPLIT: b is held as two float16 arrays, b = (hi + lo) b_scale. hi is fixed within a fluid
 // step; the sweep stages hi + lo and writes lo* = lo + increment, so the 16-bit rounding is
 // relative to lo, not to b. The first sweep of a step (a.bho set) re-splits v = hi + lo +
@@ -255,9 +258,9 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
             const float A2 = dP1z - Q1xB - Q1yC, B2 = dP0z - Q0xB - Q0yC;
             if (p >= z0 + 1) {
                 // output plane p-1: b* = b_c + increment, the increment built from differences
-                const float d0 = (acc0 + C0) + W6 * ((cm0 - cc0) + (c_x - cc0));
-                const float d1 = (acc1 + C1) + W6 * ((cm1 - cc1) + (c_y - cc1));
-                const float d2 = (acc2 + A2) + W6 * ((cm2 - cc2) + (c_z - cc2));
+                const float d0 = a.omega * ((acc0 + C0) + W6 * ((cm0 - cc0) + (c_x - cc0)));
+                const float d1 = a.omega * ((acc1 + C1) + W6 * ((cm1 - cc1) + (c_y - cc1)));
+                const float d2 = a.omega * ((acc2 + A2) + W6 * ((cm2 - cc2) + (c_z - cc2)));
                 if constexpr (SPLIT) {
                     const float d[3] = {d0, d1, d2};
                     TB *oo[3] = {o0, o1, o2};
@@ -605,9 +608,9 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 // output plane p-1: b* = b_c + increment (differences only); C2 = A2
-                out[e][0] = (acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0]));
-                out[e][1] = (acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1]));
-                out[e][2] = (acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2]));
+                out[e][0] = a.omega * ((acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0])));
+                out[e][1] = a.omega * ((acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1])));
+                out[e][2] = a.omega * ((acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2])));
                 if constexpr (!SPLIT) {
                     out[e][0] += cc[e][0];
                     out[e][1] += cc[e][1];
@@ -681,6 +684,7 @@ SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *b
     a.u_scale = c.u_scale;
     a.b_scale = c.b_scale;
     a.inv_b_scale = c.inv_b_scale;
+    a.omega = c.omega;
     return a;
 }
 

@@ -92,6 +92,24 @@ def test_one_step_no_wall_ragged_shapes(shape):
     compare(gpu_run(w, 1, markers=False), oracle_run(w, 1, markers=False), label=str(shape))
 
 
+@pytest.mark.parametrize("shape", [(37, 21, 13), (128, 13, 9), (8, 32, 32)])
+@pytest.mark.parametrize("alpha", [0.5, 4 / 9])
+def test_accelerated_sweep_one_step(shape, alpha):
+    """Sec. 5.8 accelerated iteration (rest weight w_0 - 1 + alpha, sum over alpha) against the
+    oracle's literal form; nx = 128 takes the paired sweep."""
+    print("case alpha", alpha, shape, flush=True)
+    w = random_box(*shape, key=220, n_mag=4)
+    compare(gpu_run(w, 1, alpha=alpha), oracle_run(w, 1, alpha=alpha), label=f"alpha {alpha:.3f} {shape}")
+
+
+def test_accelerated_sweep_small_pipe_40_steps():
+    # N = 135 accelerated sweeps per step (alpha = 1/2) instead of 270
+    w = W.small_pipe()
+    print("case alpha pipe8", flush=True)
+    compare(gpu_run(w, 40, alpha=0.5, n_mag=135), oracle_run(w, 40, alpha=0.5, n_mag=135),
+            label="alpha 0.5 pipe8 40 steps")
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)
@@ -193,9 +211,10 @@ def test_budget_reduction_matches_oracle_on_the_same_fields():
     p = oracle.make_params(w.nx, w.ny, w.nz, w.params)
     ref = oracle.budgets(p, rho, u, b, r["G"])
     for k in ("E_k", "E_m", "E_b", "P_in", "P_p", "P_nu", "P_L", "M_eta", "M_adv", "joule", "mass",
-              "Q", "u_max", "n_omega"):
+              "Q", "u_max", "n_omega", "res_mag"):
         scale = max(abs(ref[k]), 1e-300)
         assert abs(r[k] - ref[k]) <= 1e-9 * scale, (k, r[k], ref[k])
+    assert ref["res_mag"] > 0
 
 
 def test_budget_trajectory_matches_oracle():
@@ -280,7 +299,8 @@ def test_argument_checks():
         sim.step(1)
     assert e.value.status == _abi.MHD_ERR_STATE
     for over, st in ((dict(nu=0.2), _abi.MHD_ERR_UNSUPPORTED), (dict(nu=0.0), _abi.MHD_ERR_INVALID_ARG),
-                     (dict(n_mag=0), _abi.MHD_ERR_INVALID_ARG), (dict(eta=-1.0), _abi.MHD_ERR_INVALID_ARG)):
+                     (dict(n_mag=0), _abi.MHD_ERR_INVALID_ARG), (dict(eta=-1.0), _abi.MHD_ERR_INVALID_ARG),
+                     (dict(alpha=0.4), _abi.MHD_ERR_INVALID_ARG)):
         with pytest.raises(MhdError) as e:
             sim.set_params(w.params, **over)
         assert e.value.status == st, over

@@ -170,6 +170,111 @@ def test_magnetic_sweep_conserves_the_mean_field():
 # Fluid update (Sec. 3.3, Sec. 5.1): conservation and the discrete-effect term
 # --------------------------------------------------------------------------------------------
 
+# --------------------------------------------------------------------------------------------
+# Accelerated magnetic iteration and the induction residual (Sec. 5.8)
+# --------------------------------------------------------------------------------------------
+
+def _symbol(k):
+    cx, cy, cz = np.cos(k)
+    return 1 / 3 + (cx + cy + cz) / 9 + (cx * cy + cx * cz + cy * cz) / 9
+
+
+@pytest.mark.parametrize("alpha", [0.5, 4 / 9, 0.75, 1.7])
+def test_accelerated_sweep_over_relaxes_each_mode_by_one_over_alpha(alpha):
+    # Rest population (w_0 - 1 + alpha) b and the sum divided by alpha give, for u = 0, the mode
+    # factor 1 + (sigma(k) - 1) / alpha with sigma the averaging symbol; at k = (pi, pi, 0),
+    # sigma = 1/9 and the factor 1 - 8 / (9 alpha) reaches -1 at alpha = 4/9 (stability edge).
+    n = 8
+    p = oracle.make_params(n, n, n, eta=3.0, alpha=alpha)
+    x = np.arange(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = np.zeros((3, n, n, n))
+    for (kx, ky, kz) in [(1, 0, 0), (2, 3, 0), (4, 4, 0), (1, 2, 3), (0, 4, 4)]:
+        k = 2 * np.pi * np.array([kx, ky, kz]) / n
+        mode = np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+        b = np.stack([mode, -0.3 * mode, 2.0 * mode])
+        out = oracle.mag_sweep(p, u, b)
+        np.testing.assert_allclose(out, (1 + (_symbol(k) - 1) / alpha) * b, atol=1e-13)
+    k = np.array([np.pi, np.pi, 0.0])
+    assert abs(_symbol(k) - 1 / 9) < 1e-15
+    factor = 1 - 8 / (9 * alpha)
+    assert abs(factor) <= 1 + 1e-12  # every alpha >= 4/9 is stable on D3Q19
+    if abs(alpha - 4 / 9) < 1e-12:
+        assert abs(factor + 1) < 1e-12
+
+
+def test_accelerated_sweep_has_the_plain_fixed_point():
+    # The accelerated iteration only rescales the increment, so both converge to the same b.
+    n = 8
+    x = 2 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = 0.05 * np.stack([np.sin(Y) * np.cos(Z), np.cos(X + 2 * Z), np.sin(X - Y)])
+    out = []
+    for alpha, iters in ((1.0, 800), (0.5, 400)):
+        p = oracle.make_params(n, n, n, eta=2.0, bext_kind=W.BEXT_UNIFORM_Y, B0=1.0, alpha=alpha)
+        b = np.zeros((3, n, n, n))
+        for _ in range(iters):
+            b = oracle.mag_sweep(p, u, b)
+        out.append(b)
+    scale = np.abs(out[0]).max()
+    assert scale > 1e-4
+    assert np.abs(out[1] - out[0]).max() <= 1e-10 * scale
+
+
+def test_accelerated_sweep_halves_the_sweeps_for_a_given_residual():
+    # With alpha = 1/2 the slow modes contract twice as fast per sweep (mode factor above), so
+    # N/2 accelerated sweeps leave about the error N plain sweeps leave (Sec. 5.8: N = 9 vs 18).
+    n = 16
+    x = 2 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = 0.05 * np.stack([np.sin(Y), np.cos(Z), np.sin(X)])
+    ref = None
+    errs = {}
+    for alpha, iters in ((1.0, 3000), (1.0, 40), (0.5, 20)):
+        p = oracle.make_params(n, n, n, eta=2.0, bext_kind=W.BEXT_UNIFORM_Y, B0=1.0, alpha=alpha)
+        b = np.zeros((3, n, n, n))
+        for _ in range(iters):
+            b = oracle.mag_sweep(p, u, b)
+        if ref is None:
+            ref = b
+        else:
+            errs[alpha] = np.abs(b - ref).max()
+    # the slowest mode's factors: plain (1 - e)^40 vs accelerated (1 - 2e)^20, equal to O(e^2)
+    assert 0.8 < errs[0.5] / errs[1.0] < 1.05, errs
+
+
+def test_induction_residual_of_a_mode_is_its_closed_form():
+    # u = 0, B_ext = 0, b = cos(k.x) in one component: eta lap_h b = -6 eta (1 - sigma(k)) b, so
+    # the root mean square over Omega (the whole box here) is 6 eta (1 - sigma) / sqrt(2).
+    n = 8
+    eta = 3.0
+    p = oracle.make_params(n, n, n, eta=eta, radius=40.0, yc=n / 2, zc=n / 2)
+    x = np.arange(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    k = 2 * np.pi * np.array([1, 2, 0]) / n
+    b = np.zeros((3, n, n, n))
+    b[2] = np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+    rec = oracle.budgets(p, np.ones((n, n, n)), np.zeros((3, n, n, n)), b, 0.0)
+    assert rec["n_omega"] == n ** 3
+    assert abs(rec["res_mag"] - 6 * eta * (1 - _symbol(k)) / math.sqrt(2)) < 1e-12
+
+
+def test_induction_residual_vanishes_at_the_sweep_fixed_point():
+    n = 8
+    x = 2 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = 0.05 * np.stack([np.sin(Y) * np.cos(Z), np.cos(X + 2 * Z), np.sin(X - Y)])
+    p = oracle.make_params(n, n, n, eta=2.0, bext_kind=W.BEXT_UNIFORM_Y, B0=1.0, alpha=0.5,
+                           radius=40.0, yc=n / 2, zc=n / 2)
+    b = np.zeros((3, n, n, n))
+    rho = np.ones((n, n, n))
+    first = oracle.budgets(p, rho, u, oracle.mag_sweep(p, u, b), 0.0)["res_mag"]
+    for _ in range(400):
+        b = oracle.mag_sweep(p, u, b)
+    last = oracle.budgets(p, rho, u, b, 0.0)["res_mag"]
+    assert first > 0 and last < 1e-9 * first
+
+
 def _random_state(n, key, F_mean=1e-4):
     g = W.rng_for(key)
     rho = 1.0 + 0.01 * g.uniform(-1, 1, size=(n, n, n))

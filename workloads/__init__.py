@@ -50,6 +50,7 @@ class Params:
     flow_control: int = 0
     u_bulk_target: float = 0.0
     k_c: float = 0.1
+    alpha: float = 1.0  # accelerated magnetic iteration (1: plain sweep)
 
 
 @dataclasses.dataclass

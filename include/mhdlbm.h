@@ -163,6 +163,14 @@ mhd_status mhd_get_budgets(mhd_sim *s, mhd_budget *out, int64_t cap, int64_t *n_
 /* Take one budget record of the current state now (asynchronous). */
 mhd_status mhd_record_budget(mhd_sim *s);
 
+/* Induction residual along the magnetic iteration (Sec. 5.8, eq. "Error l2 decay"), for choosing
+ * n_mag: from the current state, runs n_sweeps (1 .. 4096) magnetic sweeps, each followed by the
+ * b wall correction, with u and the step counter held, and writes to res_out[k] (host, n_sweeps
+ * doubles) the residual res_mag (see mhd_budget) after sweep k + 1. The paper normalises the
+ * curve by its first value and takes the smallest count whose damping is sufficient. The
+ * induced field is restored afterwards, so the state is unchanged. Synchronous. */
+mhd_status mhd_mag_residual_curve(mhd_sim *s, int32_t n_sweeps, double *res_out);
+
 /* Kernel timing with HIP events on the solver's stream: when enabled, mhd_step brackets every
  * launch of the kernels with events; mhd_kernel_stats synchronises and returns the number of
  * timed launches and their summed duration for one kernel id, then forgets them. */

@@ -23,7 +23,7 @@ from ._abi import (MHD_BEXT_NONE, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_UNIFORM_Y, MH
 __all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
-           "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles",
+           "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles", "mhd_mag_residual_curve",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
            "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
            "mhd_batch_kernel_stats", "mhd_batch_destroy", "mhd_last_error", "BUDGET_FIELDS"]
@@ -133,6 +133,12 @@ def mhd_kernel_stats(h, kernel: int):
 
 def mhd_destroy(h):
     _abi.check(_abi.lib().mhd_destroy(h), "mhd_destroy")
+
+
+def mhd_mag_residual_curve(h, n_sweeps: int) -> np.ndarray:
+    out = np.zeros(int(n_sweeps))
+    _abi.check(_abi.lib().mhd_mag_residual_curve(h, int(n_sweeps), _dptr(out)), "mhd_mag_residual_curve")
+    return out
 
 
 def mhd_get_tiles(h):
@@ -303,6 +309,10 @@ class Sim:
 
     def kernel_stats(self, kernel: int):
         return mhd_kernel_stats(self._h, kernel)
+
+    def mag_residual_curve(self, n_sweeps: int) -> np.ndarray:
+        """Induction residual after each of n_sweeps sweeps from the current state (restored)."""
+        return mhd_mag_residual_curve(self._h, n_sweeps)
 
     @property
     def tiles(self):

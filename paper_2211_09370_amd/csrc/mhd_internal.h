@@ -40,6 +40,7 @@ constexpr int kRedBlocks = 1024;   // fixed grid of the float64 reductions (fixe
 constexpr int kRedThreads = 256;
 constexpr int kBudgetVals = 16;    // per-block partial sums of a budget pass
 constexpr int kRingCap = 4096;     // budget records held on the device
+constexpr int kResCap = 4096;      // residual values of one mhd_mag_residual_curve call
 
 // Launch wrappers implemented in mhd_kernels.hip. Every pointer is a device pointer.
 struct SweepLaunch {
@@ -95,6 +96,7 @@ hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,
                         void *rho_o, void *u_o, void *u_copy, StepConst c);
 hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c);
+// ring == NULL: the partials only (for launch_residual_final).
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b,
                          const void *b_hi, const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring,
                          StepConst c);
@@ -147,6 +149,8 @@ hipError_t launch_load_kind(hipStream_t s, int kind, const void *src, float *dst
 // float32 staging -> float16 hi = fp16(v), lo = fp16(v - hi) (values already divided by the scale).
 hipError_t launch_store_split(hipStream_t s, const float *src, void *hi, void *lo, int64_t n);
 hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl);
+// Residual sum of budget partials (slot 13) -> out = sqrt(sum / n_omega) (one workgroup).
+hipError_t launch_residual_final(hipStream_t s, const double *part, double *out);
 
 // Packs the three storage kinds (rho, u, b) into one dispatch code.
 inline int pack_kinds(int r, int u, int b) { return r | (u << 4) | (b << 8); }

@@ -574,6 +574,18 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part
     }
 }
 
+// Residual only: the same fixed-order sum of the partials' slots 13 (residual) and 12 (cells).
+__global__ void __launch_bounds__(kRedThreads) k_residual_final(const double *part, double *out) {
+    __shared__ double sh[2][kRedThreads];
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) {
+        v[0] += part[(int64_t)i * kBudgetVals + 13];
+        v[1] += part[(int64_t)i * kBudgetVals + 12];
+    }
+    block_sum<2>(sh, v);
+    if (threadIdx.x == 0) *out = sh[1][0] > 0.0 ? sqrt(sh[0][0] / sh[1][0]) : 0.0;
+}
+
 // -------------------------------------------------------------------------------------------
 // Storage conversion (float32 staging <-> storage kind)
 // -------------------------------------------------------------------------------------------
@@ -769,10 +781,15 @@ static hipError_t budget_t(hipStream_t s, const void *rho, const void *u, const 
     hipLaunchKernelGGL((k_budget_partial<TR, TU, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const TR *)rho,
                        (const TU *)u, (const TB *)b, (const TB *)bh, bext, part, c);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !ring) return e;  // no ring: partials only
     hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(kRedThreads), 0, s, part, ctrl, ring, c);
     return hipGetLastError();
 }
+hipError_t launch_residual_final(hipStream_t s, const double *part, double *out) {
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(kRedThreads), 0, s, part, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b, const void *b_hi,
                          const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
     const int kr = kinds & 15, ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;

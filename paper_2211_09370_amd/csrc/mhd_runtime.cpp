@@ -51,7 +51,7 @@ constexpr int64_t kBandSlots = 64;
 // Byte offsets of every region of the caller's workspace.
 struct Layout {
     size_t rho[2], u[2], b[2], bh[2], u16, F, bext, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
-    size_t band_cell, band_mk, band_w, red_part, flow_part, ring, total;
+    size_t band_cell, band_mk, band_w, red_part, flow_part, ring, res, total;
 };
 
 Layout make_layout(const mhd_grid_desc &g, int64_t M) {
@@ -88,6 +88,7 @@ Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     L.red_part = take((size_t)kRedBlocks * kBudgetVals * sizeof(double));
     L.flow_part = take((size_t)kRedBlocks * sizeof(double));
     L.ring = take((size_t)kRingCap * sizeof(mhd_budget));
+    L.res = take((size_t)kResCap * sizeof(double));
     L.total = off;
     return L;
 }
@@ -341,12 +342,10 @@ mhd_status ib_correct(mhd_sim *s, int kind, void *phi, float scale, float inv_sc
                  [&] { return launch_ib(s->stream, kind, phi, scale, inv_scale, a); });
 }
 
-mhd_status one_step(mhd_sim *s) {
-    const StepConst c = step_const(s);
+// Magnetic sweep m of a fluid step (m = 0 re-splits the split form) and its b wall correction.
+mhd_status mag_iteration(mhd_sim *s, const StepConst &c, int m) {
     hipStream_t st = s->stream;
-    STEPCHK(timed(s, MHD_K_CONTROL, "ctrl_begin", [&] { return launch_ctrl_begin(st, s->ctrl(), c); }));
-    // 1. magnetic iteration, wall correction after every sweep
-    for (int m = 0; m < s->prm.n_mag; ++m) {
+    {
         const int nb = 1 - s->cb;
         {  // timed by events the launch stamps at kernel start / end
             SweepArgs a = make_sweep_args(s->split() ? s->u16() : s->u(s->cu), s->b(s->cb), s->b(nb),
@@ -365,6 +364,15 @@ mhd_status one_step(mhd_sim *s) {
                            s->at<float>(s->L.bwall), s->bh(s->ch), nullptr, 0.f));
         s->cb = nb;
     }
+    return MHD_OK;
+}
+
+mhd_status one_step(mhd_sim *s) {
+    const StepConst c = step_const(s);
+    hipStream_t st = s->stream;
+    STEPCHK(timed(s, MHD_K_CONTROL, "ctrl_begin", [&] { return launch_ctrl_begin(st, s->ctrl(), c); }));
+    // 1. magnetic iteration, wall correction after every sweep
+    for (int m = 0; m < s->prm.n_mag; ++m) STEPCHK(mag_iteration(s, c, m));
     // 2. Lorentz + body force from the new b
     float *F = s->at<float>(s->L.F);
     STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
@@ -762,6 +770,43 @@ mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every) {
         STEPCHK(one_step(s));
         if (budget_every > 0 && s->t_host % budget_every == 0) STEPCHK(record_budget(s));
     }
+    return MHD_OK;
+}
+
+mhd_status mhd_mag_residual_curve(mhd_sim *s, int32_t n_sweeps, double *res_out) {
+    g_err.clear();
+    if (!s || !res_out) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called first");
+    if (n_sweeps < 1 || n_sweeps > kResCap) return fail(MHD_ERR_INVALID_ARG, "n_sweeps must be in [1, %d]", kResCap);
+    const StepConst c = step_const(s);
+    hipStream_t st = s->stream;
+    // save b (float32, or the split form's lo and hi: 12 N bytes either way) in the staging area
+    char *stage = reinterpret_cast<char *>(s->at<float>(s->L.F));
+    const size_t bbytes = 3 * (size_t)s->N * kind_bytes(s->g.b_storage);
+    const int cb0 = s->cb, ch0 = s->ch;
+    HIPCHK(hipMemcpyAsync(stage, s->b(cb0), bbytes, hipMemcpyDeviceToDevice, st));
+    if (s->split()) HIPCHK(hipMemcpyAsync(stage + bbytes, s->bh(ch0), 3 * (size_t)s->N * 2, hipMemcpyDeviceToDevice, st));
+    double *res = s->at<double>(s->L.res);
+    mhd_status result = MHD_OK;
+    for (int k = 0; k < n_sweeps && result == MHD_OK; ++k) {
+        result = mag_iteration(s, c, k);
+        if (result != MHD_OK) break;
+        hipError_t e = launch_budget(st, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->bh(s->ch),
+                                     s->at<float>(s->L.bext), s->ctrl(), s->at<double>(s->L.red_part), nullptr, c);
+        if (e == hipSuccess) e = launch_residual_final(st, s->at<double>(s->L.red_part), res + k);
+        if (e != hipSuccess) result = fail(MHD_ERR_HIP, "residual pass failed: %s", hipGetErrorString(e));
+    }
+    // restore the induced field and its buffer state
+    s->cb = cb0;
+    s->ch = ch0;
+    HIPCHK(hipMemcpyAsync(s->b(cb0), stage, bbytes, hipMemcpyDeviceToDevice, st));
+    if (s->split()) HIPCHK(hipMemcpyAsync(s->bh(ch0), stage + bbytes, 3 * (size_t)s->N * 2, hipMemcpyDeviceToDevice, st));
+    if (result != MHD_OK) {
+        (void)hipStreamSynchronize(st);
+        return result;
+    }
+    HIPCHK(hipMemcpyAsync(res_out, res, (size_t)n_sweeps * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     return MHD_OK;
 }
 

@@ -110,6 +110,32 @@ def test_accelerated_sweep_small_pipe_40_steps():
             label="alpha 0.5 pipe8 40 steps")
 
 
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_residual_curve_matches_oracle_and_keeps_the_state(alpha):
+    """Sec. 5.8 residual along the magnetic iteration (u held), against the oracle's sweep +
+    wall correction + residual; the call must leave the state as it was."""
+    print("case residual curve", alpha, flush=True)
+    w = W.small_pipe(b_amp=1e-4)
+    w.params.alpha = alpha
+    sim = gpu_run(w, 0)  # the initial noise in b: a residual that decays along the iteration
+    before = [sim.get_field(f) for f in ("rho", "u", "b")]
+    n = 12
+    curve = sim.mag_residual_curve(n)
+    for f, ref in zip(("rho", "u", "b"), before):
+        assert np.array_equal(sim.get_field(f), ref)
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params)
+    d = oracle.ib_rowsums(p, w.markers)
+    rho, u, b = before
+    ref = []
+    for _ in range(n):
+        b = oracle.ib_correct(p, w.markers, d, 6.0 * w.params.eta, oracle.mag_sweep(p, u, b))
+        ref.append(oracle.budgets(p, rho, u, b, 0.0)["res_mag"])
+    ref = np.array(ref)
+    print("residual curve gpu", curve[[0, -1]], "oracle", ref[[0, -1]], flush=True)
+    assert np.all(np.abs(curve - ref) <= 2e-4 * ref.max()), np.abs(curve - ref).max() / ref.max()
+    sim.step(1)  # stepping afterwards still works
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)

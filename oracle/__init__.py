@@ -40,7 +40,7 @@ class OrcParams(C.Structure):
                 ("fringe_w", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
                 ("radius", C.c_double), ("flow_control", C.c_int), ("u_target", C.c_double),
                 ("k_c", C.c_double), ("ib_u", C.c_int), ("ib_b", C.c_int),
-                ("alpha", C.c_double)]
+                ("alpha", C.c_double), ("magnet_L", C.c_double), ("magnet_D", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -71,6 +71,7 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, _D, _D, _D, C.c_int64, _I64, _D]
         L.orc_budgets.argtypes = [P, _D, _D, _D, C.c_double, _D]
         L.orc_bext.argtypes = [P, C.c_int, C.c_int, C.c_int, _D]
+        L.orc_bext_at.argtypes = [P, C.c_double, C.c_double, C.c_double, _D]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _LIB = L
@@ -92,7 +93,7 @@ def make_params(nx, ny, nz, prm=None, *, ib_u=1, ib_b=1, **over) -> OrcParams:
     """Build OrcParams from a workloads.Params-like object (attribute names match) + overrides."""
     fields = dict(nu=0.1, eta=1.0, n_mag=1, lambda_u=1.0, lambda_b=0.0, G0=0.0, G1=0.0, period=0.0,
                   bext_kind=0, B0=0.0, fringe_x0=0.0, fringe_w=1.0, yc=0.0, zc=0.0, radius=0.0,
-                  flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0)
+                  flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0, magnet_L=0.0, magnet_D=0.0)
     if prm is not None:
         for k in list(fields):
             src = {"radius": "avg_radius", "u_target": "u_bulk_target"}.get(k, k)
@@ -116,6 +117,13 @@ def set_threads(n: int) -> None:
 def bext(p: OrcParams, x, y, z):
     out = np.zeros(3)
     lib().orc_bext(C.byref(p), x, y, z, _ptr(out))
+    return out
+
+
+def bext_at(p: OrcParams, x: float, y: float, z: float):
+    """Imposed field at real coordinates (the six-magnet field is continuous)."""
+    out = np.zeros(3)
+    lib().orc_bext_at(C.byref(p), float(x), float(y), float(z), _ptr(out))
     return out
 
 

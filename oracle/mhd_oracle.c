@@ -52,13 +52,15 @@ typedef struct {
     int n_mag;
     double lambda_u, lambda_b;
     double G0, G1, period;
-    int bext_kind; /* 0 none, 1 uniform along y, 2 tanh fringe along y */
+    int bext_kind; /* 0 none, 1 uniform along y, 2 tanh fringe along y, 3 six magnets */
     double B0, fringe_x0, fringe_w;
     double yc, zc, radius;
     int flow_control;
     double u_target, k_c;
     int ib_u, ib_b; /* 1 = apply the wall correction for u / for b */
     double alpha;   /* accelerated magnetic iteration (Sec. 5.8); <= 0 means 1 (plain sweep) */
+    double magnet_L, magnet_D; /* six magnets: strip half-width (<= 0: radius / 6) and distance
+                                  of the strip centres from the axis (<= 0: see magnet_geometry) */
 } orc_params;
 
 /* D3Q19 velocity set and weights (textbook values; the paper's own table is D3Q27). */
@@ -86,16 +88,66 @@ static inline int64_t cell(const orc_params *p, int x, int y, int z) {
 
 static inline int64_t ncells(const orc_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
 
-/* Imposed field B_ext at cell (x, y, z). */
-void orc_bext(const orc_params *p, int x, int y, int z, double B[3]) {
-    (void)y;
-    (void)z;
+/* Field of one magnet in its own frame (Sec. 6, Biot-Savart form): a strip of half-width L on
+ * z' = 0, |y'| < L; B_y' = 2 [atan((y' - L)/z') - atan((y' + L)/z')],
+ * B_z' = log(((y' + L)^2 + z'^2) / ((y' - L)^2 + z'^2)). */
+static void magnet_local(double yl, double zl, double L, double out[2]) {
+    out[0] = 2.0 * (atan((yl - L) / zl) - atan((yl + L) / zl));
+    out[1] = log(((yl + L) * (yl + L) + zl * zl) / ((yl - L) * (yl - L) + zl * zl));
+}
+
+/* Six magnets with alternating poles on a hexagon around the pipe axis (yc, zc): magnet m sits at
+ * angle 60 m degrees, distance D, its strip tangential and its z' axis pointing radially
+ * outwards, polarity (-1)^m. L defaults to R / 6 (Sec. 6); D defaults to the distance of the
+ * farthest cell of the box from the axis plus L + 1, so no strip reaches into the box. */
+static void magnet_geometry(const orc_params *p, double *L, double *D) {
+    *L = p->magnet_L > 0.0 ? p->magnet_L : p->radius / 6.0;
+    if (p->magnet_D > 0.0) {
+        *D = p->magnet_D;
+    } else {
+        double dy = fmax(p->yc, (double)(p->ny - 1) - p->yc), dz = fmax(p->zc, (double)(p->nz - 1) - p->zc);
+        *D = sqrt(dy * dy + dz * dz) + *L + 1.0;
+    }
+}
+
+static void six_magnets_raw(const orc_params *p, double y, double z, double B[2]) {
+    double L, D;
+    magnet_geometry(p, &L, &D);
+    B[0] = B[1] = 0.0;
+    for (int m = 0; m < 6; ++m) {
+        double th = m * (3.14159265358979323846 / 3.0);
+        double n[2] = {cos(th), sin(th)}, t[2] = {-sin(th), cos(th)};
+        double ry = y - (p->yc + D * n[0]), rz = z - (p->zc + D * n[1]);
+        double yl = ry * t[0] + rz * t[1], zl = ry * n[0] + rz * n[1];
+        double f[2];
+        magnet_local(yl, zl, L, f);
+        double sgn = (m % 2 == 0) ? 1.0 : -1.0;
+        B[0] += sgn * (f[0] * t[0] + f[1] * n[0]);
+        B[1] += sgn * (f[0] * t[1] + f[1] * n[1]);
+    }
+}
+
+/* Imposed field B_ext at a point (x, y, z) of the box (any real coordinates). Six magnets:
+ * scaled so that |B| = B0 at the wall point (yc + R, zc) facing magnet 0. */
+void orc_bext_at(const orc_params *p, double x, double y, double z, double B[3]) {
     B[0] = B[1] = B[2] = 0.0;
     if (p->bext_kind == 1) {
         B[1] = p->B0;
     } else if (p->bext_kind == 2) {
-        B[1] = p->B0 * 0.5 * (1.0 + tanh(((double)x - p->fringe_x0) / p->fringe_w));
+        B[1] = p->B0 * 0.5 * (1.0 + tanh((x - p->fringe_x0) / p->fringe_w));
+    } else if (p->bext_kind == 3) {
+        double f[2], r[2];
+        six_magnets_raw(p, y, z, f);
+        six_magnets_raw(p, p->yc + p->radius, p->zc, r);
+        double s = p->B0 / sqrt(r[0] * r[0] + r[1] * r[1]);
+        B[1] = s * f[0];
+        B[2] = s * f[1];
     }
+}
+
+/* Imposed field at cell (x, y, z). */
+void orc_bext(const orc_params *p, int x, int y, int z, double B[3]) {
+    orc_bext_at(p, (double)x, (double)y, (double)z, B);
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -136,6 +136,50 @@ def test_residual_curve_matches_oracle_and_keeps_the_state(alpha):
     sim.step(1)  # stepping afterwards still works
 
 
+def _transition_case(eta):
+    """8x32x32 pipe, Ha 5 kept, oscillating force (T = 200), N_mag = ceil(6 eta) (Sec. 5.7)."""
+    w = W.small_pipe()
+    w.params.eta = eta
+    w.params.n_mag = W.n_mag_for(eta)
+    w.params.B0 = 5.0 * math.sqrt(eta * w.params.nu) / 14.0
+    w.params.G1 = -3.0 * w.params.G0
+    w.params.G0 = 0.0
+    w.params.period = 200.0
+    return w
+
+
+def test_qs_to_canonical_transition_budget_series():
+    """Energy-budget time series under unsteady forcing (Sec. 4 / Sec. 5.7 transition): at eta = 2
+    (N = 12) the induced field's energy changes in time and dE_b/dt balances M_eta + M_adv; at
+    eta = 45 (N = 270) its time derivative is damped (the quasi-static regime). The eta = 2 series
+    matches the oracle's record by record."""
+    ratios = {}
+    for eta, steps in ((2.0, 150), (45.0, 150)):
+        print("case transition eta", eta, flush=True)
+        w = _transition_case(eta)
+        sim = gpu_run(w, steps, budget_every=1)
+        rec = sim.budgets()
+        assert len(rec) == steps
+        Eb = np.array([r["E_b"] for r in rec])
+        Meta = np.array([r["M_eta"] for r in rec])
+        Madv = np.array([r["M_adv"] for r in rec])
+        dEb = (Eb[2:] - Eb[:-2]) / 2
+        ratios[eta] = np.abs(dEb).max() / np.abs(Meta).max()
+        if eta == 2.0:
+            assert np.abs(dEb - (Meta + Madv)[1:-1]).max() <= 0.06 * np.abs(Meta).max()
+            o = oracle_run(w, 0)
+            for k in range(steps):
+                o.step(1)
+                if k in (9, 49, 149):
+                    ref, r = o.budgets(), rec[k]
+                    for f in ("E_k", "E_b", "Q"):
+                        assert abs(r[f] - ref[f]) <= 3e-5 * abs(ref[f]), (k, f, r[f], ref[f])
+                    for f in ("P_L", "M_eta", "M_adv"):
+                        assert abs(r[f] - ref[f]) <= 1e-3 * abs(ref[f]), (k, f, r[f], ref[f])
+    print("dE_b/dt over M_eta:", ratios, flush=True)
+    assert ratios[2.0] >= 0.05 and ratios[45.0] <= 0.01
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)

@@ -510,6 +510,89 @@ def test_plane_hartmann_closed_form_solves_its_ode():
     np.testing.assert_allclose(ba, 0.0, atol=1e-12)
 
 
+def test_unsteady_kinetic_energy_balance_holds_step_by_step():
+    # Sec. 4 energy balance under the variable force G(t) = G1 cos(2 pi t / T): the central
+    # difference of the recorded E_k equals P_in + P_p + P_nu + P_L to the scheme's accuracy.
+    w = W.small_pipe()
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params, G0=0.0, G1=-3 * w.params.G0, period=200.0,
+                           n_mag=60)
+    o = oracle.Oracle(p, w.markers, w.rho, w.u, w.b)
+    rec = []
+    for _ in range(120):
+        o.step(1)
+        rec.append(o.budgets())
+    E = np.array([r["E_k"] for r in rec])
+    P = np.array([r["P_in"] + r["P_p"] + r["P_nu"] + r["P_L"] for r in rec])
+    dE = (E[2:] - E[:-2]) / 2
+    assert np.abs(dE).max() > 0.5 * max(abs(r["P_in"]) for r in rec)  # really unsteady
+    assert np.abs(dE - P[1:-1]).max() <= 0.05 * np.abs(P).max()
+
+
+# --------------------------------------------------------------------------------------------
+# Six-magnet imposed field (Sec. 6)
+# --------------------------------------------------------------------------------------------
+
+def _magnet_params(n=40, R=14.0, B0=0.3):
+    return oracle.make_params(8, n, n, bext_kind=W.BEXT_SIX_MAGNETS, B0=B0, radius=R, yc=n // 2,
+                              zc=n // 2)
+
+
+def test_six_magnet_field_is_harmonic_in_the_box():
+    # Biot-Savart field outside its sources: divergence- and curl-free (central differences,
+    # h = 1e-4, at seeded points of the box); this also makes the induced-field iteration exact
+    # (reading of the unknown: lap B_ext = 0).
+    p = _magnet_params()
+    g = W.rng_for(120)
+    h = 1e-4
+    for y, z in g.uniform(0, 39, size=(25, 2)):
+        def B(yy, zz):
+            return oracle.bext_at(p, 0.0, yy, zz)
+        dBdy = (B(y + h, z) - B(y - h, z)) / (2 * h)
+        dBdz = (B(y, z + h) - B(y, z - h)) / (2 * h)
+        scale = np.abs(dBdy).max() + np.abs(dBdz).max()
+        assert abs(dBdy[1] + dBdz[2]) <= 1e-6 * scale
+        assert abs(dBdy[2] - dBdz[1]) <= 1e-6 * scale
+        assert B(y, z)[0] == 0.0
+
+
+def test_six_magnet_field_alternates_under_a_sixth_turn_and_is_scaled_to_B0():
+    p = _magnet_params()
+    yc = zc = 20.0
+    c, s = math.cos(math.pi / 3), math.sin(math.pi / 3)
+    g = W.rng_for(121)
+    for y, z in g.uniform(8, 32, size=(20, 2)):
+        ry, rz = y - yc, z - zc
+        B = oracle.bext_at(p, 0.0, y, z)
+        Br = oracle.bext_at(p, 0.0, yc + c * ry - s * rz, zc + s * ry + c * rz)
+        rot = np.array([c * B[1] - s * B[2], s * B[1] + c * B[2]])
+        np.testing.assert_allclose(Br[1:], -rot, atol=1e-12 * np.abs(B).max())
+    wall = oracle.bext_at(p, 0.0, yc + 14.0, zc)
+    assert abs(np.linalg.norm(wall) - 0.3) < 1e-14
+    # finite everywhere in the box: the strips lie outside it
+    field = np.array([[oracle.bext(p, 0, y, z) for z in range(40)] for y in range(40)])
+    assert np.isfinite(field).all() and np.abs(field).max() < 10 * 0.3
+
+
+def test_six_magnet_flow_keeps_the_mirror_symmetries():
+    # Odd box centred on the axis (the mirrors map the periodic box onto itself without using
+    # the seam, where the non-periodic field jumps) and a ring of 88 markers: the hexapole is
+    # symmetric under z -> -z and antisymmetric (alternating poles) under y -> -y, so u_x is
+    # even in both and b_x odd in z, even in y.
+    n = 33
+    w = W.pipe_workload("six_magnets", 7, 8, n, n, 14.0, 50.0, 10.0, 1e-2,
+                        bext_kind=W.BEXT_SIX_MAGNETS, noise=0.0)
+    assert w.params.yc == (n - 1) / 2 and w.markers.shape[1] == 8 * 88
+    p = oracle.make_params(w.nx, w.ny, w.nz, w.params, n_mag=20)
+    o = oracle.Oracle(p, w.markers, w.rho, w.u, w.b)
+    o.step(15)
+    ux, bx = o.u[0], o.b[0]
+    assert np.abs(ux).max() > 1e-4 and np.abs(bx).max() > 1e-6
+    for f, sz, sy in ((ux, 1, 1), (bx, -1, 1)):
+        s = np.abs(f).max()
+        assert np.abs(np.flip(f, axis=0) - sz * f).max() <= 1e-11 * s
+        assert np.abs(np.flip(f, axis=1) - sy * f).max() <= 1e-11 * s
+
+
 def test_flow_rate_control_reaches_its_target():
     # Integral control of G on the bulk velocity over the flow region: at steady state the
     # plane channel carries the parabola whose node average equals the target, so

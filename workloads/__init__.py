@@ -27,6 +27,7 @@ U0 = 0.05  # reference (bulk) velocity in lattice units
 BEXT_NONE = 0
 BEXT_UNIFORM_Y = 1
 BEXT_TANH_FRINGE_Y = 2
+BEXT_SIX_MAGNETS = 3
 
 
 @dataclasses.dataclass
@@ -51,6 +52,8 @@ class Params:
     u_bulk_target: float = 0.0
     k_c: float = 0.1
     alpha: float = 1.0  # accelerated magnetic iteration (1: plain sweep)
+    magnet_L: float = 0.0  # six magnets: strip half-width (<= 0: R / 6)
+    magnet_D: float = 0.0  # six magnets: distance of the strips from the axis (<= 0: outside the box)
 
 
 @dataclasses.dataclass

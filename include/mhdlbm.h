@@ -60,7 +60,15 @@ typedef struct {
 typedef enum {
     MHD_BEXT_NONE = 0,
     MHD_BEXT_UNIFORM_Y = 1,     /* B_ext = (0, B0, 0)                                    */
-    MHD_BEXT_TANH_FRINGE_Y = 2  /* B_ext = (0, B0 (1 + tanh((x - fringe_x0)/fringe_w))/2, 0) */
+    MHD_BEXT_TANH_FRINGE_Y = 2, /* B_ext = (0, B0 (1 + tanh((x - fringe_x0)/fringe_w))/2, 0) */
+    MHD_BEXT_SIX_MAGNETS = 3    /* six magnets with alternating poles on a hexagon around the
+                                   axis (yc, zc) (Sec. 6): one magnet's field in its own frame is
+                                   B_y' = 2 [atan((y'-L)/z') - atan((y'+L)/z')],
+                                   B_z' = log(((y'+L)^2 + z'^2) / ((y'-L)^2 + z'^2)) (a strip of
+                                   half-width L on z' = 0); magnet m at angle 60 m degrees,
+                                   distance magnet_distance, strip tangential, z' radial outwards,
+                                   polarity (-1)^m; scaled so |B_ext| = B0 at (yc + R, zc), R =
+                                   avg_radius. Independent of x.                             */
 } mhd_bext_kind;
 
 /* Physical parameters (lattice units). */
@@ -89,6 +97,10 @@ typedef struct {
                              with S the plain sweep; same fixed point, slow modes converge
                              1/alpha times faster. 0 or 1: plain sweep. Must be >= 4/9 (the
                              D3Q19 averaging symbol is >= 1/9, so smaller alpha diverges). */
+    double magnet_half_width; /* six magnets: L; <= 0 -> avg_radius / 6 (Sec. 6)            */
+    double magnet_distance;   /* six magnets: distance of the strip centres from the axis;
+                                 <= 0 -> distance of the farthest cell of the box from the axis
+                                 + L + 1 (no strip reaches into the box)                      */
 } mhd_params;
 
 typedef enum { MHD_FIELD_RHO = 0, MHD_FIELD_U = 1, MHD_FIELD_B_INDUCED = 2 } mhd_field;

@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import (MHD_BEXT_NONE, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_UNIFORM_Y, MHD_FIELD_B_INDUCED,
+from ._abi import (MHD_BEXT_NONE, MHD_BEXT_SIX_MAGNETS, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_UNIFORM_Y,
+                   MHD_FIELD_B_INDUCED,
                    MHD_FIELD_RHO, MHD_FIELD_U, MHD_K_BUDGET, MHD_K_CONTROL, MHD_K_FLUID,
                    MHD_K_IB, MHD_K_LORENTZ, MHD_K_MAG_SWEEP,
                    MHD_STORE_BF16, MHD_STORE_F16, MHD_STORE_F16_SPLIT, MHD_STORE_F32, MhdError,
@@ -225,12 +226,18 @@ def make_params(src=None, **over) -> mhd_params:
     names = [f for f, _ in mhd_params._fields_ if f != "reserved0"]
     vals = {}
     if src is not None:
+        alias = {"magnet_half_width": "magnet_L", "magnet_distance": "magnet_D"}
         for f in names:
+            g = alias.get(f, f)
             if isinstance(src, dict):
                 if f in src:
                     vals[f] = src[f]
+                elif g in src:
+                    vals[f] = src[g]
             elif hasattr(src, f):
                 vals[f] = getattr(src, f)
+            elif hasattr(src, g):
+                vals[f] = getattr(src, g)
     vals.update(over)
     for f, v in vals.items():
         setattr(p, f, int(v) if f in ("n_mag", "bext_kind", "flow_control") else float(v))

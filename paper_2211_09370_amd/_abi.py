@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "UNSTABLE"
                 -6: "UNSUPPORTED"}
 
 MHD_STORE_F32, MHD_STORE_F16, MHD_STORE_BF16, MHD_STORE_F16_SPLIT = 0, 1, 2, 3
-MHD_BEXT_NONE, MHD_BEXT_UNIFORM_Y, MHD_BEXT_TANH_FRINGE_Y = 0, 1, 2
+MHD_BEXT_NONE, MHD_BEXT_UNIFORM_Y, MHD_BEXT_TANH_FRINGE_Y, MHD_BEXT_SIX_MAGNETS = 0, 1, 2, 3
 MHD_FIELD_RHO, MHD_FIELD_U, MHD_FIELD_B_INDUCED = 0, 1, 2
 (MHD_K_MAG_SWEEP, MHD_K_IB, MHD_K_LORENTZ, MHD_K_FLUID, MHD_K_BUDGET, MHD_K_CONTROL,
  MHD_K_COUNT) = range(7)
@@ -54,7 +54,8 @@ class mhd_params(C.Structure):
                 ("B0", C.c_double), ("fringe_x0", C.c_double), ("fringe_w", C.c_double),
                 ("yc", C.c_double), ("zc", C.c_double), ("avg_radius", C.c_double),
                 ("flow_control", C.c_int32), ("reserved0", C.c_int32),
-                ("u_bulk_target", C.c_double), ("k_c", C.c_double), ("alpha", C.c_double)]
+                ("u_bulk_target", C.c_double), ("k_c", C.c_double), ("alpha", C.c_double),
+                ("magnet_half_width", C.c_double), ("magnet_distance", C.c_double)]
 
 
 class mhd_budget(C.Structure):

@@ -46,6 +46,7 @@ constexpr int kResCap = 4096;      // residual values of one mhd_mag_residual_cu
 struct SweepLaunch {
     int tx, ty, zchunk;  // tile shape and z extent of one workgroup
     int pair;            // 1: two x cells per lane (n_x a multiple of 128); ty = rows per tile
+    int byz = 0;         // 1: add the (y, z) table of B_ext (six magnets) while staging
 };
 
 // Arguments of one magnetic sweep launch over one box.
@@ -56,6 +57,7 @@ struct SweepArgs {
     const void *bh;     // split form: hi part of b (else NULL)
     void *bho;          // split form, first sweep of a step: re-split hi output (else NULL)
     const float *bext;  // 3 x nx
+    const float *bext_yz;  // 3 x (ny nz) table added to bext (six magnets), else NULL
     int nx, ny, nz;
     int tiles_x, tiles_y, nzc, zchunk, nblocks;
     float kappa, u_scale, b_scale, inv_b_scale;
@@ -89,17 +91,17 @@ struct IbArgs {
 };
 // Interpolation launch, then spreading launch.
 hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_scale, const IbArgs &a);
-// b_hi: hi part of b in the split form (else NULL).
+// b_hi: hi part of b in the split form (else NULL); bext_yz: (y, z) table added to bext, or NULL.
 hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *b_hi, const float *bext,
-                          const DevCtrl *ctrl, float *F, StepConst c);
+                          const float *bext_yz, const DevCtrl *ctrl, float *F, StepConst c);
 // u_copy: float16 copy of the new u (u / u_scale) for the split form's sweeps (else NULL).
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,
                         void *rho_o, void *u_o, void *u_copy, StepConst c);
 hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c);
 // ring == NULL: the partials only (for launch_residual_final).
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b,
-                         const void *b_hi, const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring,
-                         StepConst c);
+                         const void *b_hi, const float *bext, const float *bext_yz, DevCtrl *ctrl, double *part,
+                         mhd_budget *ring, StepConst c);
 // -------------------------------------------------------------------------------------------
 // Batched launches: one launch covers the same kernel for many boxes. Each workgroup finds its
 // box and its workgroup index within that box in a map of (box, local workgroup) pairs, then
@@ -114,6 +116,7 @@ struct PipeStep {
     float scale[3], inv_scale[3];
     const void *b_last;       // b after the box's last sweep (Lorentz input)
     const void *b_hi;         // split form: hi part of b during and after the sweeps (else NULL)
+    const float *bext_yz;     // (y, z) table of B_ext (six magnets), else NULL
     void *u_copy;             // split form: float16 copy of u written by the fluid kernel (else NULL)
     const float *bext;
     DevCtrl *ctrl;

@@ -201,8 +201,8 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_spread(T *phi, float scale, f
 // -------------------------------------------------------------------------------------------
 template <typename TB, bool BATCH, bool SPLIT>
 __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB *bh, float bs, const float *bext,
-                                                          const DevCtrl *ctrl, float *F, StepConst c,
-                                                          const PipeStep *tab, const BlockMap *map) {
+                                                          const float *bext_yz, const DevCtrl *ctrl, float *F,
+                                                          StepConst c, const PipeStep *tab, const BlockMap *map) {
     int64_t blk = blockIdx.x;
     if constexpr (BATCH) {
         const BlockMap m = map[blk];
@@ -211,6 +211,7 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
         bh = (const TB *)q.b_hi;
         bs = q.c.b_scale;
         bext = q.bext;
+        bext_yz = q.bext_yz;
         ctrl = q.ctrl;
         F = q.F;
         c = q.c;
@@ -246,9 +247,15 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
         }
     }
     const float Jx = g[2][1] - g[1][2], Jy = g[0][2] - g[2][0], Jz = g[1][0] - g[0][1];
-    const float Bx = bv(k) * bs + bext[x];
-    const float By = bv(N + k) * bs + bext[c.nx + x];
-    const float Bz = bv(2 * N + k) * bs + bext[2 * c.nx + x];
+    float Bx = bv(k) * bs + bext[x];
+    float By = bv(N + k) * bs + bext[c.nx + x];
+    float Bz = bv(2 * N + k) * bs + bext[2 * c.nx + x];
+    if (bext_yz) {  // six magnets: (y, z) part of B_ext
+        const int64_t pyz = (int64_t)c.ny * c.nz, o = y + (int64_t)c.ny * z;
+        Bx += bext_yz[o];
+        By += bext_yz[pyz + o];
+        Bz += bext_yz[2 * pyz + o];
+    }
     const float G = (float)ctrl->G_step;
     F[k] = G + (Jy * Bz - Jz * By);
     F[N + k] = Jz * Bx - Jx * Bz;
@@ -417,8 +424,8 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
 // residual of Sec. 5.8), 14 max |u|^2, 15 nonfinite
 template <typename TR, typename TU, typename TB>
 __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, const TU *u, const TB *b,
-                                                                const TB *bh, const float *bext, double *part,
-                                                                StepConst c) {
+                                                                const TB *bh, const float *bext,
+                                                                const float *bext_yz, double *part, StepConst c) {
     __shared__ double sh[14][kRedThreads];
     __shared__ double shm[kRedThreads];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
@@ -441,6 +448,7 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
             bb[a] = (double)St<TB>::ld(b, a * N + k) * bs;
             if (bh) bb[a] += (double)St<TB>::ld(bh, a * N + k) * bs;
             B[a] = bb[a] + (double)bext[a * c.nx + x];
+            if (bext_yz) B[a] += (double)bext_yz[a * (int64_t)c.ny * c.nz + y + (int64_t)c.ny * z];
         }
         const double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
         if (!isfinite(u2) || !isfinite(r)) nonfin = 1.0;
@@ -464,6 +472,9 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
                 bn[a] = (double)St<TB>::ld(b, a * N + kn) * bs;
                 if (bh) bn[a] += (double)St<TB>::ld(bh, a * N + kn) * bs;
                 Bn[a] = bn[a] + (double)bext[a * c.nx + xn];
+                if (bext_yz)
+                    Bn[a] += (double)bext_yz[a * (int64_t)c.ny * c.nz + wrapi(y + e[1], c.ny) +
+                                             (int64_t)c.ny * wrapi(z + e[2], c.nz)];
             }
             for (int a = 0; a < 3; ++a) {
                 grho[a] += 3.0 * w * e[a] * rn;
@@ -687,20 +698,20 @@ hipError_t launch_ib_spread_batch(hipStream_t s, int kind, const PipeStep *tab, 
 }
 
 template <typename T, bool SPLIT>
-static hipError_t lorentz_t(hipStream_t s, const void *b, const void *bh, const float *bext, const DevCtrl *ctrl,
-                            float *F, StepConst c) {
+static hipError_t lorentz_t(hipStream_t s, const void *b, const void *bh, const float *bext, const float *bext_yz,
+                            const DevCtrl *ctrl, float *F, StepConst c) {
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     hipLaunchKernelGGL((k_lorentz<T, false, SPLIT>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads), 0, s,
-                       (const T *)b, (const T *)bh, c.b_scale, bext, ctrl, F, c, nullptr, nullptr);
+                       (const T *)b, (const T *)bh, c.b_scale, bext, bext_yz, ctrl, F, c, nullptr, nullptr);
     return hipGetLastError();
 }
 hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *b_hi, const float *bext,
-                          const DevCtrl *ctrl, float *F, StepConst c) {
+                          const float *bext_yz, const DevCtrl *ctrl, float *F, StepConst c) {
     switch (kind_b) {
-        case MHD_KIND_F32: return lorentz_t<float, false>(s, b, b_hi, bext, ctrl, F, c);
-        case MHD_KIND_F16: return lorentz_t<__half, false>(s, b, b_hi, bext, ctrl, F, c);
-        case MHD_KIND_BF16: return lorentz_t<__hip_bfloat16, false>(s, b, b_hi, bext, ctrl, F, c);
-        case MHD_KIND_F16_SPLIT: return lorentz_t<__half, true>(s, b, b_hi, bext, ctrl, F, c);
+        case MHD_KIND_F32: return lorentz_t<float, false>(s, b, b_hi, bext, bext_yz, ctrl, F, c);
+        case MHD_KIND_F16: return lorentz_t<__half, false>(s, b, b_hi, bext, bext_yz, ctrl, F, c);
+        case MHD_KIND_BF16: return lorentz_t<__hip_bfloat16, false>(s, b, b_hi, bext, bext_yz, ctrl, F, c);
+        case MHD_KIND_F16_SPLIT: return lorentz_t<__half, true>(s, b, b_hi, bext, bext_yz, ctrl, F, c);
         default: return hipErrorInvalidValue;
     }
 }
@@ -708,7 +719,7 @@ template <typename T, bool SPLIT>
 static hipError_t lorentz_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int nblocks) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_lorentz<T, true, SPLIT>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr, nullptr, 0.f,
-                       nullptr, nullptr, nullptr, StepConst{}, tab, map);
+                       nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map);
     return hipGetLastError();
 }
 hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks) {
@@ -777,9 +788,10 @@ hipError_t launch_flow_partial_batch(hipStream_t s, int kind_u, const PipeStep *
 
 template <typename TR, typename TU, typename TB>
 static hipError_t budget_t(hipStream_t s, const void *rho, const void *u, const void *b, const void *bh,
-                           const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
+                           const float *bext, const float *bext_yz, DevCtrl *ctrl, double *part, mhd_budget *ring,
+                           StepConst c) {
     hipLaunchKernelGGL((k_budget_partial<TR, TU, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, (const TR *)rho,
-                       (const TU *)u, (const TB *)b, (const TB *)bh, bext, part, c);
+                       (const TU *)u, (const TB *)b, (const TB *)bh, bext, bext_yz, part, c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !ring) return e;  // no ring: partials only
     hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(kRedThreads), 0, s, part, ctrl, ring, c);
@@ -791,18 +803,19 @@ hipError_t launch_residual_final(hipStream_t s, const double *part, double *out)
 }
 
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b, const void *b_hi,
-                         const float *bext, DevCtrl *ctrl, double *part, mhd_budget *ring, StepConst c) {
+                         const float *bext, const float *bext_yz, DevCtrl *ctrl, double *part, mhd_budget *ring,
+                         StepConst c) {
     const int kr = kinds & 15, ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
     if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
-        return budget_t<float, float, float>(s, rho, u, b, nullptr, bext, ctrl, part, ring, c);
+        return budget_t<float, float, float>(s, rho, u, b, nullptr, bext, bext_yz, ctrl, part, ring, c);
     if (kr == MHD_KIND_F32 && ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)
-        return budget_t<float, float, __half>(s, rho, u, b, b_hi, bext, ctrl, part, ring, c);
+        return budget_t<float, float, __half>(s, rho, u, b, b_hi, bext, bext_yz, ctrl, part, ring, c);
     if (kr == MHD_KIND_F16 && ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
-        return budget_t<__half, __half, __half>(s, rho, u, b, nullptr, bext, ctrl, part, ring, c);
+        return budget_t<__half, __half, __half>(s, rho, u, b, nullptr, bext, bext_yz, ctrl, part, ring, c);
     if (kr == MHD_KIND_F16 && ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
-        return budget_t<__half, __hip_bfloat16, __half>(s, rho, u, b, nullptr, bext, ctrl, part, ring, c);
+        return budget_t<__half, __hip_bfloat16, __half>(s, rho, u, b, nullptr, bext, bext_yz, ctrl, part, ring, c);
     if (kr == MHD_KIND_BF16 && ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
-        return budget_t<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>(s, rho, u, b, nullptr, bext, ctrl, part, ring,
+        return budget_t<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>(s, rho, u, b, nullptr, bext, bext_yz, ctrl, part, ring,
                                                                          c);
     return hipErrorInvalidValue;
 }

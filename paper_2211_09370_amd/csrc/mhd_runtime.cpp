@@ -50,7 +50,7 @@ constexpr int64_t kBandSlots = 64;
 
 // Byte offsets of every region of the caller's workspace.
 struct Layout {
-    size_t rho[2], u[2], b[2], bh[2], u16, F, bext, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
+    size_t rho[2], u[2], b[2], bh[2], u16, F, bext, bext_yz, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
     size_t band_cell, band_mk, band_w, red_part, flow_part, ring, res, total;
 };
 
@@ -74,6 +74,7 @@ Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     }
     L.F = take(3 * N * sizeof(float));
     L.bext = take(3 * (size_t)g.nx * sizeof(float));
+    L.bext_yz = take(3 * (size_t)g.ny * g.nz * sizeof(float));
     L.ctrl = take(sizeof(DevCtrl));
     L.tap_cell = take(T * sizeof(int));
     L.tap_w = take(T * sizeof(float));
@@ -169,6 +170,10 @@ struct mhd_sim {
     bool split() const { return g.b_storage == MHD_STORE_F16_SPLIT; }
     void *bh(int i) const { return split() ? ws + L.bh[i] : nullptr; }
     void *u16() const { return split() ? ws + L.u16 : nullptr; }
+    const float *byz() const {  // (y, z) part of B_ext, present for the six-magnet field only
+        return have_params && prm.bext_kind == MHD_BEXT_SIX_MAGNETS ? reinterpret_cast<const float *>(ws + L.bext_yz)
+                                                                    : nullptr;
+    }
     DevCtrl *ctrl() const { return at<DevCtrl>(L.ctrl); }
 };
 
@@ -229,9 +234,28 @@ mhd_status upload_scalings(mhd_sim *s) {
     return MHD_OK;
 }
 
-// Imposed field per x plane (3 x nx table).
+// Six magnets with alternating poles on a hexagon around (yc, zc) (Sec. 6): the (y, z) field
+// of magnet k (angle 60 k degrees, strip of half-width Lh tangential, local z' radial outwards,
+// polarity (-1)^k), summed; unscaled.
+void hexapole_field(const mhd_params &p, double Lh, double D, double y, double z, double &By, double &Bz) {
+    By = Bz = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        const double ang = k * (3.14159265358979323846 / 3.0);
+        const double ny_ = std::cos(ang), nz_ = std::sin(ang);  // radial unit vector
+        const double ty = -nz_, tz = ny_;                          // tangential unit vector
+        const double dy = y - (p.yc + D * ny_), dz = z - (p.zc + D * nz_);
+        const double yl = dy * ty + dz * tz, zl = dy * ny_ + dz * nz_;
+        const double fy = 2.0 * (std::atan((yl - Lh) / zl) - std::atan((yl + Lh) / zl));
+        const double fz = std::log(((yl + Lh) * (yl + Lh) + zl * zl) / ((yl - Lh) * (yl - Lh) + zl * zl));
+        const double sign = (k & 1) ? -1.0 : 1.0;
+        By += sign * (fy * ty + fz * ny_);
+        Bz += sign * (fy * tz + fz * nz_);
+    }
+}
+
+// Imposed field: per x plane (3 x nx table) and, for the six magnets, per (y, z) (3 x ny nz).
 mhd_status upload_bext(mhd_sim *s) {
-    const int nx = s->g.nx;
+    const int nx = s->g.nx, ny = s->g.ny, nz = s->g.nz;
     std::vector<float> t(3 * (size_t)nx, 0.f);
     const mhd_params &p = s->prm;
     for (int x = 0; x < nx; ++x) {
@@ -244,6 +268,31 @@ mhd_status upload_bext(mhd_sim *s) {
     }
     HIPCHK(hipMemcpyAsync(s->at<float>(s->L.bext), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice,
                           s->stream));
+    if (p.bext_kind == MHD_BEXT_SIX_MAGNETS) {
+        const double Lh = p.magnet_half_width > 0.0 ? p.magnet_half_width : p.avg_radius / 6.0;
+        double D = p.magnet_distance;
+        if (!(D > 0.0)) {  // beyond the farthest cell of the box
+            const double fy = std::max(p.yc, (double)(ny - 1) - p.yc), fz = std::max(p.zc, (double)(nz - 1) - p.zc);
+            D = std::sqrt(fy * fy + fz * fz) + Lh + 1.0;
+        }
+        double ry, rz;
+        hexapole_field(p, Lh, D, p.yc + p.avg_radius, p.zc, ry, rz);
+        const double scale = p.B0 / std::sqrt(ry * ry + rz * rz);
+        const size_t pyz = (size_t)ny * nz;
+        std::vector<float> tyz(3 * pyz, 0.f);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y) {
+                double By, Bz;
+                hexapole_field(p, Lh, D, (double)y, (double)z, By, Bz);
+                if (!std::isfinite(By) || !std::isfinite(Bz))
+                    return fail(MHD_ERR_INVALID_ARG, "six-magnet field is singular at cell (y %d, z %d): magnets inside the box",
+                                y, z);
+                tyz[pyz + y + (size_t)ny * z] = (float)(scale * By);
+                tyz[2 * pyz + y + (size_t)ny * z] = (float)(scale * Bz);
+            }
+        HIPCHK(hipMemcpyAsync(s->at<float>(s->L.bext_yz), tyz.data(), tyz.size() * sizeof(float), hipMemcpyHostToDevice,
+                              s->stream));
+    }
     HIPCHK(hipStreamSynchronize(s->stream));
     return MHD_OK;
 }
@@ -350,6 +399,7 @@ mhd_status mag_iteration(mhd_sim *s, const StepConst &c, int m) {
         {  // timed by events the launch stamps at kernel start / end
             SweepArgs a = make_sweep_args(s->split() ? s->u16() : s->u(s->cu), s->b(s->cb), s->b(nb),
                                           s->at<float>(s->L.bext), c, s->sweep);
+            a.bext_yz = s->byz();
             if (s->split()) {  // first sweep of the step re-splits b into a new hi and lo
                 a.u_scale = c.copy_scale;
                 a.bh = s->bh(s->ch);
@@ -376,8 +426,8 @@ mhd_status one_step(mhd_sim *s) {
     // 2. Lorentz + body force from the new b
     float *F = s->at<float>(s->L.F);
     STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
-        return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->bh(s->ch), s->at<float>(s->L.bext), s->ctrl(), F,
-                              c);
+        return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->bh(s->ch), s->at<float>(s->L.bext), s->byz(),
+                              s->ctrl(), F, c);
     }));
     // 3. fluid predictor, 4. velocity wall correction
     const int nr = 1 - s->cr, nu = 1 - s->cu;
@@ -403,7 +453,7 @@ mhd_status record_budget(mhd_sim *s) {
     const StepConst c = step_const(s);
     return timed(s, MHD_K_BUDGET, "budget", [&] {
         return launch_budget(s->stream, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->bh(s->ch),
-                             s->at<float>(s->L.bext), s->ctrl(), s->at<double>(s->L.red_part),
+                             s->at<float>(s->L.bext), s->byz(), s->ctrl(), s->at<double>(s->L.red_part),
                              s->at<mhd_budget>(s->L.ring), c);
     });
 }
@@ -643,7 +693,9 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
     if (!(tau < 1.0)) return fail(MHD_ERR_UNSUPPORTED, "tau = %g >= 1 needs the macroscopic fluid branch (not built)", tau);
     if (!(p->eta > 0.0)) return fail(MHD_ERR_INVALID_ARG, "eta must be > 0");
     if (p->n_mag < 1) return fail(MHD_ERR_INVALID_ARG, "n_mag must be >= 1");
-    if (p->bext_kind < 0 || p->bext_kind > 2) return fail(MHD_ERR_INVALID_ARG, "unknown bext_kind %d", p->bext_kind);
+    if (p->bext_kind < 0 || p->bext_kind > 3) return fail(MHD_ERR_INVALID_ARG, "unknown bext_kind %d", p->bext_kind);
+    if (p->bext_kind == MHD_BEXT_SIX_MAGNETS && !(p->avg_radius > 0.0))
+        return fail(MHD_ERR_INVALID_ARG, "the six-magnet field needs avg_radius > 0");
     if (p->bext_kind == MHD_BEXT_TANH_FRINGE_Y && !(p->fringe_w > 0.0))
         return fail(MHD_ERR_INVALID_ARG, "fringe_w must be > 0");
     if (p->flow_control && !(p->avg_radius > 0.0)) return fail(MHD_ERR_INVALID_ARG, "flow control needs avg_radius > 0");
@@ -651,7 +703,8 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
         return fail(MHD_ERR_INVALID_ARG, "alpha = %g: the accelerated sweep needs alpha >= 4/9 (or 0 for the plain sweep)",
                     p->alpha);
     for (double v : {p->nu, p->eta, p->lambda_u, p->lambda_b, p->G0, p->G1, p->period, p->B0, p->fringe_x0, p->fringe_w,
-                     p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c, p->alpha})
+                     p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c, p->alpha, p->magnet_half_width,
+                     p->magnet_distance})
         if (!std::isfinite(v)) return fail(MHD_ERR_INVALID_ARG, "non-finite parameter");
     const bool first = !s->have_params;
     const mhd_params old = s->prm;
@@ -792,7 +845,8 @@ mhd_status mhd_mag_residual_curve(mhd_sim *s, int32_t n_sweeps, double *res_out)
         result = mag_iteration(s, c, k);
         if (result != MHD_OK) break;
         hipError_t e = launch_budget(st, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->bh(s->ch),
-                                     s->at<float>(s->L.bext), s->ctrl(), s->at<double>(s->L.red_part), nullptr, c);
+                                     s->at<float>(s->L.bext), s->byz(), s->ctrl(), s->at<double>(s->L.red_part),
+                                     nullptr, c);
         if (e == hipSuccess) e = launch_residual_final(st, s->at<double>(s->L.red_part), res + k);
         if (e != hipSuccess) result = fail(MHD_ERR_HIP, "residual pass failed: %s", hipGetErrorString(e));
     }
@@ -1014,10 +1068,11 @@ mhd_status build_plan(mhd_batch *b) {
     std::vector<BlockMap> map;
     // sweep groups, one per tile form
     b->groups.clear();
-    auto key = [](const SweepLaunch &L) { return L.pair ? 100 + L.ty : L.tx; };
+    auto key = [](const SweepLaunch &L) { return (L.pair ? 100 + L.ty : L.tx) + 1000 * L.byz; };
     for (int p : b->order) {
         mhd_sim *s = b->pipes[p];
-        const SweepLaunch e = effective_tiles(s->sweep, s->g.nx);
+        SweepLaunch e = effective_tiles(s->sweep, s->g.nx);
+        e.byz = s->byz() != nullptr;
         BatchGroup *g = nullptr;
         for (auto &x : b->groups)
             if (key(x.L) == key(e)) g = &x;
@@ -1096,6 +1151,7 @@ PipeStep pipe_step(mhd_sim *s) {
     const void *us = s->split() ? s->u16() : s->u(cu);
     q.sw[0] = make_sweep_args(us, s->b(cb), s->b(1 - cb), bext, c, e);
     q.sw[1] = make_sweep_args(us, s->b(1 - cb), s->b(cb), bext, c, e);
+    q.sw[0].bext_yz = q.sw[1].bext_yz = s->byz();
     q.sw[2] = q.sw[0];
     if (s->split()) {  // round 0 re-splits hi(ch) -> hi(1 - ch); later rounds read the new hi
         for (auto &w : q.sw) {
@@ -1121,6 +1177,7 @@ PipeStep pipe_step(mhd_sim *s) {
     q.inv_scale[2] = c.inv_u_scale;
     q.b_last = s->b((s->prm.n_mag & 1) ? 1 - cb : cb);
     q.b_hi = s->split() ? s->bh(1 - ch) : nullptr;
+    q.bext_yz = s->byz();
     q.u_copy = s->u16();
     q.bext = bext;
     q.ctrl = s->ctrl();

@@ -38,12 +38,15 @@ namespace mhd {
 // Accelerated iteration (Sec. 5.8): with rest weight w_0 - 1 + alpha and the sum divided by
 // alpha, the update is b + (b* - b) / alpha, i.e. the increment above times omega = 1 / alpha.
 //
+// BYZ: B_ext also has a (y, z) part (six magnets): a 3 x (ny nz) table, requested with each
+// plane's loads and added while staging.
+//
 // SPLIT: b is held as two float16 arrays, b = (hi + lo) b_scale. hi is fixed within a fluid
 // step; the sweep stages hi + lo and writes lo* = lo + increment, so the 16-bit rounding is
 // relative to lo, not to b. The first sweep of a step (a.bho set) re-splits v = hi + lo +
 // increment into a new hi = fp16(v) and lo = fp16(v - hi).
 // -------------------------------------------------------------------------------------------
-template <int TX, int TY, typename TU, typename TB, bool BATCH, bool SPLIT>
+template <int TX, int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ>
 __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeStep *tab, const BlockMap *map,
                                                       int which, int nbatch) {
     constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
@@ -87,6 +90,7 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
 
     // halo slots handled by this thread: fixed (x, y) for the whole march
     unsigned sxy[NSLOT];
+    int sy[NSLOT];
     float sbe[NSLOT][3];
     bool sval[NSLOT];
 #pragma unroll
@@ -96,6 +100,7 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
         const int hx = i % HX, hy = i / HX;
         const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
         sxy[s] = (unsigned)(hxg + nx * hyg);
+        sy[s] = hyg;
         sbe[s][0] = sval[s] ? a.bext[hxg] * a.inv_b_scale : 0.f;
         sbe[s][1] = sval[s] ? a.bext[nx + hxg] * a.inv_b_scale : 0.f;
         sbe[s][2] = sval[s] ? a.bext[2 * nx + hxg] * a.inv_b_scale : 0.f;
@@ -106,8 +111,19 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
     TU ru[NSLOT][3];
     TB rb[NSLOT][3];
     TB rh[NSLOT][3];
+    float rt[NSLOT][3];  // BYZ: B_ext (y, z) part of the next plane
+    const unsigned pyz = (unsigned)ny * nz;
     auto load_plane = [&](int p) {
         const unsigned off = (unsigned)wrapi(p, nz) * plane;
+        if constexpr (BYZ) {
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                const unsigned o = (unsigned)(sy[s] + ny * wrapi(p, nz));
+                rt[s][0] = sval[s] ? a.bext_yz[o] : 0.f;
+                rt[s][1] = sval[s] ? a.bext_yz[pyz + o] : 0.f;
+                rt[s][2] = sval[s] ? a.bext_yz[2 * pyz + o] : 0.f;
+            }
+        }
 #pragma unroll
         for (int s = 0; s < NSLOT; ++s) {
             if (sval[s]) {
@@ -152,9 +168,15 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
                     by += St<TB>::cvt(rh[s][1]);
                     bz += St<TB>::cvt(rh[s][2]);
                 }
-                const float Bx = bx + sbe[s][0];
-                const float By = by + sbe[s][1];
-                const float Bz = bz + sbe[s][2];
+                float be0 = sbe[s][0], be1 = sbe[s][1], be2 = sbe[s][2];
+                if constexpr (BYZ) {
+                    be0 += rt[s][0] * a.inv_b_scale;
+                    be1 += rt[s][1] * a.inv_b_scale;
+                    be2 += rt[s][2] * a.inv_b_scale;
+                }
+                const float Bx = bx + be0;
+                const float By = by + be1;
+                const float Bz = bz + be2;
                 const float ux = St<TU>::cvt(ru[s][0]);
                 const float uy = St<TU>::cvt(ru[s][1]);
                 const float uz = St<TU>::cvt(ru[s][2]);
@@ -341,7 +363,7 @@ struct Pair<__hip_bfloat16> {
     }
 };
 
-template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT>
+template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ>
 __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
                                                             int which, int nbatch) {
     constexpr int HY = TY + 2;        // staged rows
@@ -392,18 +414,21 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 
     // row loads: round r stages row hy = w + r * TY (if < HY) at columns xa, xa + 1
     unsigned rowoff[NR];
+    int rowy[NR];
     bool rowval[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int hy = w + r * TY;
         rowval[r] = hy < HY;
-        rowoff[r] = (unsigned)(xa + nx * wrapi(y0 - 1 + hy, ny));
+        rowy[r] = wrapi(y0 - 1 + hy, ny);
+        rowoff[r] = (unsigned)(xa + nx * rowy[r]);
     }
     // halo columns: lanes 0 .. 2*HY-1 of the last wave, lane -> (row hy = lane / 2, side)
     const bool hval = (w == TY - 1) && (l < 2 * HY);
     const int hhy = l >> 1, hside = l & 1;
     const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
-    const unsigned hoff = (unsigned)(hx + nx * wrapi(y0 - 1 + min(hhy, HY - 1), ny));
+    const int hyg = wrapi(y0 - 1 + min(hhy, HY - 1), ny);
+    const unsigned hoff = (unsigned)(hx + nx * hyg);
     const int hidx = min(hhy, HY - 1) * RS + (hside ? 129 : 0);
     const float hbe[3] = {a.bext[hx] * ib, a.bext[nx + hx] * ib, a.bext[2 * nx + hx] * ib};
 
@@ -413,8 +438,24 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     TU hu[3];
     TB hb[3];
     TB hq[3];      // SPLIT: hi part of the halo column
+    float rt[NR][3], ht[3];  // BYZ: B_ext (y, z) part of the next plane's rows and halo column
+    const unsigned pyz = (unsigned)ny * nz;
     auto load_plane = [&](int p) {
         const unsigned off = (unsigned)wrapi(p, nz) * plane;
+        if constexpr (BYZ) {
+            const int zz = wrapi(p, nz);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const unsigned o = (unsigned)(rowy[r] + ny * zz);
+                rt[r][0] = a.bext_yz[o];
+                rt[r][1] = a.bext_yz[pyz + o];
+                rt[r][2] = a.bext_yz[2 * pyz + o];
+            }
+            const unsigned o = (unsigned)(hyg + ny * zz);
+            ht[0] = a.bext_yz[o];
+            ht[1] = a.bext_yz[pyz + o];
+            ht[2] = a.bext_yz[2 * pyz + o];
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (rowval[r]) {
@@ -474,10 +515,18 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                         b[1][q] += PB::hi(rq[r][q], bs);
                     }
                 }
+                float ea[3] = {bea[0], bea[1], bea[2]}, eb[3] = {beb[0], beb[1], beb[2]};
+                if constexpr (BYZ) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        ea[q] += rt[r][q] * ib;
+                        eb[q] += rt[r][q] * ib;
+                    }
+                }
                 put(S, idx, b[0][0], b[0][1], b[0][2], PU::lo(ru[r][0], us), PU::lo(ru[r][1], us),
-                    PU::lo(ru[r][2], us), bea);
+                    PU::lo(ru[r][2], us), ea);
                 put(S, idx + 1, b[1][0], b[1][1], b[1][2], PU::hi(ru[r][0], us), PU::hi(ru[r][1], us),
-                    PU::hi(ru[r][2], us), beb);
+                    PU::hi(ru[r][2], us), eb);
             }
         }
         if (hval) {
@@ -487,7 +536,12 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                 b[q] = St<TB>::cvt(hb[q]);
                 if constexpr (SPLIT) b[q] += St<TB>::cvt(hq[q]);
             }
-            put(S, hidx, b[0], b[1], b[2], St<TU>::cvt(hu[0]), St<TU>::cvt(hu[1]), St<TU>::cvt(hu[2]), hbe);
+            float eh[3] = {hbe[0], hbe[1], hbe[2]};
+            if constexpr (BYZ) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) eh[q] += ht[q] * ib;
+            }
+            put(S, hidx, b[0], b[1], b[2], St<TU>::cvt(hu[0]), St<TU>::cvt(hu[1]), St<TU>::cvt(hu[2]), eh);
         }
     };
     using I0 = std::integral_constant<int, 0>;
@@ -669,6 +723,7 @@ SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *b
     a.bh = nullptr;
     a.bho = nullptr;
     a.bext = bext;
+    a.bext_yz = nullptr;
     a.nx = c.nx;
     a.ny = c.ny;
     a.nz = c.nz;
@@ -693,34 +748,34 @@ static inline unsigned sweep_grid(int nblocks) { return (unsigned)(((nblocks + 7
 
 // Sweeps are launched through hipExtLaunchKernelGGL: when profiling, its start / stop events
 // are stamped when the kernel itself starts and ends (no event packets around the launch).
-template <typename TU, typename TB, bool BATCH, bool SPLIT>
+template <typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ>
 static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
                               const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(sweep_grid(nblocks));
     if (L.pair) {
         if (L.ty >= 8)
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
         else
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
         return hipGetLastError();
     }
     switch (L.tx) {
         case 64:
-            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
         case 32:
-            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
         case 16:
-            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
         default:
-            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH, SPLIT>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
     }
@@ -728,26 +783,34 @@ static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, 
 }
 
 
+template <bool BATCH, bool BYZ>
+static hipError_t sweep_kinds_yz(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
+                                 const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
+    const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
+    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
+        return sweep_typed<float, float, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+    if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
+        return sweep_typed<__half, __half, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
+        return sweep_typed<__hip_bfloat16, __half, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
+        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0,
+                                                                              e1);
+    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)  // reads the float16 copy of u
+        return sweep_typed<__half, __half, BATCH, true, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+    return hipErrorInvalidValue;
+}
 template <bool BATCH>
 static hipError_t sweep_kinds(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
                               const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
-    const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
-    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
-        return sweep_typed<float, float, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
-    if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
-        return sweep_typed<__half, __half, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
-    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
-        return sweep_typed<__hip_bfloat16, __half, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
-    if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
-        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH, false>(s, a, L, tab, map, which, nblocks, e0, e1);
-    if (ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)  // reads the float16 copy of u
-        return sweep_typed<__half, __half, BATCH, true>(s, a, L, tab, map, which, nblocks, e0, e1);
-    return hipErrorInvalidValue;
+    if (L.byz) return sweep_kinds_yz<BATCH, true>(s, kinds, a, L, tab, map, which, nblocks, e0, e1);
+    return sweep_kinds_yz<BATCH, false>(s, kinds, a, L, tab, map, which, nblocks, e0, e1);
 }
 
 hipError_t launch_mag_sweep(hipStream_t s, int kinds, const SweepArgs &a0, SweepLaunch L, hipEvent_t e0,
                             hipEvent_t e1) {
     L.pair = L.pair && a0.nx % 128 == 0;
+    L.byz = a0.bext_yz != nullptr;
     return sweep_kinds<false>(s, kinds, a0, L, nullptr, nullptr, 0, a0.nblocks, e0, e1);
 }
 

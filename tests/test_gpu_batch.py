@@ -15,8 +15,8 @@ pytestmark = pytest.mark.gpu
 
 
 def batch_spec():
-    """Five boxes: odd / even sweep counts, the paired sweep form (nx = 128, 256), a box without
-    wall, flow-rate control, an oscillating force, uniform and fringe fields."""
+    """Six boxes: odd / even sweep counts, the paired sweep form (nx = 128, 256), a box without
+    wall, flow-rate control, an oscillating force, uniform, fringe and six-magnet fields."""
     a = random_box(8, 32, 32, key=300, n_mag=7, R=12.0)
     b = random_box(32, 32, 32, key=301, n_mag=4, R=13.0, bext_kind=W.BEXT_UNIFORM_Y)
     c = random_box(128, 20, 20, key=302, n_mag=5, R=7.0)
@@ -26,7 +26,9 @@ def batch_spec():
     e = random_box(256, 12, 10, key=304, n_mag=1, R=3.5, bext_kind=W.BEXT_UNIFORM_Y)
     e.params.G1 = 1e-5
     e.params.period = 7.0
-    return [(a, True), (b, True), (c, True), (d, False), (e, True)]
+    f = W.pipe_workload("six_magnets", 305, 16, 33, 33, 14.0, 50.0, 10.0, 1e-2,
+                        bext_kind=W.BEXT_SIX_MAGNETS, n_mag=6, b_amp=1e-3)
+    return [(a, True), (b, True), (c, True), (d, False), (e, True), (f, True)]
 
 
 def setup(sim, w, markers):

@@ -180,6 +180,16 @@ def test_qs_to_canonical_transition_budget_series():
     assert ratios[2.0] >= 0.05 and ratios[45.0] <= 0.01
 
 
+@pytest.mark.parametrize("nx,steps,n_mag", [(8, 1, 4), (128, 1, 4), (8, 10, 20)])
+def test_six_magnet_field(nx, steps, n_mag):
+    """Sec. 6 six-magnet field ((y, z) table in the kernels) against the oracle's literal
+    evaluation; nx = 128 takes the paired sweep."""
+    print("case six magnets", nx, steps, flush=True)
+    w = W.pipe_workload("six_magnets", 7, nx, 33, 33, 14.0, 50.0, 10.0, 1e-2,
+                        bext_kind=W.BEXT_SIX_MAGNETS, n_mag=n_mag, b_amp=1e-4)
+    compare(gpu_run(w, steps), oracle_run(w, steps), label=f"six magnets {nx} {steps} steps")
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)

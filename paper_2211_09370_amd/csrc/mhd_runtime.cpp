@@ -19,6 +19,12 @@
 
 using namespace mhd;
 
+// The Python binding mirrors these structs field by field (tests check the same sizes).
+static_assert(sizeof(mhd_grid_desc) == 40, "mhd_grid_desc layout");
+static_assert(sizeof(mhd_params) == 160, "mhd_params layout");
+static_assert(sizeof(mhd_budget) == 136, "mhd_budget layout");
+static_assert(sizeof(mhd_pipe_desc) == 48, "mhd_pipe_desc layout");
+
 namespace {
 
 thread_local std::string g_err;

@@ -40,7 +40,8 @@ class OrcParams(C.Structure):
                 ("fringe_w", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
                 ("radius", C.c_double), ("flow_control", C.c_int), ("u_target", C.c_double),
                 ("k_c", C.c_double), ("ib_u", C.c_int), ("ib_b", C.c_int),
-                ("alpha", C.c_double), ("magnet_L", C.c_double), ("magnet_D", C.c_double)]
+                ("alpha", C.c_double), ("magnet_L", C.c_double), ("magnet_D", C.c_double),
+                ("lattice", C.c_int)]
 
 
 _D = C.POINTER(C.c_double)
@@ -93,7 +94,8 @@ def make_params(nx, ny, nz, prm=None, *, ib_u=1, ib_b=1, **over) -> OrcParams:
     """Build OrcParams from a workloads.Params-like object (attribute names match) + overrides."""
     fields = dict(nu=0.1, eta=1.0, n_mag=1, lambda_u=1.0, lambda_b=0.0, G0=0.0, G1=0.0, period=0.0,
                   bext_kind=0, B0=0.0, fringe_x0=0.0, fringe_w=1.0, yc=0.0, zc=0.0, radius=0.0,
-                  flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0, magnet_L=0.0, magnet_D=0.0)
+                  flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0, magnet_L=0.0, magnet_D=0.0,
+                  lattice=19)
     if prm is not None:
         for k in list(fields):
             src = {"radius": "avg_radius", "u_target": "u_bulk_target"}.get(k, k)
@@ -101,7 +103,7 @@ def make_params(nx, ny, nz, prm=None, *, ib_u=1, ib_b=1, **over) -> OrcParams:
                 fields[k] = getattr(prm, src)
     fields.update(over)
     return OrcParams(nx=nx, ny=ny, nz=nz, ib_u=ib_u, ib_b=ib_b,
-                     **{k: (int(v) if k in ("n_mag", "bext_kind", "flow_control") else float(v))
+                     **{k: (int(v) if k in ("n_mag", "bext_kind", "flow_control", "lattice") else float(v))
                         for k, v in fields.items()})
 
 

@@ -11,7 +11,8 @@
  * the cell it belongs to and gathered from the neighbour named by the update formula; no moment
  * shortcuts, no fusion. Arithmetic is IEEE double; build with -ffp-contract=off.
  *
- * Lattice: D3Q19 (rest 1/3, six faces 1/18, twelve edges 1/36, c_s^2 = 1/3), box nx*ny*nz
+ * Lattice: D3Q19 (rest 1/3, six faces 1/18, twelve edges 1/36, c_s^2 = 1/3) or the paper's D3Q27
+ * (rest 8/27, faces 2/27, edges 1/54, corners 1/216) for every part of the step, box nx*ny*nz
  * periodic on every face, fields component-major with x fastest.
  *
  * Step n -> n+1 (Sec. 5.7: the magnetic iteration runs before each velocity update):
@@ -61,21 +62,57 @@ typedef struct {
     double alpha;   /* accelerated magnetic iteration (Sec. 5.8); <= 0 means 1 (plain sweep) */
     double magnet_L, magnet_D; /* six magnets: strip half-width (<= 0: radius / 6) and distance
                                   of the strip centres from the axis (<= 0: see magnet_geometry) */
+    int lattice;    /* 27: D3Q27 (the paper's set, Table I); otherwise D3Q19 */
 } orc_params;
 
-/* D3Q19 velocity set and weights (textbook values; the paper's own table is D3Q27). */
-static const int E[19][3] = {
+/* D3Q19 velocity set and weights (textbook values). */
+static const int E19[19][3] = {
     {0, 0, 0},
     {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
     {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
     {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
     {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-static const double W[19] = {
+static const double W19[19] = {
     1.0 / 3.0,
     1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* D3Q27 (the paper's set): the tensor product of the 1D weights (2/3, 1/6, 1/6) -> rest 8/27,
+ * six faces 2/27, twelve edges 1/54, eight corners 1/216. */
+static const int E27[27][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+static const double W27[27] = {
+    8.0 / 27.0,
+    2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+    1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+    1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+    1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0};
 static const double CS2 = 1.0 / 3.0;
+
+/* The velocity set in use: Q velocities E[i], weights W[i] (rest first). */
+typedef struct {
+    int Q;
+    const int (*E)[3];
+    const double *W;
+} lattice_t;
+static inline lattice_t lattice_of(const orc_params *p) {
+    lattice_t l;
+    if (p->lattice == 27) {
+        l.Q = 27;
+        l.E = E27;
+        l.W = W27;
+    } else {
+        l.Q = 19;
+        l.E = E19;
+        l.W = W19;
+    }
+    return l;
+}
 
 static inline int wrap(int i, int n) {
     i %= n;
@@ -155,37 +192,39 @@ void orc_bext(const orc_params *p, int x, int y, int z, double B[3]) {
 /* ------------------------------------------------------------------------------------------ */
 
 /* Fluid equilibrium f_i^eq(rho, u) with c_s^2 = 1/3 (Sec. 3.1 / Sec. 3.5). */
-static inline double feq(int i, double rho, const double u[3]) {
-    double cu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+static inline double feq(const lattice_t *L, int i, double rho, const double u[3]) {
+    const int *e = L->E[i];
+    double cu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    return W[i] * rho * (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    return L->W[i] * rho * (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
 }
 
 /* GZS forcing population F_i (Sec. 5.1): (1 - 1/(2 tau)) w_i [(c_i - u)/c_s^2
  * + (c_i . u) c_i / c_s^4] . F */
-static inline double fgzs(int i, double tau, const double u[3], const double F[3]) {
-    double cu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+static inline double fgzs(const lattice_t *L, int i, double tau, const double u[3], const double F[3]) {
+    const int *e = L->E[i];
+    double cu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
     double s = 0.0;
     for (int a = 0; a < 3; ++a) {
-        double v = (E[i][a] - u[a]) / CS2 + cu * E[i][a] / (CS2 * CS2);
+        double v = (e[a] - u[a]) / CS2 + cu * e[a] / (CS2 * CS2);
         s += v * F[a];
     }
-    return (1.0 - 1.0 / (2.0 * tau)) * W[i] * s;
+    return (1.0 - 1.0 / (2.0 * tau)) * L->W[i] * s;
 }
 
 /* Magnetic equilibrium of the tau_m = 1 iteration with particle speed c = 6 eta (Sec. 5.7):
  * g_{i,a} = w_i [ b_a + sum_c (c_ic / cs_m^2) (u_c B_a - u_a B_c) ], c_i = c e_i, cs_m^2 = c^2/3.
  * `b` is the induced field, B = B_ext + b enters the flux. */
-static inline void geq(int i, double c, const double u[3], const double b[3], const double B[3],
-                       double g[3]) {
+static inline void geq(const lattice_t *L, int i, double c, const double u[3], const double b[3],
+                       const double B[3], double g[3]) {
     double csm2 = c * c / 3.0;
     for (int a = 0; a < 3; ++a) {
         double s = b[a];
         for (int cc = 0; cc < 3; ++cc) {
-            double cic = c * E[i][cc];
+            double cic = c * L->E[i][cc];
             s += (cic / csm2) * (u[cc] * B[a] - u[a] * B[cc]);
         }
-        g[a] = W[i] * s;
+        g[a] = L->W[i] * s;
     }
 }
 
@@ -204,20 +243,21 @@ void orc_mag_sweep(const orc_params *p, const double *u, const double *b, double
     /* Sec. 5.8, eq. "magnetic field quasi-static acelerated": the rest population becomes
      * (w_0 - 1 + alpha) b and the gathered sum is divided by alpha (alpha = 1: Sec. 5.7). */
     const double alpha = p->alpha > 0.0 ? p->alpha : 1.0;
+    const lattice_t L = lattice_of(p);
 #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 double acc[3] = {0.0, 0.0, 0.0};
-                for (int i = 0; i < 19; ++i) {
-                    int sx = x - E[i][0], sy = y - E[i][1], sz = z - E[i][2];
+                for (int i = 0; i < L.Q; ++i) {
+                    int sx = x - L.E[i][0], sy = y - L.E[i][1], sz = z - L.E[i][2];
                     int64_t k = cell(p, sx, sy, sz);
                     double us[3], bs[3], Bs[3], Be[3], g[3];
                     load3(u, N, k, us);
                     load3(b, N, k, bs);
                     orc_bext(p, wrap(sx, p->nx), wrap(sy, p->ny), wrap(sz, p->nz), Be);
                     for (int a = 0; a < 3; ++a) Bs[a] = Be[a] + bs[a];
-                    geq(i, c, us, bs, Bs, g);
+                    geq(&L, i, c, us, bs, Bs, g);
                     if (i == 0)
                         for (int a = 0; a < 3; ++a) g[a] += (alpha - 1.0) * bs[a];
                     for (int a = 0; a < 3; ++a) acc[a] += g[a];
@@ -342,18 +382,20 @@ void orc_ib_correct(const orc_params *p, int64_t M, const double *X, const doubl
 
 /* d_a phi(x) = (1/c_s^2) sum_i w_i e_ia phi(x + e_i) */
 static inline void grad_iso(const orc_params *p, const double *f, int x, int y, int z, double g[3]) {
+    const lattice_t L = lattice_of(p);
     g[0] = g[1] = g[2] = 0.0;
-    for (int i = 1; i < 19; ++i) {
-        double v = f[cell(p, x + E[i][0], y + E[i][1], z + E[i][2])];
-        for (int a = 0; a < 3; ++a) g[a] += W[i] * E[i][a] * v;
+    for (int i = 1; i < L.Q; ++i) {
+        double v = f[cell(p, x + L.E[i][0], y + L.E[i][1], z + L.E[i][2])];
+        for (int a = 0; a < 3; ++a) g[a] += L.W[i] * L.E[i][a] * v;
     }
     for (int a = 0; a < 3; ++a) g[a] /= CS2;
 }
 
 /* lap phi(x) = (2/c_s^2) sum_i w_i (phi(x + e_i) - phi(x)) */
 static inline double lap_iso(const orc_params *p, const double *f, int x, int y, int z) {
+    const lattice_t L = lattice_of(p);
     double c0 = f[cell(p, x, y, z)], s = 0.0;
-    for (int i = 1; i < 19; ++i) s += W[i] * (f[cell(p, x + E[i][0], y + E[i][1], z + E[i][2])] - c0);
+    for (int i = 1; i < L.Q; ++i) s += L.W[i] * (f[cell(p, x + L.E[i][0], y + L.E[i][1], z + L.E[i][2])] - c0);
     return 2.0 * s / CS2;
 }
 
@@ -393,6 +435,7 @@ void orc_fluid(const orc_params *p, const double *rho, const double *u, const do
                double *rho_out, double *u_out) {
     const int64_t N = ncells(p);
     const double tau = p->nu / CS2 + 0.5; /* nu = c_s^2 (tau - 1/2) */
+    const lattice_t L = lattice_of(p);
 #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
@@ -402,23 +445,23 @@ void orc_fluid(const orc_params *p, const double *rho, const double *u, const do
                 load3(u, N, k0, u0);
                 load3(F, N, k0, F0);
                 double rsum = 0.0, m[3] = {0.0, 0.0, 0.0}, fsum[3] = {0.0, 0.0, 0.0};
-                for (int i = 0; i < 19; ++i) {
-                    int64_t km = cell(p, x - E[i][0], y - E[i][1], z - E[i][2]);
-                    int64_t kp = cell(p, x + E[i][0], y + E[i][1], z + E[i][2]);
+                for (int i = 0; i < L.Q; ++i) {
+                    int64_t km = cell(p, x - L.E[i][0], y - L.E[i][1], z - L.E[i][2]);
+                    int64_t kp = cell(p, x + L.E[i][0], y + L.E[i][1], z + L.E[i][2]);
                     double um[3], up[3], Fm[3], Fp[3];
                     load3(u, N, km, um);
                     load3(u, N, kp, up);
                     load3(F, N, km, Fm);
                     load3(F, N, kp, Fp);
-                    double f_m = feq(i, rho[km], um); /* f_i^eq(x - e_i) */
-                    double f_0 = feq(i, rho[k0], u0); /* f_i^eq(x) */
-                    double f_p = feq(i, rho[kp], up); /* f_i^eq(x + e_i) */
+                    double f_m = feq(&L, i, rho[km], um); /* f_i^eq(x - e_i) */
+                    double f_0 = feq(&L, i, rho[k0], u0); /* f_i^eq(x) */
+                    double f_p = feq(&L, i, rho[kp], up); /* f_i^eq(x + e_i) */
                     rsum += 1.5 * f_m - f_0 + 0.5 * f_p;
-                    double Fi_p = fgzs(i, tau, up, Fp);
-                    double Fi_m = fgzs(i, tau, um, Fm);
+                    double Fi_p = fgzs(&L, i, tau, up, Fp);
+                    double Fi_m = fgzs(&L, i, tau, um, Fm);
                     for (int a = 0; a < 3; ++a) {
-                        m[a] += E[i][a] * (f_m + (tau - 1.0) * (f_p - 2.0 * f_0 + f_m));
-                        fsum[a] += E[i][a] * (Fi_p - Fi_m);
+                        m[a] += L.E[i][a] * (f_m + (tau - 1.0) * (f_p - 2.0 * f_0 + f_m));
+                        fsum[a] += L.E[i][a] * (Fi_p - Fi_m);
                     }
                 }
                 rho_out[k0] = rsum;

@@ -137,12 +137,13 @@ def test_magnetic_sweep_symbol_is_the_lattice_average():
         assert symbol >= 1 / 9 - 1e-15
 
 
-def test_magnetic_fixed_point_solves_qs_poisson_equation():
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_magnetic_fixed_point_solves_qs_poisson_equation(lattice):
     # The iteration's steady state satisfies eta lap b = div(u B - B u), B = B_ext + b
-    # (asymptotic limit stated in Sec. 5.7), with the isotropic operators.
+    # (asymptotic limit stated in Sec. 5.7), with the isotropic operators of the lattice.
     n = 8
     eta = 2.0
-    p = oracle.make_params(n, n, n, eta=eta, bext_kind=W.BEXT_UNIFORM_Y, B0=1.0)
+    p = oracle.make_params(n, n, n, eta=eta, bext_kind=W.BEXT_UNIFORM_Y, B0=1.0, lattice=lattice)
     x = 2 * np.pi * np.arange(n) / n
     Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
     u = 0.05 * np.stack([np.sin(Y) * np.cos(Z), np.cos(X + 2 * Z), np.sin(X - Y)])
@@ -151,8 +152,8 @@ def test_magnetic_fixed_point_solves_qs_poisson_equation():
         b = oracle.mag_sweep(p, u, b)
     B = b.copy()
     B[1] += 1.0
-    res = eta * np.stack([fdops.lap(b[a]) for a in range(3)]) - fdops.div_flux(u, B)
-    scale = np.abs(fdops.div_flux(u, B)).max()
+    res = eta * np.stack([fdops.lap(b[a], lattice) for a in range(3)]) - fdops.div_flux(u, B, lattice)
+    scale = np.abs(fdops.div_flux(u, B, lattice)).max()
     assert np.abs(res).max() <= 1e-10 * scale
 
 
@@ -177,6 +178,29 @@ def test_magnetic_sweep_conserves_the_mean_field():
 def _symbol(k):
     cx, cy, cz = np.cos(k)
     return 1 / 3 + (cx + cy + cz) / 9 + (cx * cy + cx * cz + cy * cz) / 9
+
+
+def test_d3q27_sweep_symbol_is_the_tensor_product_average():
+    # D3Q27 weights are the product of the 1D weights (2/3, 1/6, 1/6), so for u = 0 one sweep
+    # multiplies a mode by prod_a (2/3 + cos(k_a)/3), whose minimum 1/27 at k = (pi, pi, pi)
+    # puts the accelerated iteration's stability edge at alpha = 13/27 (the paper reports
+    # instability below about 1/2 for its D3Q27 scheme).
+    n = 8
+    x = np.arange(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = np.zeros((3, n, n, n))
+    for alpha in (1.0, 13 / 27):
+        p = oracle.make_params(n, n, n, eta=3.0, lattice=27, alpha=alpha)
+        for (kx, ky, kz) in [(1, 0, 0), (2, 3, 0), (4, 4, 0), (1, 2, 3), (4, 4, 4), (0, 4, 4)]:
+            k = 2 * np.pi * np.array([kx, ky, kz]) / n
+            mode = np.cos(k[0] * X + k[1] * Y + k[2] * Z)
+            b = np.stack([mode, 0.5 * mode, -mode])
+            sigma = float(np.prod(2 / 3 + np.cos(k) / 3))
+            out = oracle.mag_sweep(p, u, b)
+            np.testing.assert_allclose(out, (1 + (sigma - 1) / alpha) * b, atol=1e-13)
+            assert sigma >= 1 / 27 - 1e-15
+            if (kx, ky, kz) == (4, 4, 4) and alpha < 1:
+                assert abs(1 + (sigma - 1) / alpha + 1) < 1e-12
 
 
 @pytest.mark.parametrize("alpha", [0.5, 4 / 9, 0.75, 1.7])
@@ -283,19 +307,21 @@ def _random_state(n, key, F_mean=1e-4):
     return rho, u, F
 
 
-def test_density_update_conserves_mass_exactly():
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_density_update_conserves_mass_exactly(lattice):
     rho, u, F = _random_state(7, 103)
-    p = oracle.make_params(7, 7, 7, nu=0.05)
+    p = oracle.make_params(7, 7, 7, nu=0.05, lattice=lattice)
     r2, _ = oracle.fluid(p, rho, u, F)
     assert abs(r2.sum() - rho.sum()) <= 1e-13 * rho.sum()
 
 
-def test_momentum_update_adds_exactly_the_body_force():
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_momentum_update_adds_exactly_the_body_force(lattice):
     # Without walls every gathered term telescopes on the periodic grid:
     # sum rho' u* - sum rho u = sum F.
     rho, u, F = _random_state(7, 104)
     for nu in (0.01, 0.1, 0.15):
-        p = oracle.make_params(7, 7, 7, nu=nu)
+        p = oracle.make_params(7, 7, 7, nu=nu, lattice=lattice)
         r2, u2 = oracle.fluid(p, rho, u, F)
         lhs = (r2 * u2).sum(axis=(1, 2, 3)) - (rho * u).sum(axis=(1, 2, 3))
         np.testing.assert_allclose(lhs, F.sum(axis=(1, 2, 3)), rtol=1e-12)
@@ -345,12 +371,13 @@ def _plane_channel(ny, yc, a, **kw):
     return p, X
 
 
-def test_plane_poiseuille_is_exact():
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_plane_poiseuille_is_exact(lattice):
     # Walls on lattice nodes (D = delta, d = 1): the steady discrete state is the parabola
     # G (a^2 - y^2) / (2 nu), exactly.
     oracle.set_threads(1)
     ny, yc, a, nu, G = 24, 12, 8, 0.1, 1e-5
-    p, X = _plane_channel(ny, yc, a, nu=nu, eta=1.0, n_mag=1, G0=G)
+    p, X = _plane_channel(ny, yc, a, nu=nu, eta=1.0, n_mag=1, G0=G, lattice=lattice)
     y = np.arange(ny) - yc
     u0 = np.zeros((3, 1, ny, 1))
     u0[0, 0, :, 0] = gold.plane_poiseuille_u(y, a, nu, G) * 0.9

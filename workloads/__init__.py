@@ -54,6 +54,7 @@ class Params:
     alpha: float = 1.0  # accelerated magnetic iteration (1: plain sweep)
     magnet_L: float = 0.0  # six magnets: strip half-width (<= 0: R / 6)
     magnet_D: float = 0.0  # six magnets: distance of the strips from the axis (<= 0: outside the box)
+    lattice: int = 19  # 19 or 27 (the paper's D3Q27)
 
 
 @dataclasses.dataclass

@@ -88,15 +88,18 @@ typedef struct {
     double yc, zc;        /* pipe axis position in the cross-section (cells)               */
     double avg_radius;    /* pipe radius R used by the budgets (r < R - 2) and flow rate   */
     int32_t flow_control; /* 1: integral control of G towards u_bulk_target               */
-    int32_t reserved0;
+    int32_t lattice;      /* velocity set of both iterations: 0 or 19 -> D3Q19; 27 -> D3Q27, the
+                             paper's own set (Table I; weights 8/27, 2/27, 1/54, 1/216), with
+                             float32 or split storage only (UNSUPPORTED otherwise)            */
     double u_bulk_target; /* target bulk velocity over r <= R                               */
     double k_c;           /* control gain: G += k_c (8 nu / R^2) (target - U_b) per step    */
     double alpha;         /* accelerated magnetic iteration (Sec. 5.8, eq. "magnetic field
                              quasi-static acelerated"): rest population (w_0 - 1 + alpha) b,
                              gathered sum divided by alpha, i.e. b' = b + (S(b) - b) / alpha
                              with S the plain sweep; same fixed point, slow modes converge
-                             1/alpha times faster. 0 or 1: plain sweep. Must be >= 4/9 (the
-                             D3Q19 averaging symbol is >= 1/9, so smaller alpha diverges). */
+                             1/alpha times faster. 0 or 1: plain sweep. Must be >= 4/9 on
+                             D3Q19, >= 13/27 on D3Q27 (the averaging symbol's minimum is 1/9,
+                             resp. 1/27; smaller alpha diverges).                          */
     double magnet_half_width; /* six magnets: L; <= 0 -> avg_radius / 6 (Sec. 6)            */
     double magnet_distance;   /* six magnets: distance of the strip centres from the axis;
                                  <= 0 -> distance of the farthest cell of the box from the axis

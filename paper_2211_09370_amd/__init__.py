@@ -223,7 +223,7 @@ def make_params(src=None, **over) -> mhd_params:
     p.k_c = 0.1
     p.n_mag = 1
     p.alpha = 1.0
-    names = [f for f, _ in mhd_params._fields_ if f != "reserved0"]
+    names = [f for f, _ in mhd_params._fields_]
     vals = {}
     if src is not None:
         alias = {"magnet_half_width": "magnet_L", "magnet_distance": "magnet_D"}
@@ -240,7 +240,7 @@ def make_params(src=None, **over) -> mhd_params:
                 vals[f] = getattr(src, g)
     vals.update(over)
     for f, v in vals.items():
-        setattr(p, f, int(v) if f in ("n_mag", "bext_kind", "flow_control") else float(v))
+        setattr(p, f, int(v) if f in ("n_mag", "bext_kind", "flow_control", "lattice") else float(v))
     return p
 
 

@@ -53,7 +53,7 @@ class mhd_params(C.Structure):
                 ("G0", C.c_double), ("G1", C.c_double), ("period", C.c_double),
                 ("B0", C.c_double), ("fringe_x0", C.c_double), ("fringe_w", C.c_double),
                 ("yc", C.c_double), ("zc", C.c_double), ("avg_radius", C.c_double),
-                ("flow_control", C.c_int32), ("reserved0", C.c_int32),
+                ("flow_control", C.c_int32), ("lattice", C.c_int32),
                 ("u_bulk_target", C.c_double), ("k_c", C.c_double), ("alpha", C.c_double),
                 ("magnet_half_width", C.c_double), ("magnet_distance", C.c_double)]
 

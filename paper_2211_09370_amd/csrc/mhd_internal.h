@@ -29,6 +29,7 @@ struct StepConst {
     float u_scale, inv_u_scale, b_scale, inv_b_scale;
     float copy_scale, inv_copy_scale;  // split form: scale of the float16 copy of u
     float omega;                       // 1 / alpha of the accelerated magnetic iteration
+    int lattice;                       // 19 or 27
     double nu, eta;
     double G0, G1, period;
     double yc, zc, radius;
@@ -47,6 +48,7 @@ struct SweepLaunch {
     int tx, ty, zchunk;  // tile shape and z extent of one workgroup
     int pair;            // 1: two x cells per lane (n_x a multiple of 128); ty = rows per tile
     int byz = 0;         // 1: add the (y, z) table of B_ext (six magnets) while staging
+    int q27 = 0;         // 1: D3Q27 weights
 };
 
 // Arguments of one magnetic sweep launch over one box.
@@ -62,6 +64,7 @@ struct SweepArgs {
     int tiles_x, tiles_y, nzc, zchunk, nblocks;
     float kappa, u_scale, b_scale, inv_b_scale;
     float omega;        // b' = b + omega (S(b) - b); 1 for the plain sweep
+    int q27;            // 1: D3Q27 lattice
 };
 // Sweep arguments of a box for tile choice L (tile counts and workgroup count filled in).
 SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *bext, StepConst c, SweepLaunch L);
@@ -139,8 +142,11 @@ hipError_t launch_ib_interp_batch(hipStream_t s, int kind, const PipeStep *tab, 
                                   int nblocks);
 hipError_t launch_ib_spread_batch(hipStream_t s, int kind, const PipeStep *tab, const BlockMap *map, int which,
                                   int nblocks);
-hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks);
-hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks);
+// q27: the lattice of every box of the batch (a batch holds one lattice)
+hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks,
+                                bool q27);
+hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks,
+                              bool q27);
 hipError_t launch_flow_partial_batch(hipStream_t s, int kind_u, const PipeStep *tab, int n);
 // Workgroups per box of the cell-wise kernels and of the wall-correction launches.
 constexpr int kCellThreads = 256;

@@ -24,10 +24,23 @@
 
 namespace mhd {
 
-// D3Q19 neighbour offsets without the rest direction: 6 faces (w = 1/18), 12 edges (w = 1/36).
-__constant__ int c_dir[18][3] = {{1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+// Neighbour offsets without the rest direction: 6 faces, 12 edges (the D3Q19 set), then the 8
+// corners of D3Q27. Weights: D3Q19 faces 1/18, edges 1/36; D3Q27 faces 2/27, edges 1/54,
+// corners 1/216.
+__constant__ int c_dir[26][3] = {{1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
                                  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
-                                 {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+                                 {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+                                 {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+                                 {-1, 1, 1}, {1, -1, -1}};
+// weight of neighbour i of c_dir on either lattice
+__device__ __forceinline__ float dir_weight(int i, bool q27) {
+    if (q27) return i < 6 ? 2.0f / 27.0f : i < 18 ? 1.0f / 54.0f : 1.0f / 216.0f;
+    return i < 6 ? WF : WE;
+}
+__device__ __forceinline__ double dir_weight_d(int i, bool q27) {
+    if (q27) return i < 6 ? 2.0 / 27.0 : i < 18 ? 1.0 / 54.0 : 1.0 / 216.0;
+    return i < 6 ? 1.0 / 18.0 : 1.0 / 36.0;
+}
 
 // -------------------------------------------------------------------------------------------
 // Control kernels
@@ -199,7 +212,7 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_spread(T *phi, float scale, f
 // Lorentz + body force (Sec. 5.1): J = curl_h b with d_a f = 3 sum_i w_i e_ia f(x + e_i),
 // F = G x + J x (B_ext + b).
 // -------------------------------------------------------------------------------------------
-template <typename TB, bool BATCH, bool SPLIT>
+template <typename TB, bool BATCH, bool SPLIT, bool Q27>
 __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB *bh, float bs, const float *bext,
                                                           const float *bext_yz, const DevCtrl *ctrl, float *F,
                                                           StepConst c, const PipeStep *tab, const BlockMap *map) {
@@ -232,9 +245,9 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
     };
     float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // g[a][c] = d_c b_a
 #pragma unroll
-    for (int i = 0; i < 18; ++i) {
+    for (int i = 0; i < (Q27 ? 26 : 18); ++i) {
         const int ex = c_dir[i][0], ey = c_dir[i][1], ez = c_dir[i][2];
-        const float w = 3.0f * (i < 6 ? WF : WE);
+        const float w = 3.0f * dir_weight(i, Q27);
         const int64_t kn = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
         const float v0 = bv(kn) * bs, v1 = bv(N + kn) * bs, v2 = bv(2 * N + kn) * bs;
         const float e3[3] = {(float)ex, (float)ey, (float)ez};
@@ -281,10 +294,11 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
 // float32 rounding is relative to the change of the step, and the new state is
 // drho' = drho + delta, u* = u + (Dm - delta u) / (1 + drho').
 // -------------------------------------------------------------------------------------------
-__constant__ int c_pair[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0},
-                                 {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+// One direction of each opposite pair: 3 faces, 6 edges (D3Q19), then the 4 corners of D3Q27.
+__constant__ int c_pair[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1},
+                                  {0, 1, 1}, {0, 1, -1}, {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
 
-template <typename TR, typename TU, bool BATCH>
+template <typename TR, typename TU, bool BATCH, bool Q27>
 __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o,
                                                         TU *u_o, __half *u_copy, StepConst c, const PipeStep *tab,
                                                         const BlockMap *map) {
@@ -317,9 +331,9 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
     float dr = 0.f;
     float m0 = 0.f, m1 = 0.f, m2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < (Q27 ? 13 : 9); ++i) {
         const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
-        const float w = i < 3 ? WF : WE;
+        const float w = Q27 ? (i < 3 ? 2.0f / 27.0f : i < 9 ? 1.0f / 54.0f : 1.0f / 216.0f) : (i < 3 ? WF : WE);
         const int64_t kp = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
         const int64_t km = wrapi(x - ex, c.nx) + (int64_t)c.nx * (wrapi(y - ey, c.ny) + (int64_t)c.ny * wrapi(z - ez, c.nz));
         const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
@@ -460,9 +474,10 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
         v[12] += 1.0;
         double grho[3] = {0, 0, 0}, lu[3] = {0, 0, 0}, lb[3] = {0, 0, 0}, divL[3] = {0, 0, 0};
         double gb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        for (int i = 0; i < 18; ++i) {
+        const bool q27 = c.lattice == 27;
+        for (int i = 0; i < (q27 ? 26 : 18); ++i) {
             const int e[3] = {c_dir[i][0], c_dir[i][1], c_dir[i][2]};
-            const double w = i < 6 ? 1.0 / 18.0 : 1.0 / 36.0;
+            const double w = dir_weight_d(i, q27);
             const int xn = wrapi(x + e[0], c.nx);
             const int64_t kn = xn + (int64_t)c.nx * (wrapi(y + e[1], c.ny) + (int64_t)c.ny * wrapi(z + e[2], c.nz));
             const double rn = 1.0 + (double)St<TR>::ld(rho, kn);
@@ -701,8 +716,12 @@ template <typename T, bool SPLIT>
 static hipError_t lorentz_t(hipStream_t s, const void *b, const void *bh, const float *bext, const float *bext_yz,
                             const DevCtrl *ctrl, float *F, StepConst c) {
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    hipLaunchKernelGGL((k_lorentz<T, false, SPLIT>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads), 0, s,
-                       (const T *)b, (const T *)bh, c.b_scale, bext, bext_yz, ctrl, F, c, nullptr, nullptr);
+    if (c.lattice == 27)
+        hipLaunchKernelGGL((k_lorentz<T, false, SPLIT, true>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads),
+                           0, s, (const T *)b, (const T *)bh, c.b_scale, bext, bext_yz, ctrl, F, c, nullptr, nullptr);
+    else
+        hipLaunchKernelGGL((k_lorentz<T, false, SPLIT, false>), dim3(blocks_for(N, kCellThreads)), dim3(kCellThreads),
+                           0, s, (const T *)b, (const T *)bh, c.b_scale, bext, bext_yz, ctrl, F, c, nullptr, nullptr);
     return hipGetLastError();
 }
 hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *b_hi, const float *bext,
@@ -716,18 +735,23 @@ hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *
     }
 }
 template <typename T, bool SPLIT>
-static hipError_t lorentz_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int nblocks) {
+static hipError_t lorentz_batch_t(hipStream_t s, const PipeStep *tab, const BlockMap *map, int nblocks, bool q27) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_lorentz<T, true, SPLIT>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr, nullptr, 0.f,
-                       nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map);
+    if (q27)
+        hipLaunchKernelGGL((k_lorentz<T, true, SPLIT, true>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr, nullptr,
+                           0.f, nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map);
+    else
+        hipLaunchKernelGGL((k_lorentz<T, true, SPLIT, false>), dim3(nblocks), dim3(kCellThreads), 0, s, nullptr,
+                           nullptr, 0.f, nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map);
     return hipGetLastError();
 }
-hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks) {
+hipError_t launch_lorentz_batch(hipStream_t s, int kind_b, const PipeStep *tab, const BlockMap *map, int nblocks,
+                                bool q27) {
     switch (kind_b) {
-        case MHD_KIND_F32: return lorentz_batch_t<float, false>(s, tab, map, nblocks);
-        case MHD_KIND_F16: return lorentz_batch_t<__half, false>(s, tab, map, nblocks);
-        case MHD_KIND_BF16: return lorentz_batch_t<__hip_bfloat16, false>(s, tab, map, nblocks);
-        case MHD_KIND_F16_SPLIT: return lorentz_batch_t<__half, true>(s, tab, map, nblocks);
+        case MHD_KIND_F32: return lorentz_batch_t<float, false>(s, tab, map, nblocks, q27);
+        case MHD_KIND_F16: return lorentz_batch_t<__half, false>(s, tab, map, nblocks, q27);
+        case MHD_KIND_BF16: return lorentz_batch_t<__hip_bfloat16, false>(s, tab, map, nblocks, q27);
+        case MHD_KIND_F16_SPLIT: return lorentz_batch_t<__half, true>(s, tab, map, nblocks, q27);
         default: return hipErrorInvalidValue;
     }
 }
@@ -737,8 +761,12 @@ static hipError_t fluid_t(hipStream_t s, const void *rho, const void *u, const f
                           void *u_copy, StepConst c, const PipeStep *tab, const BlockMap *map, int nblocks) {
     if (!BATCH) nblocks = (int)blocks_for((int64_t)c.nx * c.ny * c.nz, kCellThreads);
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fluid<TR, TU, BATCH>), dim3(nblocks), dim3(kCellThreads), 0, s, (const TR *)rho,
-                       (const TU *)u, F, (TR *)rho_o, (TU *)u_o, (__half *)u_copy, c, tab, map);
+    if (c.lattice == 27)  // batched launches pass the lattice of the whole batch in c
+        hipLaunchKernelGGL((k_fluid<TR, TU, BATCH, true>), dim3(nblocks), dim3(kCellThreads), 0, s, (const TR *)rho,
+                           (const TU *)u, F, (TR *)rho_o, (TU *)u_o, (__half *)u_copy, c, tab, map);
+    else
+        hipLaunchKernelGGL((k_fluid<TR, TU, BATCH, false>), dim3(nblocks), dim3(kCellThreads), 0, s, (const TR *)rho,
+                           (const TU *)u, F, (TR *)rho_o, (TU *)u_o, (__half *)u_copy, c, tab, map);
     return hipGetLastError();
 }
 template <bool BATCH>
@@ -761,9 +789,11 @@ hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u
                         void *u_o, void *u_copy, StepConst c) {
     return fluid_kinds<false>(s, kinds, rho, u, F, rho_o, u_o, u_copy, c, nullptr, nullptr, 0);
 }
-hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks) {
-    return fluid_kinds<true>(s, kinds, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, StepConst{}, tab, map,
-                             nblocks);
+hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks,
+                              bool q27) {
+    StepConst c{};
+    c.lattice = q27 ? 27 : 19;
+    return fluid_kinds<true>(s, kinds, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c, tab, map, nblocks);
 }
 
 template <typename T>

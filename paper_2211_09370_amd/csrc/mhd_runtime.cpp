@@ -200,6 +200,7 @@ StepConst step_const(const mhd_sim *s) {
     c.b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.b_scale;
     c.inv_b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.b_scale);
     c.omega = (float)(1.0 / (p.alpha > 0.0 ? p.alpha : 1.0));
+    c.lattice = p.lattice == 27 ? 27 : 19;
     c.copy_scale = s->split() ? (float)s->g.u_scale : 1.0f;
     c.inv_copy_scale = s->split() ? (float)(1.0 / s->g.u_scale) : 1.0f;
     c.nu = p.nu;
@@ -705,9 +706,14 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
     if (p->bext_kind == MHD_BEXT_TANH_FRINGE_Y && !(p->fringe_w > 0.0))
         return fail(MHD_ERR_INVALID_ARG, "fringe_w must be > 0");
     if (p->flow_control && !(p->avg_radius > 0.0)) return fail(MHD_ERR_INVALID_ARG, "flow control needs avg_radius > 0");
-    if (p->alpha != 0.0 && !(p->alpha >= 4.0 / 9.0))
-        return fail(MHD_ERR_INVALID_ARG, "alpha = %g: the accelerated sweep needs alpha >= 4/9 (or 0 for the plain sweep)",
-                    p->alpha);
+    if (p->lattice != 0 && p->lattice != 19 && p->lattice != 27)
+        return fail(MHD_ERR_INVALID_ARG, "lattice %d: use 19 (D3Q19, also 0) or 27 (D3Q27)", p->lattice);
+    const double alpha_min = p->lattice == 27 ? 13.0 / 27.0 : 4.0 / 9.0;
+    if (p->alpha != 0.0 && !(p->alpha >= alpha_min))
+        return fail(MHD_ERR_INVALID_ARG, "alpha = %g: the accelerated sweep needs alpha >= %g on this lattice (or 0)",
+                    p->alpha, alpha_min);
+    if (p->lattice == 27 && !(s->g.rho_storage == MHD_STORE_F32 && s->g.u_storage == MHD_STORE_F32))
+        return fail(MHD_ERR_UNSUPPORTED, "D3Q27 is built for float32 and split storage only");
     for (double v : {p->nu, p->eta, p->lambda_u, p->lambda_b, p->G0, p->G1, p->period, p->B0, p->fringe_x0, p->fringe_w,
                      p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c, p->alpha, p->magnet_half_width,
                      p->magnet_distance})
@@ -1033,6 +1039,7 @@ struct mhd_batch {
     int64_t interp_base = 0, spread_base = 0, cell_base = 0;
     std::vector<int64_t> cum_interp, cum_spread, cum_cells;  // over `order`
     bool any_flow = false;
+    bool q27 = false;  // lattice of the batch (one for all pipes)
     BatchSlot slot[2];
     int next_slot = 0;
     std::vector<Event2> ev_pool[MHD_K_COUNT];
@@ -1074,11 +1081,16 @@ mhd_status build_plan(mhd_batch *b) {
     std::vector<BlockMap> map;
     // sweep groups, one per tile form
     b->groups.clear();
+    for (auto *s : b->pipes)
+        if ((s->prm.lattice == 27) != (b->pipes[0]->prm.lattice == 27))
+            return fail(MHD_ERR_UNSUPPORTED, "all pipes of a batch must use the same lattice");
+    b->q27 = b->pipes[0]->prm.lattice == 27;
     auto key = [](const SweepLaunch &L) { return (L.pair ? 100 + L.ty : L.tx) + 1000 * L.byz; };
     for (int p : b->order) {
         mhd_sim *s = b->pipes[p];
         SweepLaunch e = effective_tiles(s->sweep, s->g.nx);
         e.byz = s->byz() != nullptr;
+        e.q27 = b->q27;
         BatchGroup *g = nullptr;
         for (auto &x : b->groups)
             if (key(x.L) == key(e)) g = &x;
@@ -1257,9 +1269,9 @@ mhd_status issue_step(mhd_batch *b, int k) {
     }
     const int nc = (int)b->cum_cells[n];
     STEPCHK(timed_b(b, MHD_K_LORENTZ, "lorentz",
-                    [&] { return launch_lorentz_batch(st, b->kind_b, tab, map + b->cell_base, nc); }));
+                    [&] { return launch_lorentz_batch(st, b->kind_b, tab, map + b->cell_base, nc, b->q27); }));
     STEPCHK(timed_b(b, MHD_K_FLUID, "fluid",
-                    [&] { return launch_fluid_batch(st, b->kinds, tab, map + b->cell_base, nc); }));
+                    [&] { return launch_fluid_batch(st, b->kinds, tab, map + b->cell_base, nc, b->q27); }));
     const int64_t ni = b->cum_interp[n], ns = b->cum_spread[n];
     if (ni > 0)
         STEPCHK(timed_b(b, MHD_K_IB, "wall correction", [&] {

@@ -9,6 +9,21 @@
 
 namespace mhd {
 
+// Weights of the plane decomposition: a0f, a0c = in-plane face and corner neighbours of the
+// cell's own plane; a1c, a1f, a1k = centre, face and corner of a neighbouring plane.
+// D3Q19: 1/18, 1/36 | 1/18, 1/36, 0.  D3Q27 (the product of the 1D weights 2/3, 1/6, 1/6):
+// 2/27, 1/54 | 2/27, 1/54, 1/216. Both give a neighbouring plane the total weight 1/6.
+template <bool Q27>
+struct Lat {
+    static constexpr float A0F = 1.0f / 18.0f, A0C = 1.0f / 36.0f, A1C = 1.0f / 18.0f, A1F = 1.0f / 36.0f,
+                           A1K = 0.0f;
+};
+template <>
+struct Lat<true> {
+    static constexpr float A0F = 2.0f / 27.0f, A0C = 1.0f / 54.0f, A1C = 2.0f / 27.0f, A1F = 1.0f / 54.0f,
+                           A1K = 1.0f / 216.0f;
+};
+
 // -------------------------------------------------------------------------------------------
 // Magnetic sweep (Sec. 5.7): tau_m = 1, particle speed c = 6 eta, so c_i / c_s^2 = e_i / (2 eta).
 //
@@ -46,9 +61,10 @@ namespace mhd {
 // relative to lo, not to b. The first sweep of a step (a.bho set) re-splits v = hi + lo +
 // increment into a new hi = fp16(v) and lo = fp16(v - hi).
 // -------------------------------------------------------------------------------------------
-template <int TX, int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ>
+template <int TX, int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ, bool Q27>
 __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeStep *tab, const BlockMap *map,
                                                       int which, int nbatch) {
+    using LW = Lat<Q27>;
     constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HN = HX * HY;
     constexpr int NSLOT = (HN + NT - 1) / NT;
     // two LDS planes: the next plane is staged while the current one is reduced
@@ -146,7 +162,7 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
 
     const int c0 = (ly + 1) * HX + (lx + 1);
     const float kap = a.kappa * a.u_scale;
-    constexpr float W6 = 1.0f / 6.0f;  // WF + 4 WE: weight of a neighbouring plane as a whole
+    constexpr float W6 = 1.0f / 6.0f;  // total weight of a neighbouring plane (both lattices)
     // running sums of the plane contributions (difference form), and the column's own values
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     float ap0 = 0.f, ap1 = 0.f, ap2 = 0.f;
@@ -228,7 +244,8 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
         const float *s_lxy = s_pl[cur][3], *s_lxz = s_pl[cur][4], *s_lyz = s_pl[cur][5];
         if (own) {
             // b components: centre value and in-plane sums of differences to it
-            //   dP0 = sum_faces WF (f - c) + sum_corners WE (f - c),  dP1 = sum_faces WE (f - c)
+            //   dP0 = sum_faces a0f (f - c) + sum_corners a0c (f - c),
+            //   dP1 = sum_faces a1f (f - c) [+ sum_corners a1k (f - c) on D3Q27]
             float c_x, c_y, c_z, dP0x, dP1x, dP0y, dP1y, dP0z, dP1z;
 #define MHD_PLANE_DIFFS(F, C, DP0, DP1)                                                              \
     {                                                                                                \
@@ -237,8 +254,9 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
         const float fs = ((f[c0 - 1] - C) + (f[c0 + 1] - C)) + ((f[c0 - HX] - C) + (f[c0 + HX] - C)); \
         const float cs = ((f[c0 - HX - 1] - C) + (f[c0 - HX + 1] - C)) +                              \
                          ((f[c0 + HX - 1] - C) + (f[c0 + HX + 1] - C));                               \
-        DP0 = WF * fs + WE * cs;                                                                     \
-        DP1 = WE * fs;                                                                               \
+        DP0 = LW::A0F * fs + LW::A0C * cs;                                                           \
+        DP1 = LW::A1F * fs;                                                                          \
+        if constexpr (Q27) DP1 += LW::A1K * cs;                                                      \
     }
             MHD_PLANE_DIFFS(s_bx, c_x, dP0x, dP1x)
             MHD_PLANE_DIFFS(s_by, c_y, dP0y, dP1y)
@@ -249,10 +267,14 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
                 const float *f = s_lxy;
                 const float dx = f[c0 - 1] - f[c0 + 1], dy = f[c0 - HX] - f[c0 + HX];
                 const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
-                Q0xA = WF * dx + WE * ((mm - pm) + (mp - pp));
-                Q1xA = WE * dx;
-                Q0yA = WF * dy + WE * ((mm - mp) + (pm - pp));
-                Q1yA = WE * dy;
+                Q0xA = LW::A0F * dx + LW::A0C * ((mm - pm) + (mp - pp));
+                Q1xA = LW::A1F * dx;
+                Q0yA = LW::A0F * dy + LW::A0C * ((mm - mp) + (pm - pp));
+                Q1yA = LW::A1F * dy;
+                if constexpr (Q27) {
+                    Q1xA += LW::A1K * ((mm - pm) + (mp - pp));
+                    Q1yA += LW::A1K * ((mm - mp) + (pm - pp));
+                }
             }
             // kappa Lam_xz: P1, Q0x, Q1x and kappa Lam_yz: P1, Q0y, Q1y. These flux terms are
             // of order b / R, so plain weighted sums keep their rounding below that of b.
@@ -261,18 +283,26 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
                 const float *f = s_lxz;
                 const float xm = f[c0 - 1], xp = f[c0 + 1];
                 const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
-                P1B = WF * f[c0] + WE * ((xm + xp) + (f[c0 - HX] + f[c0 + HX]));
-                Q0xB = WF * (xm - xp) + WE * ((mm - pm) + (mp - pp));
-                Q1xB = WE * (xm - xp);
+                P1B = LW::A1C * f[c0] + LW::A1F * ((xm + xp) + (f[c0 - HX] + f[c0 + HX]));
+                Q0xB = LW::A0F * (xm - xp) + LW::A0C * ((mm - pm) + (mp - pp));
+                Q1xB = LW::A1F * (xm - xp);
+                if constexpr (Q27) {
+                    P1B += LW::A1K * ((mm + pm) + (mp + pp));
+                    Q1xB += LW::A1K * ((mm - pm) + (mp - pp));
+                }
             }
             float P1C, Q0yC, Q1yC;
             {
                 const float *f = s_lyz;
                 const float ym = f[c0 - HX], yp = f[c0 + HX];
                 const float mm = f[c0 - HX - 1], pm = f[c0 - HX + 1], mp = f[c0 + HX - 1], pp = f[c0 + HX + 1];
-                P1C = WF * f[c0] + WE * ((f[c0 - 1] + f[c0 + 1]) + (ym + yp));
-                Q0yC = WF * (ym - yp) + WE * ((mm - mp) + (pm - pp));
-                Q1yC = WE * (ym - yp);
+                P1C = LW::A1C * f[c0] + LW::A1F * ((f[c0 - 1] + f[c0 + 1]) + (ym + yp));
+                Q0yC = LW::A0F * (ym - yp) + LW::A0C * ((mm - mp) + (pm - pp));
+                Q1yC = LW::A1F * (ym - yp);
+                if constexpr (Q27) {
+                    P1C += LW::A1K * ((mm + pm) + (mp + pp));
+                    Q1yC += LW::A1K * ((mm - mp) + (pm - pp));
+                }
             }
             // contributions of this plane to the outputs at z+1 (A), z (B), z-1 (C)
             const float A0 = dP1x + Q1yA + P1B, B0 = dP0x + Q0yA, C0 = dP1x + Q1yA - P1B;
@@ -363,9 +393,10 @@ struct Pair<__hip_bfloat16> {
     }
 };
 
-template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ>
+template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ, bool Q27>
 __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
                                                             int which, int nbatch) {
+    using LW = Lat<Q27>;
     constexpr int HY = TY + 2;        // staged rows
     constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
     constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
@@ -602,7 +633,9 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                         const float c = v[1][1 + e];
                         const float fs = ((v[1][e] - c) + (v[1][e + 2] - c)) + ((v[0][1 + e] - c) + (v[2][1 + e] - c));
                         const float cs = ((v[0][e] - c) + (v[0][e + 2] - c)) + ((v[2][e] - c) + (v[2][e + 2] - c));
-                        const float dP0 = WF * fs + WE * cs, dP1 = WE * fs;
+                        const float dP0 = LW::A0F * fs + LW::A0C * cs;
+                        float dP1 = LW::A1F * fs;
+                        if constexpr (Q27) dP1 += LW::A1K * cs;
                         cen[e][k] = c;
                         A[e][k] = dP1;
                         B[e][k] = dP0;
@@ -616,10 +649,16 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const float dx = v[1][e] - v[1][e + 2], dy = v[0][1 + e] - v[2][1 + e];
-                    const float Q0x = WF * dx + WE * ((v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]));
-                    const float Q1x = WE * dx;
-                    const float Q0y = WF * dy + WE * ((v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]));
-                    const float Q1y = WE * dy;
+                    const float cdx = (v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]);
+                    const float cdy = (v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]);
+                    const float Q0x = LW::A0F * dx + LW::A0C * cdx;
+                    float Q1x = LW::A1F * dx;
+                    const float Q0y = LW::A0F * dy + LW::A0C * cdy;
+                    float Q1y = LW::A1F * dy;
+                    if constexpr (Q27) {
+                        Q1x += LW::A1K * cdx;
+                        Q1y += LW::A1K * cdy;
+                    }
                     A[e][0] += Q1y;
                     B[e][0] += Q0y;
                     C[e][0] += Q1y;
@@ -634,9 +673,14 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const float dx = v[1][e] - v[1][e + 2];
-                    const float P1 = WF * v[1][1 + e] + WE * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
-                    const float Q0x = WF * dx + WE * ((v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]));
-                    const float Q1x = WE * dx;
+                    const float cdx = (v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]);
+                    float P1 = LW::A1C * v[1][1 + e] + LW::A1F * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
+                    const float Q0x = LW::A0F * dx + LW::A0C * cdx;
+                    float Q1x = LW::A1F * dx;
+                    if constexpr (Q27) {
+                        P1 += LW::A1K * ((v[0][e] + v[0][e + 2]) + (v[2][e] + v[2][e + 2]));
+                        Q1x += LW::A1K * cdx;
+                    }
                     A[e][0] += P1;
                     C[e][0] -= P1;
                     A[e][2] -= Q1x;
@@ -649,9 +693,14 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const float dy = v[0][1 + e] - v[2][1 + e];
-                    const float P1 = WF * v[1][1 + e] + WE * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
-                    const float Q0y = WF * dy + WE * ((v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]));
-                    const float Q1y = WE * dy;
+                    const float cdy = (v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]);
+                    float P1 = LW::A1C * v[1][1 + e] + LW::A1F * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
+                    const float Q0y = LW::A0F * dy + LW::A0C * cdy;
+                    float Q1y = LW::A1F * dy;
+                    if constexpr (Q27) {
+                        P1 += LW::A1K * ((v[0][e] + v[0][e + 2]) + (v[2][e] + v[2][e + 2]));
+                        Q1y += LW::A1K * cdy;
+                    }
                     A[e][1] += P1;
                     C[e][1] -= P1;
                     A[e][2] -= Q1y;
@@ -724,6 +773,7 @@ SweepArgs make_sweep_args(const void *u, const void *b, void *bo, const float *b
     a.bho = nullptr;
     a.bext = bext;
     a.bext_yz = nullptr;
+    a.q27 = c.lattice == 27;
     a.nx = c.nx;
     a.ny = c.ny;
     a.nz = c.nz;
@@ -748,34 +798,34 @@ static inline unsigned sweep_grid(int nblocks) { return (unsigned)(((nblocks + 7
 
 // Sweeps are launched through hipExtLaunchKernelGGL: when profiling, its start / stop events
 // are stamped when the kernel itself starts and ends (no event packets around the launch).
-template <typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ>
+template <typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ, bool Q27>
 static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
                               const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(sweep_grid(nblocks));
     if (L.pair) {
         if (L.ty >= 8)
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
         else
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
         return hipGetLastError();
     }
     switch (L.tx) {
         case 64:
-            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<64, 4, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
         case 32:
-            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<32, 8, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
         case 16:
-            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<16, 16, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
         default:
-            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH, SPLIT, BYZ>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep<8, 32, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
             break;
     }
@@ -787,17 +837,25 @@ template <bool BATCH, bool BYZ>
 static hipError_t sweep_kinds_yz(hipStream_t s, int kinds, const SweepArgs &a, SweepLaunch L, const PipeStep *tab,
                                  const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     const int ku = (kinds >> 4) & 15, kb = (kinds >> 8) & 15;
+    if (L.q27) {  // D3Q27: float32 and the split form
+        if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
+            return sweep_typed<float, float, BATCH, false, BYZ, true>(s, a, L, tab, map, which, nblocks, e0, e1);
+        if (ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)
+            return sweep_typed<__half, __half, BATCH, true, BYZ, true>(s, a, L, tab, map, which, nblocks, e0, e1);
+        return hipErrorInvalidValue;
+    }
     if (ku == MHD_KIND_F32 && kb == MHD_KIND_F32)
-        return sweep_typed<float, float, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+        return sweep_typed<float, float, BATCH, false, BYZ, false>(s, a, L, tab, map, which, nblocks, e0, e1);
     if (ku == MHD_KIND_F16 && kb == MHD_KIND_F16)
-        return sweep_typed<__half, __half, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+        return sweep_typed<__half, __half, BATCH, false, BYZ, false>(s, a, L, tab, map, which, nblocks, e0, e1);
     if (ku == MHD_KIND_BF16 && kb == MHD_KIND_F16)
-        return sweep_typed<__hip_bfloat16, __half, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+        return sweep_typed<__hip_bfloat16, __half, BATCH, false, BYZ, false>(s, a, L, tab, map, which, nblocks, e0,
+                                                                             e1);
     if (ku == MHD_KIND_BF16 && kb == MHD_KIND_BF16)
-        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH, false, BYZ>(s, a, L, tab, map, which, nblocks, e0,
-                                                                              e1);
+        return sweep_typed<__hip_bfloat16, __hip_bfloat16, BATCH, false, BYZ, false>(s, a, L, tab, map, which, nblocks,
+                                                                                     e0, e1);
     if (ku == MHD_KIND_F32 && kb == MHD_KIND_F16_SPLIT)  // reads the float16 copy of u
-        return sweep_typed<__half, __half, BATCH, true, BYZ>(s, a, L, tab, map, which, nblocks, e0, e1);
+        return sweep_typed<__half, __half, BATCH, true, BYZ, false>(s, a, L, tab, map, which, nblocks, e0, e1);
     return hipErrorInvalidValue;
 }
 template <bool BATCH>
@@ -811,6 +869,7 @@ hipError_t launch_mag_sweep(hipStream_t s, int kinds, const SweepArgs &a0, Sweep
                             hipEvent_t e1) {
     L.pair = L.pair && a0.nx % 128 == 0;
     L.byz = a0.bext_yz != nullptr;
+    L.q27 = a0.q27;
     return sweep_kinds<false>(s, kinds, a0, L, nullptr, nullptr, 0, a0.nblocks, e0, e1);
 }
 

@@ -169,3 +169,19 @@ def test_batch_member_rules():
         mhd_destroy(B.pipes[0]._h)
     assert e.value.status == -5
     B.close()
+
+
+def test_batch_d3q27_matches_single_boxes_bitwise():
+    print("case batch d3q27", flush=True)
+    spec = batch_spec()[:3]
+    for w, _ in spec:
+        w.params.lattice = 27
+    B = make_batch(spec)
+    S = make_singles(spec, [p.tiles for p in B.pipes])
+    B.step(2)
+    for s in S:
+        s.step(2)
+    for i, (p, s) in enumerate(zip(B.pipes, S)):
+        assert_same(p, s, f"d3q27 pipe {i}")
+    compare(B.pipes[0], oracle_run(spec[0][0], 2), label="batch d3q27 pipe 0")
+    B.close()

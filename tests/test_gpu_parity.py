@@ -190,6 +190,64 @@ def test_six_magnet_field(nx, steps, n_mag):
     compare(gpu_run(w, steps), oracle_run(w, steps), label=f"six magnets {nx} {steps} steps")
 
 
+# ---------------------------------------------------------------------------------------------
+# D3Q27, the paper's own lattice (every part of the step)
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,markers", [((37, 21, 13), False), ((128, 13, 9), False), ((8, 32, 32), True)])
+def test_d3q27_one_step(shape, markers):
+    print("case d3q27", shape, flush=True)
+    w = random_box(*shape, key=230, n_mag=3)
+    compare(gpu_run(w, 1, markers=markers, lattice=27), oracle_run(w, 1, markers=markers, lattice=27),
+            label=f"d3q27 {shape}")
+
+
+def test_d3q27_small_pipe_10_steps_and_alpha_edge():
+    w = W.small_pipe()
+    print("case d3q27 pipe8", flush=True)
+    compare(gpu_run(w, 10, lattice=27, n_mag=60), oracle_run(w, 10, lattice=27, n_mag=60), label="d3q27 pipe8 10")
+    a = 13 / 27  # stability edge of the accelerated iteration on D3Q27
+    compare(gpu_run(w, 3, lattice=27, n_mag=30, alpha=a), oracle_run(w, 3, lattice=27, n_mag=30, alpha=a),
+            label="d3q27 alpha 13/27")
+
+
+def test_d3q27_split_form_and_budgets():
+    from paper_2211_09370_amd import Sim
+
+    print("case d3q27 split", flush=True)
+    w = random_box(128, 13, 9, key=231, n_mag=3)
+    sim = Sim(w.nx, w.ny, w.nz, 0, b_storage="f16split", u_scale=0.05, b_scale=0.01)
+    sim.set_params(w.params, lattice=27)
+    for f in ("rho", "u", "b"):
+        sim.set_field(f, getattr(w, f))
+    sim.step(1)
+    compare(sim, oracle_run(w, 1, markers=False, lattice=27), tol=2e-3, label="d3q27 split")
+    ws = W.small_pipe(b_amp=1e-3)
+    sim = gpu_run(ws, 4, budget_every=4, lattice=27, n_mag=20)
+    r = sim.budgets()[0]
+    p = oracle.make_params(ws.nx, ws.ny, ws.nz, ws.params, lattice=27, n_mag=20)
+    ref = oracle.budgets(p, sim.get_field("rho"), sim.get_field("u"), sim.get_field("b"), r["G"])
+    for k in ("E_k", "E_b", "P_nu", "P_L", "M_eta", "M_adv", "joule", "res_mag"):
+        assert abs(r[k] - ref[k]) <= 1e-9 * abs(ref[k]), (k, r[k], ref[k])
+
+
+def test_d3q27_argument_checks():
+    from paper_2211_09370_amd import MhdError, Sim, _abi
+
+    w = W.small_pipe()
+    sim = Sim(w.nx, w.ny, w.nz, 0)
+    for over, st in ((dict(lattice=27, alpha=0.47), _abi.MHD_ERR_INVALID_ARG),
+                     (dict(lattice=15), _abi.MHD_ERR_INVALID_ARG)):
+        with pytest.raises(MhdError) as e:
+            sim.set_params(w.params, **over)
+        assert e.value.status == st, over
+    sim.set_params(w.params, lattice=19, alpha=0.46)  # >= 4/9 is stable on D3Q19
+    half = Sim(w.nx, w.ny, w.nz, 0, rho_storage="f16", u_storage="f16", b_storage="f16", u_scale=0.05, b_scale=1.0)
+    with pytest.raises(MhdError) as e:
+        half.set_params(w.params, lattice=27)
+    assert e.value.status == _abi.MHD_ERR_UNSUPPORTED
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)

@@ -34,9 +34,12 @@ typedef int32_t mhd_status;
 #define MHD_ERR_INVALID_ARG (-1) /* argument out of range or inconsistent                   */
 #define MHD_ERR_OOM (-2)         /* workspace too small / host allocation failed            */
 #define MHD_ERR_HIP (-3)         /* a HIP runtime call failed (message names it)            */
-#define MHD_ERR_UNSTABLE (-4)    /* non-finite state or |u| >= c_s found by a budget pass    */
+#define MHD_ERR_UNSTABLE (-4)    /* non-finite state or |u| >= c_s found by a budget pass
+                                    (c_s = 1/sqrt(3); 6 nu / sqrt(3) on the macroscopic
+                                    fluid branch)                                           */
 #define MHD_ERR_STATE (-5)       /* call out of order (e.g. step before params/markers)     */
-#define MHD_ERR_UNSUPPORTED (-6) /* valid request outside this build (e.g. tau >= 1)        */
+#define MHD_ERR_UNSUPPORTED (-6) /* valid request outside this build (e.g. gamma != 1 with
+                                    tau >= 1)                                               */
 
 /* Storage kind of a field in device memory. Arithmetic is always float32. 16-bit kinds store
  * offsets: rho as rho - 1, u as u / u_scale, b as b / b_scale.
@@ -73,7 +76,11 @@ typedef enum {
 
 /* Physical parameters (lattice units). */
 typedef struct {
-    double nu;            /* kinematic viscosity; tau = 3 nu + 1/2 must lie in (1/2, 1)     */
+    double nu;            /* kinematic viscosity (> 0). tau = 3 nu / gamma + 1/2 selects the
+                             fluid update: tau < 1, the single-step predictor (Sec. 3.3, 5.1);
+                             tau >= 1 (gamma = 1 only), the macroscopic tau = 1 update with
+                             particle speed c = 6 nu (Sec. 5.7), one step then advancing the
+                             time by 1 / (6 nu) (forces act over that step)                  */
     double eta;           /* magnetic resistivity (> 0); particle speed of the b iteration
                              c = 6 eta, kappa = 1/(2 eta) (Sec. 5.7)                      */
     int32_t n_mag;        /* magnetic sweeps per fluid step (>= 1), usually
@@ -104,6 +111,13 @@ typedef struct {
     double magnet_distance;   /* six magnets: distance of the strip centres from the axis;
                                  <= 0 -> distance of the farthest cell of the box from the axis
                                  + L + 1 (no strip reaches into the box)                      */
+    double gamma;         /* time-step rescaling of the fluid update (Sec. 7): dt -> dt / gamma,
+                             c_i -> gamma c_i. The quadratic part of f^eq is divided by gamma,
+                             tau = 3 nu / gamma + 1/2, the GZS populations take their rescaled
+                             form and the explicit force term is F / gamma, so a steady state
+                             does not depend on gamma and a transient takes gamma times as many
+                             steps. <= 0 or 1: no rescaling. The magnetic iteration is unchanged
+                             (quasi-static: it has no time step).                             */
 } mhd_params;
 
 typedef enum { MHD_FIELD_RHO = 0, MHD_FIELD_U = 1, MHD_FIELD_B_INDUCED = 2 } mhd_field;
@@ -149,9 +163,10 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
 mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const double *u_wall,
                            const double *b_wall);
 
-/* Parameters (copied). INVALID_ARG if tau = 3 nu + 1/2 <= 1/2, eta <= 0, n_mag < 1, a fringe
- * width <= 0, 0 < alpha < 4/9, or (with markers set) 1 + d_j (lambda - 1) <= 0 for some marker
- * (the scaling of Sec. 5.5 / 5.6 would be singular or negative). UNSUPPORTED if tau >= 1. */
+/* Parameters (copied). INVALID_ARG if nu <= 0, eta <= 0, n_mag < 1, a fringe width <= 0,
+ * 0 < alpha below its lattice bound, or (with markers set) 1 + d_j (lambda - 1) <= 0 for some
+ * marker (the scaling of Sec. 5.5 / 5.6 would be singular or negative). UNSUPPORTED if
+ * tau = 3 nu / gamma + 1/2 >= 1 with gamma != 1 (the macroscopic branch has no rescaling). */
 mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p);
 
 /* Copy a field in / out (host float64, layout above; rho has 1 component, u and b 3).

@@ -11,7 +11,9 @@ Functions and the passage each follows:
   ib_correct   - explicit correction phi* + D^T diag(s) (phi_b - D phi*), s from Sec. 5.5 / 5.6
   lorentz      - G x + (curl b) x B with isotropic differences (Sec. 5.1)
   fluid        - single-step density / momentum update with GZS forcing and the lattice
-                 discrete-effect term (Sec. 3.3, Sec. 5.1)
+                 discrete-effect term (Sec. 3.3, Sec. 5.1), with the time-step rescaling gamma
+                 (Sec. 7); for tau >= 1 the macroscopic tau = 1 update with speed 6 nu (Sec. 5.7)
+  fluid_tau    - tau = 3 nu / gamma + 1/2 (Sec. 7)
   Oracle.step  - whole step in the order of Sec. 5.7 (magnetic iteration, then velocity)
   budgets      - energy budget averages of Sec. 4 over r < R - 2, mass, flow rate
 """
@@ -41,7 +43,7 @@ class OrcParams(C.Structure):
                 ("radius", C.c_double), ("flow_control", C.c_int), ("u_target", C.c_double),
                 ("k_c", C.c_double), ("ib_u", C.c_int), ("ib_b", C.c_int),
                 ("alpha", C.c_double), ("magnet_L", C.c_double), ("magnet_D", C.c_double),
-                ("lattice", C.c_int)]
+                ("lattice", C.c_int), ("gamma", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -65,6 +67,8 @@ def lib():
         L.orc_ib_correct.argtypes = [P, C.c_int64, _D, _D, C.c_double, _D, _D]
         L.orc_lorentz.argtypes = [P, _D, C.c_double, _D]
         L.orc_fluid.argtypes = [P, _D, _D, _D, _D, _D]
+        L.orc_fluid_tau.argtypes = [P]
+        L.orc_fluid_tau.restype = C.c_double
         L.orc_create.argtypes = [P, C.c_int64, _D, _D, _D]
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -95,7 +99,7 @@ def make_params(nx, ny, nz, prm=None, *, ib_u=1, ib_b=1, **over) -> OrcParams:
     fields = dict(nu=0.1, eta=1.0, n_mag=1, lambda_u=1.0, lambda_b=0.0, G0=0.0, G1=0.0, period=0.0,
                   bext_kind=0, B0=0.0, fringe_x0=0.0, fringe_w=1.0, yc=0.0, zc=0.0, radius=0.0,
                   flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0, magnet_L=0.0, magnet_D=0.0,
-                  lattice=19)
+                  lattice=19, gamma=1.0)
     if prm is not None:
         for k in list(fields):
             src = {"radius": "avg_radius", "u_target": "u_bulk_target"}.get(k, k)
@@ -171,6 +175,10 @@ def lorentz(p: OrcParams, b, G):
     F = np.empty_like(b)
     lib().orc_lorentz(C.byref(p), _ptr(b), float(G), _ptr(F))
     return F
+
+
+def fluid_tau(p: OrcParams) -> float:
+    return float(lib().orc_fluid_tau(C.byref(p)))
 
 
 def fluid(p: OrcParams, rho, u, F):

@@ -20,7 +20,8 @@
  *                   b  = b* + D^T S_m (b_wall - D b*) (explicit IB for B, Sec. 5.4 / 5.6)
  *   2. F = G(t) x + (curl b) x (B_ext + b)           (Lorentz force, Sec. 5.1)
  *   3. rho', u* from the single-step update with the GZS forcing and its lattice discrete-effect
- *      term (Sec. 3.3 and Sec. 5.1)
+ *      term (Sec. 3.3 and Sec. 5.1), optionally with the time-step rescaling gamma of Sec. 7;
+ *      for tau >= 1 from the macroscopic tau = 1 update with particle speed 6 nu (Sec. 5.7)
  *   4. u = u* + D^T S (u_wall - D u*)                (explicit IB for u, Sec. 5.3 / 5.5)
  *   5. optional flow-rate control of G, t += 1.
  *
@@ -30,6 +31,10 @@
  *   - the Lorentz current is J = curl b (identical for curl-free B_ext);
  *   - the improved momentum update is read in momentum form: rho' u* = gather - (tau/2) sum ...
  *     + F, as in the plain forcing form of Sec. 3.5;
+ *   - with the rescaling gamma (Sec. 7) the explicit force term is F dt with the rescaled step
+ *     dt = 1/gamma, so that a steady state does not depend on gamma;
+ *   - the macroscopic branch (tau >= 1) takes the GZS forcing at tau = 1 with the usual half-force
+ *     term in the momentum, (dt/2) F(x), evaluated with the force of the current step;
  *   - the wall correction for B runs after every magnetic sweep, the one for u once per step;
  *   - sums over i run over all Q directions, rest included;
  *   - the Lagrange stencil of a marker is its nearest node and that node +-1 in each direction,
@@ -63,6 +68,7 @@ typedef struct {
     double magnet_L, magnet_D; /* six magnets: strip half-width (<= 0: radius / 6) and distance
                                   of the strip centres from the axis (<= 0: see magnet_geometry) */
     int lattice;    /* 27: D3Q27 (the paper's set, Table I); otherwise D3Q19 */
+    double gamma;   /* time-step rescaling of Sec. 7 (dt -> dt / gamma); <= 0 means 1 */
 } orc_params;
 
 /* D3Q19 velocity set and weights (textbook values). */
@@ -191,25 +197,51 @@ void orc_bext(const orc_params *p, int x, int y, int z, double B[3]) {
 /* Equilibria                                                                                 */
 /* ------------------------------------------------------------------------------------------ */
 
-/* Fluid equilibrium f_i^eq(rho, u) with c_s^2 = 1/3 (Sec. 3.1 / Sec. 3.5). */
-static inline double feq(const lattice_t *L, int i, double rho, const double u[3]) {
+/* Fluid equilibrium f_i^eq(rho, u) with c_s^2 = 1/3 (Sec. 3.1 / Sec. 3.5). With the time-step
+ * rescaling of Sec. 7 (dt -> dt / gamma, c_i -> gamma c_i) the quadratic part is divided by
+ * gamma; gamma = 1 is the plain equilibrium. */
+static inline double feq(const lattice_t *L, int i, double rho, const double u[3], double gamma) {
     const int *e = L->E[i];
     double cu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    return L->W[i] * rho * (1.0 + cu / CS2 + (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    double quad = (cu * cu) / (2.0 * CS2 * CS2) - uu / (2.0 * CS2);
+    return L->W[i] * rho * (1.0 + cu / CS2 + quad / gamma);
 }
 
-/* GZS forcing population F_i (Sec. 5.1): (1 - 1/(2 tau)) w_i [(c_i - u)/c_s^2
- * + (c_i . u) c_i / c_s^4] . F */
-static inline double fgzs(const lattice_t *L, int i, double tau, const double u[3], const double F[3]) {
+/* GZS forcing population F_i (Sec. 5.1), in the rescaled form of Sec. 7:
+ * (1 - 1/(2 tau)) w_i [(c_i - u/gamma) / (gamma c_s^2) + (c_i . u) c_i / (gamma^2 c_s^4)] . F
+ * (gamma = 1: the plain GZS population). */
+static inline double fgzs(const lattice_t *L, int i, double tau, double gamma, const double u[3],
+                          const double F[3]) {
     const int *e = L->E[i];
     double cu = e[0] * u[0] + e[1] * u[1] + e[2] * u[2];
     double s = 0.0;
     for (int a = 0; a < 3; ++a) {
-        double v = (e[a] - u[a]) / CS2 + cu * e[a] / (CS2 * CS2);
+        double v = (e[a] - u[a] / gamma) / (gamma * CS2) + cu * e[a] / (gamma * gamma * CS2 * CS2);
         s += v * F[a];
     }
     return (1.0 - 1.0 / (2.0 * tau)) * L->W[i] * s;
+}
+
+/* Equilibrium with particle speed c (c_i = c e_i, c_s^2 = c^2 / 3), the macroscopic branch of
+ * Sec. 5.7 for tau >= 1. */
+static inline double feq_c(const lattice_t *L, int i, double c, double rho, const double u[3]) {
+    double ci[3], cs2 = c * c / 3.0;
+    for (int a = 0; a < 3; ++a) ci[a] = c * L->E[i][a];
+    double cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return L->W[i] * rho * (1.0 + cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+}
+
+/* GZS population with particle speed c and tau = 1: (1/2) w_i [(c_i - u)/c_s^2 + (c_i . u) c_i /
+ * c_s^4] . F. */
+static inline double fgzs_c(const lattice_t *L, int i, double c, const double u[3], const double F[3]) {
+    double ci[3], cs2 = c * c / 3.0;
+    for (int a = 0; a < 3; ++a) ci[a] = c * L->E[i][a];
+    double cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2];
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) s += ((ci[a] - u[a]) / cs2 + cu * ci[a] / (cs2 * cs2)) * F[a];
+    return 0.5 * L->W[i] * s;
 }
 
 /* Magnetic equilibrium of the tau_m = 1 iteration with particle speed c = 6 eta (Sec. 5.7):
@@ -429,12 +461,24 @@ void orc_lorentz(const orc_params *p, const double *b, double G, double *F) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Fluid single-step predictor with GZS forcing and discrete-effect term (Sec. 3.3, 5.1)     */
+/* Fluid update                                                                               */
 /* ------------------------------------------------------------------------------------------ */
-void orc_fluid(const orc_params *p, const double *rho, const double *u, const double *F,
-               double *rho_out, double *u_out) {
+static double gamma_of(const orc_params *p) { return p->gamma > 0.0 ? p->gamma : 1.0; }
+
+/* Relaxation time of the fluid: nu = c_s^2 (tau - 1/2) dt with the rescaled step dt / gamma
+ * (Sec. 7), i.e. tau = 3 nu / gamma + 1/2. */
+double orc_fluid_tau(const orc_params *p) { return p->nu / (CS2 * gamma_of(p)) + 0.5; }
+
+/* Single-step predictor with GZS forcing and discrete-effect term (Sec. 3.3, 5.1), tau < 1:
+ *   rho'    = sum_i [3/2 f_i(x - e_i) - f_i(x) + 1/2 f_i(x + e_i)]
+ *   rho' u' = sum_i e_i {f_i(x - e_i) + (tau - 1) [f_i(x + e_i) - 2 f_i(x) + f_i(x - e_i)]}
+ *             - (tau/2) sum_i e_i [F_i(x + e_i) - F_i(x - e_i)] + F(x) dt
+ * with the rescaled f^eq, F_i and tau of Sec. 7 and dt = 1/gamma (1 without rescaling). */
+static void fluid_single_step(const orc_params *p, const double *rho, const double *u, const double *F,
+                              double *rho_out, double *u_out) {
     const int64_t N = ncells(p);
-    const double tau = p->nu / CS2 + 0.5; /* nu = c_s^2 (tau - 1/2) */
+    const double gamma = gamma_of(p);
+    const double tau = orc_fluid_tau(p);
     const lattice_t L = lattice_of(p);
 #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < p->nz; ++z)
@@ -453,12 +497,12 @@ void orc_fluid(const orc_params *p, const double *rho, const double *u, const do
                     load3(u, N, kp, up);
                     load3(F, N, km, Fm);
                     load3(F, N, kp, Fp);
-                    double f_m = feq(&L, i, rho[km], um); /* f_i^eq(x - e_i) */
-                    double f_0 = feq(&L, i, rho[k0], u0); /* f_i^eq(x) */
-                    double f_p = feq(&L, i, rho[kp], up); /* f_i^eq(x + e_i) */
+                    double f_m = feq(&L, i, rho[km], um, gamma); /* f_i^eq(x - e_i) */
+                    double f_0 = feq(&L, i, rho[k0], u0, gamma); /* f_i^eq(x) */
+                    double f_p = feq(&L, i, rho[kp], up, gamma); /* f_i^eq(x + e_i) */
                     rsum += 1.5 * f_m - f_0 + 0.5 * f_p;
-                    double Fi_p = fgzs(&L, i, tau, up, Fp);
-                    double Fi_m = fgzs(&L, i, tau, um, Fm);
+                    double Fi_p = fgzs(&L, i, tau, gamma, up, Fp);
+                    double Fi_m = fgzs(&L, i, tau, gamma, um, Fm);
                     for (int a = 0; a < 3; ++a) {
                         m[a] += L.E[i][a] * (f_m + (tau - 1.0) * (f_p - 2.0 * f_0 + f_m));
                         fsum[a] += L.E[i][a] * (Fi_p - Fi_m);
@@ -466,10 +510,55 @@ void orc_fluid(const orc_params *p, const double *rho, const double *u, const do
                 }
                 rho_out[k0] = rsum;
                 for (int a = 0; a < 3; ++a) {
-                    double mom = m[a] - 0.5 * tau * fsum[a] + F0[a];
+                    double mom = m[a] - 0.5 * tau * fsum[a] + F0[a] / gamma;
                     u_out[a * N + k0] = mom / rsum;
                 }
             }
+}
+
+/* Macroscopic update for tau >= 1 (Sec. 5.7): the BGK update with tau = 1 and the GZS forcing
+ * population, particle speed c = 6 nu (c_i = c e_i, c_s^2 = c^2/3, dt = 1/c, dx = 1):
+ *   f_i(x, t + dt) = f_i^eq(x - c_i dt, t) + dt F_i(x - c_i dt, t)
+ *   rho' = sum_i f_i(x, t + dt),  rho' u' = sum_i c_i f_i(x, t + dt) + (dt/2) F(x, t).
+ * One call advances the time by dt = 1/(6 nu). */
+static void fluid_macroscopic(const orc_params *p, const double *rho, const double *u, const double *F,
+                              double *rho_out, double *u_out) {
+    const int64_t N = ncells(p);
+    const double c = 6.0 * p->nu, dt = 1.0 / c;
+    const lattice_t L = lattice_of(p);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t k0 = cell(p, x, y, z);
+                double rsum = 0.0, m[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < L.Q; ++i) {
+                    int64_t km = cell(p, x - L.E[i][0], y - L.E[i][1], z - L.E[i][2]);
+                    double um[3], Fm[3];
+                    load3(u, N, km, um);
+                    load3(F, N, km, Fm);
+                    double fi = feq_c(&L, i, c, rho[km], um) + dt * fgzs_c(&L, i, c, um, Fm);
+                    rsum += fi;
+                    for (int a = 0; a < 3; ++a) m[a] += c * L.E[i][a] * fi;
+                }
+                rho_out[k0] = rsum;
+                for (int a = 0; a < 3; ++a) u_out[a * N + k0] = (m[a] + 0.5 * dt * F[a * N + k0]) / rsum;
+            }
+}
+
+/* One fluid update: the single-step predictor for tau < 1, the macroscopic branch for tau >= 1
+ * (defined without rescaling only: gamma != 1 with tau >= 1 gives NaN). */
+void orc_fluid(const orc_params *p, const double *rho, const double *u, const double *F,
+               double *rho_out, double *u_out) {
+    if (orc_fluid_tau(p) < 1.0) {
+        fluid_single_step(p, rho, u, F, rho_out, u_out);
+    } else if (gamma_of(p) == 1.0) {
+        fluid_macroscopic(p, rho, u, F, rho_out, u_out);
+    } else {
+        const int64_t N = ncells(p);
+        for (int64_t k = 0; k < N; ++k) rho_out[k] = NAN;
+        for (int64_t k = 0; k < 3 * N; ++k) u_out[k] = NAN;
+    }
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -223,6 +223,7 @@ def make_params(src=None, **over) -> mhd_params:
     p.k_c = 0.1
     p.n_mag = 1
     p.alpha = 1.0
+    p.gamma = 1.0
     names = [f for f, _ in mhd_params._fields_]
     vals = {}
     if src is not None:

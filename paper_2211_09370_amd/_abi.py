@@ -55,7 +55,8 @@ class mhd_params(C.Structure):
                 ("yc", C.c_double), ("zc", C.c_double), ("avg_radius", C.c_double),
                 ("flow_control", C.c_int32), ("lattice", C.c_int32),
                 ("u_bulk_target", C.c_double), ("k_c", C.c_double), ("alpha", C.c_double),
-                ("magnet_half_width", C.c_double), ("magnet_distance", C.c_double)]
+                ("magnet_half_width", C.c_double), ("magnet_distance", C.c_double),
+                ("gamma", C.c_double)]
 
 
 class mhd_budget(C.Structure):

@@ -25,7 +25,11 @@ struct DevCtrl {
 struct StepConst {
     int nx, ny, nz;
     float kappa;       // 1 / (2 eta)
-    float tau;         // 3 nu + 1/2
+    float tau;         // 3 nu / gamma + 1/2
+    float inv_gamma;   // 1 / gamma of the rescaled fluid update (1: none)
+    int mac;           // 1: macroscopic tau = 1 fluid update with particle speed mac_c = 6 nu
+    float mac_c, inv_mac_c;
+    double u_limit2;   // |u|^2 at or above which a budget pass flags the state (c_s^2)
     float u_scale, inv_u_scale, b_scale, inv_b_scale;
     float copy_scale, inv_copy_scale;  // split form: scale of the float16 copy of u
     float omega;                       // 1 / alpha of the accelerated magnetic iteration

@@ -12,7 +12,8 @@
 //   k_ib_interp    per marker: delta_j = s_j (b_wall - sum_k D_jk phi_k)     (Sec. 5.4 / 5.6)
 //   k_ib_spread    per wall-band cell: phi_k += sum_j D_jk delta_j (gather form, no atomics)
 //   k_lorentz      F = G x + (curl b) x (B_ext + b), isotropic differences    (Sec. 5.1)
-//   k_fluid        single-step rho, rho u with GZS forcing + discrete-effect term (Sec. 3.3, 5.1)
+//   k_fluid        single-step rho, rho u with GZS forcing + discrete-effect term (Sec. 3.3, 5.1),
+//                  rescaled by gamma (Sec. 7); macroscopic tau = 1 update for tau >= 1 (Sec. 5.7)
 //   k_ib_interp / k_ib_spread on u                                              (Sec. 5.3 / 5.5)
 //   k_flow_partial + k_step_end   flow-rate control sum (float64), step counter
 //   k_budget_partial + k_budget_final   every K steps: energy budgets of Sec. 4 (float64)
@@ -293,6 +294,24 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
 // G = 9 (d.u)(d.F) - 3 u.F and c_F = 1 - 1/(2 tau). Every term is a neighbour difference, so the
 // float32 rounding is relative to the change of the step, and the new state is
 // drho' = drho + delta, u* = u + (Dm - delta u) / (1 + drho').
+//
+// Time-step rescaling (Sec. 7, inv_gamma = 1/gamma): q2 -> q2 / gamma (so DQ scales by 1/gamma),
+// the velocity terms of the GZS populations by 1/gamma^2 (G scales by 1/gamma^2; their e.F part
+// cancels in the pair sums) and the explicit force F -> F / gamma; tau = 3 nu / gamma + 1/2.
+// All three are exact no-ops at gamma = 1.
+//
+// Macroscopic update (tau >= 1, Sec. 5.7; c.mac): the lattice BGK update with tau = 1 and the GZS
+// populations, in v = u / c and phi = F / c^2 with particle speed c = 6 nu (one step is dt = 1/c):
+//   f_i(x) = f_i^eq(x - e_i) + P_i(x - e_i),  P_i = (w_i / 2) [3 (e_i - v) . phi + 9 (e_i . v)(e_i . phi)],
+//   rho' = sum_i f_i,  rho' v' = sum_i e_i f_i + phi(x) / 2.
+// Per pair d (i = +d gathers from x - d, i = -d from x + d), with Q_i = (1 + drho) q_i(v),
+// q_i = 3 e_i.v + 4.5 (e_i.v)^2 - 1.5 v.v and H = 9 (d.v)(d.phi) - 3 v.phi (sum_i w_i H_i = 0 at
+// one point, sum_i w_i e_i (e_i.phi) = phi / 3):
+//   drho' - drho = sum_pairs w [(Ddrho- + Ddrho+) + (DQ_d(x-d) + DQ_-d(x+d))
+//                               + 1.5 d.(phi- - phi+) + (H- + H+ - 2 H0) / 2]
+//   rho' v' - rho v = phi + sum_pairs w d [(drho- - drho+) + (DQ_d(x-d) - DQ_-d(x+d))
+//                               + 1.5 d.(phi- + phi+ - 2 phi) + (H- - H+) / 2]
+// with DQ_i(y) = Q_i(y) - Q_i(x): again neighbour differences only.
 // -------------------------------------------------------------------------------------------
 // One direction of each opposite pair: 3 faces, 6 edges (D3Q19), then the 4 corners of D3Q27.
 __constant__ int c_pair[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1},
@@ -321,7 +340,70 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
     const int x = (int)(k % c.nx);
     const int y = (int)((k / c.nx) % c.ny);
     const int z = (int)(k / ((int64_t)c.nx * c.ny));
-    const float tau = c.tau, us = c.u_scale;
+    const float us = c.u_scale;
+    if (c.mac) {
+        const float ic = c.inv_mac_c, ic2 = ic * ic;
+        const float d0 = St<TR>::ld(rho, k);
+        const float vx0 = St<TU>::ld(u, k) * us * ic, vy0 = St<TU>::ld(u, N + k) * us * ic,
+                    vz0 = St<TU>::ld(u, 2 * N + k) * us * ic;
+        const float px0 = F[k] * ic2, py0 = F[N + k] * ic2, pz0 = F[2 * N + k] * ic2;
+        const float vv0 = vx0 * vx0 + vy0 * vy0 + vz0 * vz0, vp0 = vx0 * px0 + vy0 * py0 + vz0 * pz0;
+        float dr = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < (Q27 ? 13 : 9); ++i) {
+            const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
+            const float w = Q27 ? (i < 3 ? 2.0f / 27.0f : i < 9 ? 1.0f / 54.0f : 1.0f / 216.0f) : (i < 3 ? WF : WE);
+            const int64_t kp = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
+            const int64_t km = wrapi(x - ex, c.nx) + (int64_t)c.nx * (wrapi(y - ey, c.ny) + (int64_t)c.ny * wrapi(z - ez, c.nz));
+            const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
+            const float vpx = St<TU>::ld(u, kp) * us * ic, vpy = St<TU>::ld(u, N + kp) * us * ic,
+                        vpz = St<TU>::ld(u, 2 * N + kp) * us * ic;
+            const float vmx = St<TU>::ld(u, km) * us * ic, vmy = St<TU>::ld(u, N + km) * us * ic,
+                        vmz = St<TU>::ld(u, 2 * N + km) * us * ic;
+            const float ppx = F[kp] * ic2, ppy = F[N + kp] * ic2, ppz = F[2 * N + kp] * ic2;
+            const float pmx = F[km] * ic2, pmy = F[N + km] * ic2, pmz = F[2 * N + km] * ic2;
+            const float Dpx = vpx - vx0, Dpy = vpy - vy0, Dpz = vpz - vz0;
+            const float Dmx = vmx - vx0, Dmy = vmy - vy0, Dmz = vmz - vz0;
+            const float Ddp = dp - d0, Ddm = dm - d0;
+            const float ev0 = ex * vx0 + ey * vy0 + ez * vz0;
+            const float eDp = ex * Dpx + ey * Dpy + ez * Dpz, eDm = ex * Dmx + ey * Dmy + ez * Dmz;
+            const float q20 = 4.5f * ev0 * ev0 - 1.5f * vv0;
+            // q_{+d}(v-) - q_{+d}(v0) and q_{-d}(v+) - q_{-d}(v0)
+            const float dqm = 3.0f * eDm + 4.5f * eDm * (eDm + 2.0f * ev0) -
+                              1.5f * (Dmx * (vmx + vx0) + Dmy * (vmy + vy0) + Dmz * (vmz + vz0));
+            const float dqp = -3.0f * eDp + 4.5f * eDp * (eDp + 2.0f * ev0) -
+                              1.5f * (Dpx * (vpx + vx0) + Dpy * (vpy + vy0) + Dpz * (vpz + vz0));
+            const float DQm = (1.0f + dm) * dqm + Ddm * (q20 + 3.0f * ev0);
+            const float DQp = (1.0f + dp) * dqp + Ddp * (q20 - 3.0f * ev0);
+            const float epm = ex * pmx + ey * pmy + ez * pmz, epp = ex * ppx + ey * ppy + ez * ppz,
+                        ep0 = ex * px0 + ey * py0 + ez * pz0;
+            const float Hm = 9.0f * (ev0 + eDm) * epm - 3.0f * (vmx * pmx + vmy * pmy + vmz * pmz);
+            const float Hp = 9.0f * (ev0 + eDp) * epp - 3.0f * (vpx * ppx + vpy * ppy + vpz * ppz);
+            const float H0 = 9.0f * ev0 * ep0 - 3.0f * vp0;
+            dr += w * ((Ddm + Ddp) + (DQm + DQp) + 1.5f * (epm - epp) + 0.5f * ((Hm - H0) + (Hp - H0)));
+            const float cm = w * ((dm - dp) + (DQm - DQp) + 1.5f * ((epm - ep0) + (epp - ep0)) + 0.5f * (Hm - Hp));
+            m0 += ex * cm;
+            m1 += ey * cm;
+            m2 += ez * cm;
+        }
+        const float dnew = d0 + dr;
+        const float inv = 1.0f / (1.0f + dnew);
+        St<TR>::st(rho_o, k, dnew);
+        const float cu = c.mac_c;
+        const float un0 = cu * (vx0 + ((m0 + px0) - dr * vx0) * inv);
+        const float un1 = cu * (vy0 + ((m1 + py0) - dr * vy0) * inv);
+        const float un2 = cu * (vz0 + ((m2 + pz0) - dr * vz0) * inv);
+        St<TU>::st(u_o, k, un0 * c.inv_u_scale);
+        St<TU>::st(u_o, N + k, un1 * c.inv_u_scale);
+        St<TU>::st(u_o, 2 * N + k, un2 * c.inv_u_scale);
+        if (u_copy) {
+            u_copy[k] = __float2half_rn(un0 * c.inv_copy_scale);
+            u_copy[N + k] = __float2half_rn(un1 * c.inv_copy_scale);
+            u_copy[2 * N + k] = __float2half_rn(un2 * c.inv_copy_scale);
+        }
+        return;
+    }
+    const float tau = c.tau, ig = c.inv_gamma;
     const float cF = 1.0f - 0.5f / tau;
     const float a3 = 3.0f * (2.0f * tau - 1.0f);
 
@@ -352,7 +434,7 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         const float q20 = 4.5f * eu0 * eu0 - 1.5f * uu0;
         const float dq2p = 4.5f * eDp * (eup + eu0) - 1.5f * (Dpx * (upx + ux0) + Dpy * (upy + uy0) + Dpz * (upz + uz0));
         const float dq2m = 4.5f * eDm * (eum + eu0) - 1.5f * (Dmx * (umx + ux0) + Dmy * (umy + uy0) + Dmz * (umz + uz0));
-        const float DQp = (1.0f + dp) * dq2p + Ddp * q20, DQm = (1.0f + dm) * dq2m + Ddm * q20;
+        const float DQp = ig * ((1.0f + dp) * dq2p + Ddp * q20), DQm = ig * ((1.0f + dm) * dq2m + Ddm * q20);
         // momentum differences along d: d.(J+- - J0) = d.D + (drho+- d.u+- - drho0 d.u0)
         const float dJp = eDp + (dp * eup - d0 * eu0), dJm = eDm + (dm * eum - d0 * eu0);
         dr += w * (2.0f * (Ddp + Ddm) + 2.0f * (DQp + DQm) + 3.0f * (dJm - dJp));
@@ -369,10 +451,10 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         g2 += ez * cg;
     }
     const float dnew = d0 + dr;
-    const float tcF = tau * cF;
-    const float Dm0 = (m0 - tcF * g0) + F[k];
-    const float Dm1 = (m1 - tcF * g1) + F[N + k];
-    const float Dm2 = (m2 - tcF * g2) + F[2 * N + k];
+    const float tcF = tau * cF * (ig * ig);
+    const float Dm0 = (m0 - tcF * g0) + F[k] * ig;
+    const float Dm1 = (m1 - tcF * g1) + F[N + k] * ig;
+    const float Dm2 = (m2 - tcF * g2) + F[2 * N + k] * ig;
     const float inv = 1.0f / (1.0f + dnew);
     St<TR>::st(rho_o, k, dnew);
     const float un0 = ux0 + (Dm0 - dr * ux0) * inv, un1 = uy0 + (Dm1 - dr * uy0) * inv,
@@ -588,8 +670,8 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part
         r.u_max = sqrt(shm[0]);
         r.n_omega = n;
         r.res_mag = sqrt(sh[13][0] * inv);
-        // |u| >= c_s = 1/sqrt(3) or a non-finite value marks the run unstable
-        if (shf[0] != 0.0 || !(shm[0] < 1.0 / 3.0) || !isfinite(sh[0][0])) ctrl->status |= 1;
+        // |u| >= c_s or a non-finite value marks the run unstable
+        if (shf[0] != 0.0 || !(shm[0] < c.u_limit2) || !isfinite(sh[0][0])) ctrl->status |= 1;
         const int idx = ctrl->n_records;
         if (idx < kRingCap) {
             ring[idx] = r;

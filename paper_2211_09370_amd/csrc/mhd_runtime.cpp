@@ -21,7 +21,7 @@ using namespace mhd;
 
 // The Python binding mirrors these structs field by field (tests check the same sizes).
 static_assert(sizeof(mhd_grid_desc) == 40, "mhd_grid_desc layout");
-static_assert(sizeof(mhd_params) == 160, "mhd_params layout");
+static_assert(sizeof(mhd_params) == 168, "mhd_params layout");
 static_assert(sizeof(mhd_budget) == 136, "mhd_budget layout");
 static_assert(sizeof(mhd_pipe_desc) == 48, "mhd_pipe_desc layout");
 
@@ -187,6 +187,10 @@ namespace {
 
 void batch_touch(mhd_batch *b);  // the launch plan of a batch must be rebuilt
 
+double gamma_of(const mhd_params &p) { return p.gamma > 0.0 ? p.gamma : 1.0; }
+// tau = 3 nu / gamma + 1/2 >= 1: the macroscopic branch (set_params admits it with gamma = 1 only)
+bool fluid_branch_mac(const mhd_params &p) { return !(3.0 * p.nu / gamma_of(p) + 0.5 < 1.0); }
+
 StepConst step_const(const mhd_sim *s) {
     StepConst c{};
     c.nx = s->g.nx;
@@ -194,7 +198,13 @@ StepConst step_const(const mhd_sim *s) {
     c.nz = s->g.nz;
     const mhd_params &p = s->prm;
     c.kappa = (float)(1.0 / (2.0 * p.eta));
-    c.tau = (float)(3.0 * p.nu + 0.5);
+    const double gamma = gamma_of(p);
+    c.tau = (float)(3.0 * p.nu / gamma + 0.5);
+    c.inv_gamma = (float)(1.0 / gamma);
+    c.mac = fluid_branch_mac(p) ? 1 : 0;
+    c.mac_c = (float)(6.0 * p.nu);
+    c.inv_mac_c = (float)(1.0 / (6.0 * p.nu));
+    c.u_limit2 = c.mac ? 12.0 * p.nu * p.nu : 1.0 / 3.0;
     c.u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.u_scale;
     c.inv_u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.u_scale);
     c.b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.b_scale;
@@ -695,9 +705,11 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
 mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
     g_err.clear();
     if (!s || !p) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
-    const double tau = 3.0 * p->nu + 0.5;
-    if (!(p->nu > 0.0)) return fail(MHD_ERR_INVALID_ARG, "nu = %g gives tau = %g <= 1/2", p->nu, tau);
-    if (!(tau < 1.0)) return fail(MHD_ERR_UNSUPPORTED, "tau = %g >= 1 needs the macroscopic fluid branch (not built)", tau);
+    if (!(p->nu > 0.0)) return fail(MHD_ERR_INVALID_ARG, "nu = %g must be > 0", p->nu);
+    if (!std::isfinite(p->gamma)) return fail(MHD_ERR_INVALID_ARG, "non-finite gamma");
+    if (fluid_branch_mac(*p) && gamma_of(*p) != 1.0)
+        return fail(MHD_ERR_UNSUPPORTED, "tau = 3 nu / gamma + 1/2 = %g >= 1: the macroscopic branch has no rescaling (gamma = %g)",
+                    3.0 * p->nu / gamma_of(*p) + 0.5, gamma_of(*p));
     if (!(p->eta > 0.0)) return fail(MHD_ERR_INVALID_ARG, "eta must be > 0");
     if (p->n_mag < 1) return fail(MHD_ERR_INVALID_ARG, "n_mag must be >= 1");
     if (p->bext_kind < 0 || p->bext_kind > 3) return fail(MHD_ERR_INVALID_ARG, "unknown bext_kind %d", p->bext_kind);

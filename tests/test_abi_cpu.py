@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_the_header_layout():
     assert C.sizeof(_abi.mhd_grid_desc) == 6 * 4 + 2 * 8
-    assert C.sizeof(_abi.mhd_params) == 160  # 18 doubles + 4 int32, no padding holes
+    assert C.sizeof(_abi.mhd_params) == 168  # 19 doubles + 4 int32, no padding holes
     assert C.sizeof(_abi.mhd_budget) == 17 * 8
 
 

@@ -185,3 +185,22 @@ def test_batch_d3q27_matches_single_boxes_bitwise():
         assert_same(p, s, f"d3q27 pipe {i}")
     compare(B.pipes[0], oracle_run(spec[0][0], 2), label="batch d3q27 pipe 0")
     B.close()
+
+
+def test_batch_mixes_fluid_branches_bitwise():
+    """Plain, rescaled (gamma) and macroscopic (tau >= 1) boxes advanced by the same launches."""
+    print("case batch fluid branches", flush=True)
+    spec = batch_spec()[:4]
+    spec[0][0].params.gamma = 2.5
+    spec[1][0].params.nu = 0.3
+    spec[2][0].params.nu = 1.0 / 6.0
+    B = make_batch(spec)
+    S = make_singles(spec, [p.tiles for p in B.pipes])
+    B.step(3)
+    for s in S:
+        s.step(3)
+    for i, (p, s) in enumerate(zip(B.pipes, S)):
+        assert_same(p, s, f"branch pipe {i}")
+    for i in (0, 1):
+        compare(B.pipes[i], oracle_run(spec[i][0], 3, markers=spec[i][1]), label=f"batch branch pipe {i}")
+    B.close()

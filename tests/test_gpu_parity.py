@@ -248,6 +248,58 @@ def test_d3q27_argument_checks():
     assert e.value.status == _abi.MHD_ERR_UNSUPPORTED
 
 
+# ---------------------------------------------------------------------------------------------
+# time-step rescaling gamma (Sec. 7) and the macroscopic fluid branch for tau >= 1 (Sec. 5.7)
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(37, 21, 13), (128, 13, 9), (8, 32, 32)])
+@pytest.mark.parametrize("gamma", [0.5, 2.5])
+def test_rescaled_fluid_one_step(shape, gamma):
+    print("case gamma", gamma, shape, flush=True)
+    w = random_box(*shape, key=230, n_mag=2, nu=0.04)
+    compare(gpu_run(w, 1, gamma=gamma), oracle_run(w, 1, gamma=gamma), label=f"gamma {gamma} {shape}")
+
+
+def test_rescaled_small_pipe_40_steps():
+    w = W.small_pipe()
+    print("case gamma pipe8", flush=True)
+    compare(gpu_run(w, 40, gamma=4.0), oracle_run(w, 40, gamma=4.0), label="gamma 4 pipe8 40 steps")
+
+
+@pytest.mark.parametrize("shape", [(37, 21, 13), (128, 13, 9), (8, 32, 32), (1, 24, 1)])
+@pytest.mark.parametrize("nu", [1.0 / 6.0, 0.3, 1.0])
+def test_macroscopic_branch_one_step(shape, nu):
+    print("case mac", nu, shape, flush=True)
+    w = random_box(*shape, key=240, n_mag=2, nu=nu)
+    compare(gpu_run(w, 1), oracle_run(w, 1), label=f"mac nu {nu:.3f} {shape}")
+
+
+def test_macroscopic_branch_small_pipe_and_d3q27():
+    w = W.small_pipe()
+    print("case mac pipe8", flush=True)
+    compare(gpu_run(w, 20, nu=0.25), oracle_run(w, 20, nu=0.25), label="mac pipe8 20 steps")
+    print("case mac d3q27 pipe8", flush=True)
+    compare(gpu_run(w, 5, nu=0.25, lattice=27), oracle_run(w, 5, nu=0.25, lattice=27),
+            label="mac d3q27 pipe8 5 steps")
+
+
+def test_macroscopic_branch_split_form():
+    """The macroscopic update also refreshes the float16 copy of u that the split form's sweeps
+    read (one step from a random state: bound 2e-3 as for the plain split form)."""
+    from paper_2211_09370_amd import Sim
+
+    print("case mac split", flush=True)
+    w = random_box(37, 21, 13, key=241, n_mag=3, nu=0.4)
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], b_storage="f16split", u_scale=0.05, b_scale=0.01)
+    sim.set_markers(w.markers)
+    sim.set_params(w.params)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.step(2)
+    compare(sim, oracle_run(w, 2), tol=2e-3, label="mac split")
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)
@@ -436,7 +488,7 @@ def test_argument_checks():
     with pytest.raises(MhdError) as e:
         sim.step(1)
     assert e.value.status == _abi.MHD_ERR_STATE
-    for over, st in ((dict(nu=0.2), _abi.MHD_ERR_UNSUPPORTED), (dict(nu=0.0), _abi.MHD_ERR_INVALID_ARG),
+    for over, st in ((dict(nu=0.5, gamma=2.0), _abi.MHD_ERR_UNSUPPORTED), (dict(nu=0.0), _abi.MHD_ERR_INVALID_ARG),
                      (dict(n_mag=0), _abi.MHD_ERR_INVALID_ARG), (dict(eta=-1.0), _abi.MHD_ERR_INVALID_ARG),
                      (dict(alpha=0.4), _abi.MHD_ERR_INVALID_ARG)):
         with pytest.raises(MhdError) as e:

@@ -327,35 +327,169 @@ def test_momentum_update_adds_exactly_the_body_force(lattice):
         np.testing.assert_allclose(lhs, F.sum(axis=(1, 2, 3)), rtol=1e-12)
 
 
-def test_discrete_effect_term_converges_to_its_continuum_form():
-    # -(tau/2) sum_i e_i [F_i(x+e_i) - F_i(x-e_i)] -> -(tau - 1/2) div(u F + F u), second order.
-    nu = 0.05
-    tau = 3 * nu + 0.5
+@pytest.mark.parametrize("lattice", [19, 27])
+@pytest.mark.parametrize("gamma", [0.5, 2.0, 4.0])
+def test_rescaled_update_conserves_mass_and_adds_the_force_over_gamma(lattice, gamma):
+    # With the rescaled step dt / gamma (Sec. 7) the explicit force term is F / gamma and the
+    # gathered terms still telescope: sum rho' = sum rho, sum rho' u* - sum rho u = sum F / gamma.
+    rho, u, F = _random_state(7, 105)
+    p = oracle.make_params(7, 7, 7, nu=0.04, lattice=lattice, gamma=gamma)
+    r2, u2 = oracle.fluid(p, rho, u, F)
+    assert abs(r2.sum() - rho.sum()) <= 1e-13 * rho.sum()
+    lhs = (r2 * u2).sum(axis=(1, 2, 3)) - (rho * u).sum(axis=(1, 2, 3))
+    np.testing.assert_allclose(lhs, F.sum(axis=(1, 2, 3)) / gamma, rtol=1e-12)
+
+
+def _shear_state(n, ny, A, F0, m=1):
+    """u = (A sin k y, 0, 0), F = (F0 sin k y, 0, 0), rho = 1 on an n x ny x n box."""
+    k = 2 * np.pi * m / ny
+    s = np.sin(k * np.arange(ny))[None, :, None]
+    u = np.zeros((3, n, ny, n))
+    F = np.zeros((3, n, ny, n))
+    u[0] = A * s
+    F[0] = F0 * s
+    return np.ones((n, ny, n)), u, F, k, s
+
+
+def _march_shear(p, rho, u, F, steps):
+    for _ in range(steps):
+        rho, u = oracle.fluid(p, rho, u, F)
+    return rho, u
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+@pytest.mark.parametrize("gamma", [0.5, 1.0, 2.0, 4.0])
+def test_rescaled_shear_wave_keeps_its_steady_state_and_slows_by_gamma(lattice, gamma):
+    # Shear flow u = (A(y), 0, 0) under F = (F(y), 0, 0): within each group of directions with the
+    # same e_y the quadratic equilibrium terms and the velocity-dependent forcing terms cancel, so
+    # rho stays 1, u_y = u_z = 0, and each Fourier mode of u_x obeys
+    #   A' = r A + F0 / gamma,  r = 1 - (2 tau - 1)(1 - cos k)/3 = 1 - 2 nu (1 - cos k) / gamma
+    # (the single-step symbol with lambda = 2/3 + cos(k)/3 on both lattices). The steady amplitude
+    # F0 / (2 nu (1 - cos k)) does not depend on gamma; the approach to it is slowed by gamma.
+    oracle.set_threads(1)
+    nu, A0, F0, steps = 0.04, 0.02, 2e-5, 40
+    rho, u, F, k, s = _shear_state(3, 16, A0, F0)
+    p = oracle.make_params(3, 16, 3, nu=nu, lattice=lattice, gamma=gamma)
+    rho, u = _march_shear(p, rho, u, F, steps)
+    r = 1.0 - 2.0 * nu * (1.0 - math.cos(k)) / gamma
+    A_ss = F0 / (2.0 * nu * (1.0 - math.cos(k)))
+    A_n = A_ss + (A0 - A_ss) * r ** steps
+    np.testing.assert_allclose(u[0], A_n * np.broadcast_to(s, u[0].shape), rtol=0, atol=1e-13)
+    assert np.abs(u[1:]).max() <= 1e-14 and np.abs(rho - 1.0).max() <= 1e-14
+    oracle.set_threads(8)
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+@pytest.mark.parametrize("nu", [1.0 / 6.0, 0.3, 1.0])
+def test_macroscopic_branch_shear_wave_is_its_closed_form(lattice, nu):
+    # tau = 3 nu + 1/2 >= 1: the tau = 1 update with speed c = 6 nu (Sec. 5.7). For the same shear
+    # flow each mode obeys A' = lambda A + (1 + lambda) F0 / (2 c), lambda = 2/3 + cos(k)/3, from
+    # the gathered equilibria, the gathered GZS populations and the half-force term. The steady
+    # amplitude (1 + lambda) F0 / (2 c (1 - lambda)) tends to F0 / (nu k^2) for small k.
+    oracle.set_threads(1)
+    A0, F0, steps = 0.05, 1e-3, 30
+    rho, u, F, k, s = _shear_state(3, 24, A0, F0)
+    p = oracle.make_params(3, 24, 3, nu=nu, lattice=lattice)
+    assert oracle.fluid_tau(p) >= 1.0
+    rho, u = _march_shear(p, rho, u, F, steps)
+    c = 6.0 * nu
+    lam = 2.0 / 3.0 + math.cos(k) / 3.0
+    A_ss = (1.0 + lam) * F0 / (2.0 * c * (1.0 - lam))
+    A_n = A_ss + (A0 - A_ss) * lam ** steps
+    np.testing.assert_allclose(u[0], A_n * np.broadcast_to(s, u[0].shape), rtol=0, atol=1e-13)
+    assert np.abs(u[1:]).max() <= 1e-14 and np.abs(rho - 1.0).max() <= 1e-14
+    # the continuum limit of the steady amplitude
+    assert abs(A_ss * nu * k * k / F0 - 1.0) < 0.02
+    oracle.set_threads(8)
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
+def test_macroscopic_branch_conserves_mass_and_adds_force_times_its_step(lattice):
+    # sum_x sum_i f_i^eq(x - e_i) = sum rho and sum_i F_i = 0; sum_i c_i f_i^eq = rho u and
+    # sum_i c_i F_i = F / 2, so with the half-force term sum rho' u' - sum rho u = dt sum F,
+    # dt = 1 / (6 nu).
+    rho, u, F = _random_state(7, 106, F_mean=1e-3)
+    for nu in (0.2, 0.5):
+        p = oracle.make_params(7, 7, 7, nu=nu, lattice=lattice)
+        r2, u2 = oracle.fluid(p, rho, u, F)
+        assert abs(r2.sum() - rho.sum()) <= 1e-13 * rho.sum()
+        lhs = (r2 * u2).sum(axis=(1, 2, 3)) - (rho * u).sum(axis=(1, 2, 3))
+        np.testing.assert_allclose(lhs, F.sum(axis=(1, 2, 3)) / (6.0 * nu), rtol=1e-12)
+
+
+def test_macroscopic_branch_rejects_rescaling():
+    rho, u, F = _random_state(5, 107)
+    p = oracle.make_params(5, 5, 5, nu=0.5, gamma=2.0)  # tau = 3 nu / gamma + 1/2 = 1.25
+    r2, u2 = oracle.fluid(p, rho, u, F)
+    assert np.isnan(r2).all() and np.isnan(u2).all()
+
+
+def _smooth_fields(n):
+    h = 2 * np.pi / n
+    x = h * np.arange(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = 0.05 * np.stack([np.sin(Y + Z), np.cos(X) * np.sin(Z), np.sin(X + Y)])
+    F = 1e-3 * np.stack([np.cos(Z), np.sin(X), np.cos(Y + X)])
+    return h, u, F
+
+
+def _spectral_div(n, h, T):
+    """div of the tensor T[a][c] (row a, derivative along c), in lattice units."""
+    k = np.fft.fftfreq(n, d=1.0 / n)
+
+    def d(f, axis):
+        shape = [1, 1, 1]
+        shape[axis] = n
+        return np.real(np.fft.ifftn(1j * k.reshape(shape) * np.fft.fftn(f))) * h
+
+    axes = {0: 2, 1: 1, 2: 0}  # component index -> array axis
+    out = np.zeros((3, n, n, n))
+    for a in range(3):
+        for c in range(3):
+            out[a] += d(T[a][c], axes[c])
+    return out
+
+
+def test_rescaled_equilibrium_divides_the_momentum_flux_by_gamma():
+    # At a fixed tau (nu proportional to gamma) the rescaled update differs only by the quadratic
+    # equilibrium part divided by gamma, so without force rho' u* is affine in 1/gamma, and its
+    # slope, the gathered quadratic part, tends to -div(u u) (the Euler momentum flux) at second
+    # order.
     errs = []
     for n in (16, 32, 64):
-        h = 2 * np.pi / n
-        x = h * np.arange(n)
-        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
-        u = 0.05 * np.stack([np.sin(Y + Z), np.cos(X) * np.sin(Z), np.sin(X + Y)])
-        F = 1e-3 * np.stack([np.cos(Z), np.sin(X), np.cos(Y + X)])
+        h, u, _ = _smooth_fields(n)
         rho = np.ones((n, n, n))
-        p = oracle.make_params(n, n, n, nu=nu)
+        M = {}
+        for g in (1.0, 2.0, 4.0):
+            p = oracle.make_params(n, n, n, nu=0.05 * g, gamma=g)
+            r2, u2 = oracle.fluid(p, rho, u, np.zeros_like(u))
+            M[g] = r2 * u2
+        slope = (M[1.0] - M[2.0]) / (1.0 - 0.5)
+        np.testing.assert_allclose(M[4.0], M[2.0] - slope * (0.5 - 0.25), rtol=0, atol=1e-14)
+        cont = -_spectral_div(n, h, [[u[a] * u[c] for c in range(3)] for a in range(3)])
+        errs.append(np.abs(slope - cont).max() / np.abs(cont).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) >= 1.9, (errs, orders)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 2.5])
+def test_discrete_effect_term_converges_to_its_continuum_form(gamma):
+    # -(tau/2) sum_i e_i [F_i(x+e_i) - F_i(x-e_i)] -> -(tau - 1/2) div(u F + F u) / gamma^2,
+    # second order; tau = 3 nu / gamma + 1/2 and the rescaled F_i of Sec. 7 (its velocity terms
+    # carry 1/gamma^2).
+    nu = 0.05
+    tau = 3 * nu / gamma + 0.5
+    errs = []
+    for n in (16, 32, 64):
+        h, u, F = _smooth_fields(n)
+        rho = np.ones((n, n, n))
+        p = oracle.make_params(n, n, n, nu=nu, gamma=gamma)
         r_F, u_F = oracle.fluid(p, rho, u, F)
         r_0, u_0 = oracle.fluid(p, rho, u, np.zeros_like(F))
-        term = r_F * u_F - r_0 * u_0 - F
+        term = r_F * u_F - r_0 * u_0 - F / gamma
         # continuum value with spectral derivatives of the smooth products
-        k = np.fft.fftfreq(n, d=1.0 / n)
-        def d(f, axis):
-            # spectral derivative, converted to lattice units (dx = 1 <-> physical h)
-            shape = [1, 1, 1]
-            shape[axis] = n
-            return np.real(np.fft.ifftn(1j * k.reshape(shape) * np.fft.fftn(f))) * h
-        axes = {0: 2, 1: 1, 2: 0}  # component index -> array axis
-        cont = np.zeros_like(u)
-        for a in range(3):
-            for c in range(3):
-                cont[a] += d(u[a] * F[c] + F[a] * u[c], axes[c])
-        cont *= -(tau - 0.5)
+        cont = _spectral_div(n, h, [[u[a] * F[c] + F[a] * u[c] for c in range(3)] for a in range(3)])
+        cont *= -(tau - 0.5) / gamma**2
         errs.append(np.abs(term - cont).max() / np.abs(cont).max())
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(orders) >= 1.9, (errs, orders)

@@ -55,6 +55,7 @@ class Params:
     magnet_L: float = 0.0  # six magnets: strip half-width (<= 0: R / 6)
     magnet_D: float = 0.0  # six magnets: distance of the strips from the axis (<= 0: outside the box)
     lattice: int = 19  # 19 or 27 (the paper's D3Q27)
+    gamma: float = 1.0  # time-step rescaling of the fluid update (1: none)
 
 
 @dataclasses.dataclass

@@ -399,7 +399,6 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     using LW = Lat<Q27>;
     constexpr int HY = TY + 2;        // staged rows
     constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
-    constexpr int NR = (HY + TY - 1) / TY;  // row-load rounds per wave
     __shared__ __align__(16) float s_pl[2][6][HY * RS];
 
     const int per = gridDim.x >> 3;
@@ -437,72 +436,84 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const int xa = x0 + 2 * l;            // this lane's cells: xa, xa + 1 (always inside: nx % 128 == 0)
     const int gy = y0 + w;
     const bool own = gy < ny;
-    const float kap = a.kappa * a.u_scale;
     const float ib = a.inv_b_scale;
-    // B_ext / b_scale of this lane's pair of columns and of the two halo columns
-    const float bea[3] = {a.bext[xa] * ib, a.bext[nx + xa] * ib, a.bext[2 * nx + xa] * ib};
-    const float beb[3] = {a.bext[xa + 1] * ib, a.bext[nx + xa + 1] * ib, a.bext[2 * nx + xa + 1] * ib};
+    // Weights with omega (b terms) and kappa * u_scale * omega (flux terms) folded in: the staged
+    // flux is u_c B_a - u_a B_c in stored units, and the increment comes out already relaxed.
+    const float om = a.omega, ko = a.kappa * a.u_scale * a.omega;
+    const float b0f = LW::A0F * om, b0c = LW::A0C * om, b1f = LW::A1F * om, b1k = LW::A1K * om;
+    const float l0f = LW::A0F * ko, l0c = LW::A0C * ko, l1c = LW::A1C * ko, l1f = LW::A1F * ko, l1k = LW::A1K * ko;
+    const float w6 = (1.0f / 6.0f) * om;  // total weight of a neighbouring plane (both lattices)
 
-    // row loads: round r stages row hy = w + r * TY (if < HY) at columns xa, xa + 1
-    unsigned rowoff[NR];
-    int rowy[NR];
-    bool rowval[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int hy = w + r * TY;
-        rowval[r] = hy < HY;
-        rowy[r] = wrapi(y0 - 1 + hy, ny);
-        rowoff[r] = (unsigned)(xa + nx * rowy[r]);
-    }
-    // halo columns: lanes 0 .. 2*HY-1 of the last wave, lane -> (row hy = lane / 2, side)
+    // Staging: wave w stages row hy = w (its own pair of cells per lane); the two remaining rows
+    // hy = TY, TY + 1 are staged one cell per lane by waves 0 .. 3 (lane -> x = 64 (w & 1) + l),
+    // so the staging work is the same on every wave; lanes 0 .. 2*HY-1 of the last wave stage the
+    // halo columns x0 - 1 and x0 + 128.
+    const int pyr = wrapi(y0 - 1 + w, ny);
+    const unsigned poff = (unsigned)(xa + nx * pyr);
+    const bool sval = w < 4;
+    const int shy = TY + (w >> 1), sxl = ((w & 1) << 6) + l;
+    const int syr = wrapi(y0 - 1 + shy, ny);
+    const unsigned soff = (unsigned)(x0 + sxl + nx * syr);
+    const int sidx = shy * RS + 1 + sxl;
     const bool hval = (w == TY - 1) && (l < 2 * HY);
     const int hhy = l >> 1, hside = l & 1;
     const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
     const int hyg = wrapi(y0 - 1 + min(hhy, HY - 1), ny);
     const unsigned hoff = (unsigned)(hx + nx * hyg);
     const int hidx = min(hhy, HY - 1) * RS + (hside ? 129 : 0);
+    // B_ext / b_scale of the staged columns
+    const float bea[3] = {a.bext[xa] * ib, a.bext[nx + xa] * ib, a.bext[2 * nx + xa] * ib};
+    const float beb[3] = {a.bext[xa + 1] * ib, a.bext[nx + xa + 1] * ib, a.bext[2 * nx + xa + 1] * ib};
+    const int xs = x0 + sxl;
+    const float bes[3] = {a.bext[xs] * ib, a.bext[nx + xs] * ib, a.bext[2 * nx + xs] * ib};
     const float hbe[3] = {a.bext[hx] * ib, a.bext[nx + hx] * ib, a.bext[2 * nx + hx] * ib};
 
-    RU ru[NR][3];
-    RB rb[NR][3];
-    RB rq[NR][3];  // SPLIT: hi part of the rows
+    RU ru[3];
+    RB rb[3], rq[3];        // pair row (rq: SPLIT hi part)
+    TU su[3];
+    TB sb[3], sq[3];        // single cell
     TU hu[3];
-    TB hb[3];
-    TB hq[3];      // SPLIT: hi part of the halo column
-    float rt[NR][3], ht[3];  // BYZ: B_ext (y, z) part of the next plane's rows and halo column
+    TB hb[3], hq[3];        // halo column
+    float tp[3], ts[3], th[3];  // BYZ: B_ext (y, z) part at the pair row, single cell, halo column
     const unsigned pyz = (unsigned)ny * nz;
     auto load_plane = [&](int p) {
-        const unsigned off = (unsigned)wrapi(p, nz) * plane;
+        const int zz = wrapi(p, nz);
+        const unsigned off = (unsigned)zz * plane;
         if constexpr (BYZ) {
-            const int zz = wrapi(p, nz);
+            const unsigned op = (unsigned)(pyr + ny * zz), os = (unsigned)(syr + ny * zz), oh = (unsigned)(hyg + ny * zz);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const unsigned o = (unsigned)(rowy[r] + ny * zz);
-                rt[r][0] = a.bext_yz[o];
-                rt[r][1] = a.bext_yz[pyz + o];
-                rt[r][2] = a.bext_yz[2 * pyz + o];
+            for (int q = 0; q < 3; ++q) {
+                tp[q] = a.bext_yz[q * pyz + op];
+                ts[q] = a.bext_yz[q * pyz + os];
+                th[q] = a.bext_yz[q * pyz + oh];
             }
-            const unsigned o = (unsigned)(hyg + ny * zz);
-            ht[0] = a.bext_yz[o];
-            ht[1] = a.bext_yz[pyz + o];
-            ht[2] = a.bext_yz[2 * pyz + o];
         }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (rowval[r]) {
-                const unsigned ku = (off + rowoff[r]) * (unsigned)sizeof(TU);
-                const unsigned kb = (off + rowoff[r]) * (unsigned)sizeof(TB);
-                ru[r][0] = ld_off(reinterpret_cast<const RU *>(u0), ku);
-                ru[r][1] = ld_off(reinterpret_cast<const RU *>(u1), ku);
-                ru[r][2] = ld_off(reinterpret_cast<const RU *>(u2), ku);
-                rb[r][0] = ld_off(reinterpret_cast<const RB *>(b0), kb);
-                rb[r][1] = ld_off(reinterpret_cast<const RB *>(b1), kb);
-                rb[r][2] = ld_off(reinterpret_cast<const RB *>(b2), kb);
-                if constexpr (SPLIT) {
-                    rq[r][0] = ld_off(reinterpret_cast<const RB *>(bh0), kb);
-                    rq[r][1] = ld_off(reinterpret_cast<const RB *>(bh1), kb);
-                    rq[r][2] = ld_off(reinterpret_cast<const RB *>(bh2), kb);
-                }
+        {
+            const unsigned ku = (off + poff) * (unsigned)sizeof(TU), kb = (off + poff) * (unsigned)sizeof(TB);
+            ru[0] = ld_off(reinterpret_cast<const RU *>(u0), ku);
+            ru[1] = ld_off(reinterpret_cast<const RU *>(u1), ku);
+            ru[2] = ld_off(reinterpret_cast<const RU *>(u2), ku);
+            rb[0] = ld_off(reinterpret_cast<const RB *>(b0), kb);
+            rb[1] = ld_off(reinterpret_cast<const RB *>(b1), kb);
+            rb[2] = ld_off(reinterpret_cast<const RB *>(b2), kb);
+            if constexpr (SPLIT) {
+                rq[0] = ld_off(reinterpret_cast<const RB *>(bh0), kb);
+                rq[1] = ld_off(reinterpret_cast<const RB *>(bh1), kb);
+                rq[2] = ld_off(reinterpret_cast<const RB *>(bh2), kb);
+            }
+        }
+        if (sval) {
+            const unsigned ku = (off + soff) * (unsigned)sizeof(TU), kb = (off + soff) * (unsigned)sizeof(TB);
+            su[0] = ld_off(u0, ku);
+            su[1] = ld_off(u1, ku);
+            su[2] = ld_off(u2, ku);
+            sb[0] = ld_off(b0, kb);
+            sb[1] = ld_off(b1, kb);
+            sb[2] = ld_off(b2, kb);
+            if constexpr (SPLIT) {
+                sq[0] = ld_off(bh0, kb);
+                sq[1] = ld_off(bh1, kb);
+                sq[2] = ld_off(bh2, kb);
             }
         }
         if (hval) {
@@ -520,66 +531,69 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
             }
         }
     };
+    // staged: b (stored units) and the flux u_c B_a - u_a B_c with B = b + B_ext
     auto put = [&](int buf, int idx, float bx, float by, float bz, float ux, float uy, float uz, const float *be) {
         const float Bx = bx + be[0], By = by + be[1], Bz = bz + be[2];
         s_pl[buf][0][idx] = bx;
         s_pl[buf][1][idx] = by;
         s_pl[buf][2][idx] = bz;
-        s_pl[buf][3][idx] = kap * (uy * Bx - ux * By);
-        s_pl[buf][4][idx] = kap * (uz * Bx - ux * Bz);
-        s_pl[buf][5][idx] = kap * (uz * By - uy * Bz);
+        s_pl[buf][3][idx] = uy * Bx - ux * By;
+        s_pl[buf][4][idx] = uz * Bx - ux * Bz;
+        s_pl[buf][5][idx] = uz * By - uy * Bz;
     };
     auto stage = [&](auto bufc) {
         constexpr int S = decltype(bufc)::value;
+        constexpr float us = 1.0f, bs = 1.0f;  // stored units
+        {
+            float b[2][3];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (rowval[r]) {
-                const int idx = (w + r * TY) * RS + 1 + 2 * l;
-                constexpr float us = 1.0f, bs = 1.0f;  // stored units
-                float b[2][3];
+            for (int q = 0; q < 3; ++q) {
+                b[0][q] = PB::lo(rb[q], bs);
+                b[1][q] = PB::hi(rb[q], bs);
+                if constexpr (SPLIT) {
+                    b[0][q] += PB::lo(rq[q], bs);
+                    b[1][q] += PB::hi(rq[q], bs);
+                }
+            }
+            float ea[3] = {bea[0], bea[1], bea[2]}, eb[3] = {beb[0], beb[1], beb[2]};
+            if constexpr (BYZ) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    b[0][q] = PB::lo(rb[r][q], bs);
-                    b[1][q] = PB::hi(rb[r][q], bs);
-                    if constexpr (SPLIT) {
-                        b[0][q] += PB::lo(rq[r][q], bs);
-                        b[1][q] += PB::hi(rq[r][q], bs);
-                    }
+                    ea[q] += tp[q] * ib;
+                    eb[q] += tp[q] * ib;
                 }
-                float ea[3] = {bea[0], bea[1], bea[2]}, eb[3] = {beb[0], beb[1], beb[2]};
-                if constexpr (BYZ) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        ea[q] += rt[r][q] * ib;
-                        eb[q] += rt[r][q] * ib;
-                    }
-                }
-                put(S, idx, b[0][0], b[0][1], b[0][2], PU::lo(ru[r][0], us), PU::lo(ru[r][1], us),
-                    PU::lo(ru[r][2], us), ea);
-                put(S, idx + 1, b[1][0], b[1][1], b[1][2], PU::hi(ru[r][0], us), PU::hi(ru[r][1], us),
-                    PU::hi(ru[r][2], us), eb);
             }
+            const int idx = w * RS + 1 + 2 * l;
+            put(S, idx, b[0][0], b[0][1], b[0][2], PU::lo(ru[0], us), PU::lo(ru[1], us), PU::lo(ru[2], us), ea);
+            put(S, idx + 1, b[1][0], b[1][1], b[1][2], PU::hi(ru[0], us), PU::hi(ru[1], us), PU::hi(ru[2], us), eb);
+        }
+        if (sval) {
+            float b[3], e[3] = {bes[0], bes[1], bes[2]};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                b[q] = St<TB>::cvt(sb[q]);
+                if constexpr (SPLIT) b[q] += St<TB>::cvt(sq[q]);
+                if constexpr (BYZ) e[q] += ts[q] * ib;
+            }
+            put(S, sidx, b[0], b[1], b[2], St<TU>::cvt(su[0]), St<TU>::cvt(su[1]), St<TU>::cvt(su[2]), e);
         }
         if (hval) {
-            float b[3];
+            float b[3], e[3] = {hbe[0], hbe[1], hbe[2]};
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 b[q] = St<TB>::cvt(hb[q]);
                 if constexpr (SPLIT) b[q] += St<TB>::cvt(hq[q]);
+                if constexpr (BYZ) e[q] += th[q] * ib;
             }
-            float eh[3] = {hbe[0], hbe[1], hbe[2]};
-            if constexpr (BYZ) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) eh[q] += ht[q] * ib;
-            }
-            put(S, hidx, b[0], b[1], b[2], St<TU>::cvt(hu[0]), St<TU>::cvt(hu[1]), St<TU>::cvt(hu[2]), eh);
+            put(S, hidx, b[0], b[1], b[2], St<TU>::cvt(hu[0]), St<TU>::cvt(hu[1]), St<TU>::cvt(hu[2]), e);
         }
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
 
-    constexpr float W6 = 1.0f / 6.0f;
-    float acc[2][3] = {}, ap[2][3] = {}, cm[2][3] = {}, cc[2][3] = {};
+    // rolling state of the march, per cell and component: acc = A(p-2) + B(p-1) (the output at
+    // p-1 without its C(p) part), ap = A(p-1), cc = b(p-1) at the centre, dz = b(p-1) - b(p-2)
+    float acc[2][3] = {}, ap[2][3] = {}, cc[2][3] = {}, dz[2][3] = {};
 
     load_plane(z0 - 1);
     stage(I0{});
@@ -593,24 +607,26 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
             if (p + 2 <= z1) load_plane(p + 2);
         }
         // SPLIT: stored lo (and, re-splitting, hi) of the output pair, requested now
-        const unsigned ko = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);
+        const unsigned ko_ = ((unsigned)(p - 1) * plane + (unsigned)(xa + nx * gy)) * (unsigned)sizeof(TB);
         RB lc[3], hc[3];
         if constexpr (SPLIT) {
             if (own && p >= z0 + 1) {
-                lc[0] = ld_off(reinterpret_cast<const RB *>(b0), ko);
-                lc[1] = ld_off(reinterpret_cast<const RB *>(b1), ko);
-                lc[2] = ld_off(reinterpret_cast<const RB *>(b2), ko);
+                lc[0] = ld_off(reinterpret_cast<const RB *>(b0), ko_);
+                lc[1] = ld_off(reinterpret_cast<const RB *>(b1), ko_);
+                lc[2] = ld_off(reinterpret_cast<const RB *>(b2), ko_);
                 if (resplit) {
-                    hc[0] = ld_off(reinterpret_cast<const RB *>(bh0), ko);
-                    hc[1] = ld_off(reinterpret_cast<const RB *>(bh1), ko);
-                    hc[2] = ld_off(reinterpret_cast<const RB *>(bh2), ko);
+                    hc[0] = ld_off(reinterpret_cast<const RB *>(bh0), ko_);
+                    hc[1] = ld_off(reinterpret_cast<const RB *>(bh1), ko_);
+                    hc[2] = ld_off(reinterpret_cast<const RB *>(bh2), ko_);
                 }
             }
         }
         if (own) {
-            // per field: rows y-1, y, y+1 at columns xa-1 .. xa+2 (two aligned 8-byte reads per
-            // row), reduced at once into the plane terms of both cells
-            float A[2][3], B[2][3], C[2][2], cen[2][3];
+            // Plane p's contributions to the outputs at p+1 (A = S + P), p (B) and p-1
+            // (C = S - P) of both cells: S and B collect the in-plane sums, P the flux through
+            // the planes (components x, y; zero for z, so A = C there).
+            float S[2][3], B[2][3], Pz[2][2], cen[2][3];
+            // rows y-1, y, y+1 of a field at columns xa-1 .. xa+2 (two aligned 8-byte reads per row)
             auto rows = [&](int k, float (&v)[3][4]) {
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
@@ -623,108 +639,111 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                     v[r][3] = hi.y;
                 }
             };
-            {  // b components
+            // b components: face and corner sums of differences to each centre, taken against
+            // the first centre r0 and shifted by 4 (c1 - r0) for the second cell; the column
+            // sums t_j of rows y-1 and y+1 serve both cells
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
                 float v[3][4];
+                rows(k, v);
+                const float r0 = v[1][1];
+                float d[3][4];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    rows(k, v);
+                for (int r = 0; r < 3; ++r)
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const float c = v[1][1 + e];
-                        const float fs = ((v[1][e] - c) + (v[1][e + 2] - c)) + ((v[0][1 + e] - c) + (v[2][1 + e] - c));
-                        const float cs = ((v[0][e] - c) + (v[0][e + 2] - c)) + ((v[2][e] - c) + (v[2][e + 2] - c));
-                        const float dP0 = LW::A0F * fs + LW::A0C * cs;
-                        float dP1 = LW::A1F * fs;
-                        if constexpr (Q27) dP1 += LW::A1K * cs;
-                        cen[e][k] = c;
-                        A[e][k] = dP1;
-                        B[e][k] = dP0;
-                        if (k < 2) C[e][k] = dP1;
-                    }
+                    for (int j = 0; j < 4; ++j) d[r][j] = v[r][j] - r0;
+                const float dl = d[1][2];  // c1 - c0
+                const float t0 = d[0][0] + d[2][0], t1 = d[0][1] + d[2][1], t2 = d[0][2] + d[2][2],
+                            t3 = d[0][3] + d[2][3];
+                const float fs0 = (d[1][0] + dl) + t1, cs0 = t0 + t2;
+                const float fs1 = fmaf(-4.0f, dl, d[1][3] + t2), cs1 = fmaf(-4.0f, dl, t1 + t3);
+                cen[0][k] = r0;
+                cen[1][k] = v[1][2];
+                B[0][k] = fmaf(b0c, cs0, b0f * fs0);
+                B[1][k] = fmaf(b0c, cs1, b0f * fs1);
+                S[0][k] = b1f * fs0;
+                S[1][k] = b1f * fs1;
+                if constexpr (Q27) {
+                    S[0][k] = fmaf(b1k, cs0, S[0][k]);
+                    S[1][k] = fmaf(b1k, cs1, S[1][k]);
                 }
             }
-            {  // kappa Lam_xy: Q0x, Q1x, Q0y, Q1y
+            {  // flux xy: in-plane differences along x (component y) and along y (component x)
                 float v[3][4];
                 rows(3, v);
+                float q[4], s[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    q[j] = v[0][j] - v[2][j];
+                    s[j] = v[0][j] + v[2][j];
+                }
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    const float dx = v[1][e] - v[1][e + 2], dy = v[0][1 + e] - v[2][1 + e];
-                    const float cdx = (v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]);
-                    const float cdy = (v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]);
-                    const float Q0x = LW::A0F * dx + LW::A0C * cdx;
-                    float Q1x = LW::A1F * dx;
-                    const float Q0y = LW::A0F * dy + LW::A0C * cdy;
-                    float Q1y = LW::A1F * dy;
+                    const float dx = v[1][e] - v[1][e + 2], cdx = s[e] - s[e + 2];
+                    const float dy = q[1 + e], cdy = q[e] + q[e + 2];
+                    B[e][0] = fmaf(l0c, cdy, fmaf(l0f, dy, B[e][0]));
+                    S[e][0] = fmaf(l1f, dy, S[e][0]);
+                    B[e][1] = fmaf(-l0c, cdx, fmaf(-l0f, dx, B[e][1]));
+                    S[e][1] = fmaf(-l1f, dx, S[e][1]);
                     if constexpr (Q27) {
-                        Q1x += LW::A1K * cdx;
-                        Q1y += LW::A1K * cdy;
+                        S[e][0] = fmaf(l1k, cdy, S[e][0]);
+                        S[e][1] = fmaf(-l1k, cdx, S[e][1]);
                     }
-                    A[e][0] += Q1y;
-                    B[e][0] += Q0y;
-                    C[e][0] += Q1y;
-                    A[e][1] -= Q1x;
-                    B[e][1] -= Q0x;
-                    C[e][1] -= Q1x;
                 }
             }
-            {  // kappa Lam_xz: P1, Q0x, Q1x
+            {  // flux xz: through-plane sum (component x) and differences along x (component z)
                 float v[3][4];
                 rows(4, v);
+                float s[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s[j] = v[0][j] + v[2][j];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    const float dx = v[1][e] - v[1][e + 2];
-                    const float cdx = (v[0][e] - v[0][e + 2]) + (v[2][e] - v[2][e + 2]);
-                    float P1 = LW::A1C * v[1][1 + e] + LW::A1F * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
-                    const float Q0x = LW::A0F * dx + LW::A0C * cdx;
-                    float Q1x = LW::A1F * dx;
-                    if constexpr (Q27) {
-                        P1 += LW::A1K * ((v[0][e] + v[0][e + 2]) + (v[2][e] + v[2][e + 2]));
-                        Q1x += LW::A1K * cdx;
-                    }
-                    A[e][0] += P1;
-                    C[e][0] -= P1;
-                    A[e][2] -= Q1x;
-                    B[e][2] -= Q0x;
+                    const float dx = v[1][e] - v[1][e + 2], cdx = s[e] - s[e + 2];
+                    float pz = fmaf(l1c, v[1][1 + e], l1f * ((v[1][e] + v[1][e + 2]) + s[1 + e]));
+                    if constexpr (Q27) pz = fmaf(l1k, s[e] + s[e + 2], pz);
+                    Pz[e][0] = pz;
+                    B[e][2] = fmaf(-l0c, cdx, fmaf(-l0f, dx, B[e][2]));
+                    S[e][2] = fmaf(-l1f, dx, S[e][2]);
+                    if constexpr (Q27) S[e][2] = fmaf(-l1k, cdx, S[e][2]);
                 }
             }
-            {  // kappa Lam_yz: P1, Q0y, Q1y
+            {  // flux yz: through-plane sum (component y) and differences along y (component z)
                 float v[3][4];
                 rows(5, v);
+                float q[4], s[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    q[j] = v[0][j] - v[2][j];
+                    s[j] = v[0][j] + v[2][j];
+                }
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    const float dy = v[0][1 + e] - v[2][1 + e];
-                    const float cdy = (v[0][e] - v[2][e]) + (v[0][e + 2] - v[2][e + 2]);
-                    float P1 = LW::A1C * v[1][1 + e] + LW::A1F * ((v[1][e] + v[1][e + 2]) + (v[0][1 + e] + v[2][1 + e]));
-                    const float Q0y = LW::A0F * dy + LW::A0C * cdy;
-                    float Q1y = LW::A1F * dy;
-                    if constexpr (Q27) {
-                        P1 += LW::A1K * ((v[0][e] + v[0][e + 2]) + (v[2][e] + v[2][e + 2]));
-                        Q1y += LW::A1K * cdy;
-                    }
-                    A[e][1] += P1;
-                    C[e][1] -= P1;
-                    A[e][2] -= Q1y;
-                    B[e][2] -= Q0y;
+                    const float dy = q[1 + e], cdy = q[e] + q[e + 2];
+                    float pz = fmaf(l1c, v[1][1 + e], l1f * ((v[1][e] + v[1][e + 2]) + s[1 + e]));
+                    if constexpr (Q27) pz = fmaf(l1k, s[e] + s[e + 2], pz);
+                    Pz[e][1] = pz;
+                    B[e][2] = fmaf(-l0c, cdy, fmaf(-l0f, dy, B[e][2]));
+                    S[e][2] = fmaf(-l1f, dy, S[e][2]);
+                    if constexpr (Q27) S[e][2] = fmaf(-l1k, cdy, S[e][2]);
                 }
             }
             float out[2][3];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                // output plane p-1: b* = b_c + increment (differences only); C2 = A2
-                out[e][0] = a.omega * ((acc[e][0] + C[e][0]) + W6 * ((cm[e][0] - cc[e][0]) + (cen[e][0] - cc[e][0])));
-                out[e][1] = a.omega * ((acc[e][1] + C[e][1]) + W6 * ((cm[e][1] - cc[e][1]) + (cen[e][1] - cc[e][1])));
-                out[e][2] = a.omega * ((acc[e][2] + A[e][2]) + W6 * ((cm[e][2] - cc[e][2]) + (cen[e][2] - cc[e][2])));
-                if constexpr (!SPLIT) {
-                    out[e][0] += cc[e][0];
-                    out[e][1] += cc[e][1];
-                    out[e][2] += cc[e][2];
-                }
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    acc[e][q] = ap[e][q] + B[e][q];
-                    ap[e][q] = A[e][q];
-                    cm[e][q] = cc[e][q];
-                    cc[e][q] = cen[e][q];
+                for (int k = 0; k < 3; ++k) {
+                    // output plane p-1: b* = b_c + increment, the increment built from
+                    // differences only; C = S - P (P = 0 for z)
+                    const float Ck = k < 2 ? S[e][k] - Pz[e][k] : S[e][k];
+                    const float dzc = cen[e][k] - cc[e][k];  // b(p) - b(p-1)
+                    out[e][k] = fmaf(w6, dzc - dz[e][k], acc[e][k] + Ck);
+                    if constexpr (!SPLIT) out[e][k] += cc[e][k];
+                    const float Ak = k < 2 ? S[e][k] + Pz[e][k] : S[e][k];
+                    acc[e][k] = ap[e][k] + B[e][k];
+                    ap[e][k] = Ak;
+                    cc[e][k] = cen[e][k];
+                    dz[e][k] = dzc;
                 }
             }
             if (p >= z0 + 1) {
@@ -740,16 +759,16 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                             const float v0 = (PB::lo(hc[q], bs) + l0) + out[0][q];
                             const float v1 = (PB::hi(hc[q], bs) + l1) + out[1][q];
                             const RB hn = PB::make(v0, v1, inv);
-                            st_off(ho + q * (size_t)(N / 2), ko, hn);
-                            st_off(oo[q], ko, PB::make(v0 - PB::lo(hn, bs), v1 - PB::hi(hn, bs), inv));
+                            st_off(ho + q * (size_t)(N / 2), ko_, hn);
+                            st_off(oo[q], ko_, PB::make(v0 - PB::lo(hn, bs), v1 - PB::hi(hn, bs), inv));
                         } else {
-                            st_off(oo[q], ko, PB::make(l0 + out[0][q], l1 + out[1][q], inv));
+                            st_off(oo[q], ko_, PB::make(l0 + out[0][q], l1 + out[1][q], inv));
                         }
                     }
                 } else {
-                    st_off(oo[0], ko, PB::make(out[0][0], out[1][0], 1.0f));
-                    st_off(oo[1], ko, PB::make(out[0][1], out[1][1], 1.0f));
-                    st_off(oo[2], ko, PB::make(out[0][2], out[1][2], 1.0f));
+                    st_off(oo[0], ko_, PB::make(out[0][0], out[1][0], 1.0f));
+                    st_off(oo[1], ko_, PB::make(out[0][1], out[1][1], 1.0f));
+                    st_off(oo[2], ko_, PB::make(out[0][2], out[1][2], 1.0f));
                 }
             }
         }

@@ -1,0 +1,109 @@
+"""Full-size configurations on the GPU, checked at sampled cells against the oracle.
+
+The oracle cannot step a 512 x 256 x 256 box or the 60-million-cell 64-pipe batch, but one step
+is local (tests/subbox.py, pinned in tests/test_subbox_cpu.py): at a sampled cell the oracle run
+on a small box cut around it gives the whole-box value. The GPU runs the whole box in the
+launch configuration the benchmark times (default tiles, graphs for the batch) with two
+sweeps per step (the sweep count only repeats the same launches), then the sampled cells are
+compared: near and on the wall, on the axis, at tile and box edges, at the periodic seams.
+Bars: the float32 bar 1e-5 of each field's maximum; the split form's one-step bar 2e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.subbox import influence_radius, oracle_cell
+
+pytestmark = pytest.mark.gpu
+
+N_MAG = 2
+
+
+def _sample_cells(w, n, key, margin_x=0):
+    g = W.rng_for(key)
+    yc, zc, R = int(w.params.yc), int(w.params.zc), w.R
+    lo, hi = margin_x, w.nx - 1 - margin_x
+    cells = [(lo, yc, zc), (hi, yc, zc), ((lo + hi) // 2, yc, zc), ((lo + hi) // 2, 0, 0),
+             (min(hi, max(lo, 127)), min(w.ny - 1, yc + 4), zc)]
+    for k in range(n):
+        th = g.uniform(0, 2 * math.pi)
+        rr = R + g.uniform(-2.5, 2.5) if k % 2 == 0 else g.uniform(0, R)
+        cx = int(g.integers(lo, hi + 1))
+        cy = int(round(yc + rr * math.cos(th))) % w.ny
+        cz = int(round(zc + rr * math.sin(th))) % w.nz
+        cells.append((cx, cy, cz))
+    return cells
+
+
+def _compare_cells(label, w, fields, cells, tol, **over):
+    rho, u, b = fields
+    us, bs = np.abs(u).max(), np.abs(b).max()
+    rs = max(np.abs(rho - 1.0).max(), math.sqrt(3.0) * us)
+    worst = [0.0, 0.0, 0.0]
+    for (cx, cy, cz) in cells:
+        r_o, u_o, b_o = oracle_cell(w, (cx, cy, cz), N_MAG, **over)
+        worst[0] = max(worst[0], abs(rho[cz, cy, cx] - r_o) / rs)
+        worst[1] = max(worst[1], np.abs(u[:, cz, cy, cx] - u_o).max() / us)
+        worst[2] = max(worst[2], np.abs(b[:, cz, cy, cx] - b_o).max() / bs)
+    print(f"{label}: {len(cells)} cells, err rho-1 {worst[0]:.2e} u {worst[1]:.2e} b {worst[2]:.2e}", flush=True)
+    assert max(worst) <= tol, (label, worst)
+
+
+def _large():
+    return W.large_pipe(Rm=1e-2, noise=1e-2, rho_amp=1e-3, b_amp=1e-3)
+
+
+@pytest.mark.parametrize("form", ["f32", "f16split"])
+def test_large_pipe_full_size_sampled_cells(form):
+    from paper_2211_09370_amd import Sim
+
+    w = _large()
+    print("case large pipe", form, w.nx, w.ny, w.nz, flush=True)
+    store = {} if form == "f32" else dict(b_storage="f16split", u_scale=W.U0, b_scale=1e-2 * w.params.B0)
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], **store)
+    sim.set_markers(w.markers)
+    sim.set_params(w.params, n_mag=N_MAG)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    print("tiles", tuple(sim.tiles), flush=True)
+    sim.step(1)
+    fields = (sim.get_field("rho"), sim.get_field("u"), sim.get_field("b"))
+    sim.close()
+    assert all(np.isfinite(f).all() for f in fields)
+    cells = _sample_cells(w, 24, key=600)
+    _compare_cells(f"large {form}", w, fields, cells, 1e-5 if form == "f32" else 2e-3)
+
+
+def test_batch_64_pipes_full_size_sampled_cells():
+    from paper_2211_09370_amd import Batch
+
+    pipes = W.batch_pipes(noise=1e-2)
+    print("case batch 64 pipes", sum(w.nx * w.ny * w.nz for w in pipes), "cells", flush=True)
+    B = Batch([(w.nx, w.ny, w.nz, w.markers.shape[1]) for w in pipes])
+    for p, w in zip(B.pipes, pipes):
+        rho, u, b = W.batch_fields(w)
+        p.set_markers(w.markers)
+        p.set_params(w.params, n_mag=N_MAG)
+        p.set_field("rho", rho)
+        p.set_field("u", u)
+        p.set_field("b", b)
+    B.step(1)  # graphs
+    r = influence_radius(N_MAG) + 3
+    checked = 0
+    for i in range(0, len(pipes), 4):  # every fourth pipe: uniform and fringe fields, all lengths
+        w = pipes[i]
+        w.rho, w.u, w.b = W.batch_fields(w)
+        margin = r if w.params.bext_kind == W.BEXT_TANH_FRINGE_Y else 0
+        if w.nx - 1 - 2 * margin < 0:
+            continue
+        p = B.pipes[i]
+        fields = (p.get_field("rho"), p.get_field("u"), p.get_field("b"))
+        assert all(np.isfinite(f).all() for f in fields)
+        _compare_cells(f"batch pipe {i} ({w.nx}x{w.ny}x{w.nz}, kind {w.params.bext_kind})", w, fields,
+                       _sample_cells(w, 4, key=700 + i, margin_x=margin), 1e-5)
+        checked += 1
+    B.close()
+    assert checked >= 10

@@ -12,14 +12,17 @@ roofline = the magnetic sweep kernel (the dominant one): 36 algorithmic bytes pe
 cpu_baseline = the FP64 oracle on this host, timed on a bounded sample of the same workload.
 batched = the batched form on 64 independent pipes of uneven size and physics (~74 M cells,
 ~2.3 M markers, tiles autotuned), MLUPS over all their cells (an extra object, not `value`).
+accelerated = the accelerated magnetic iteration (alpha = 1/2, 135 sweeps) on the same box, with the
+induction residual after a step next to the plain method's (an extra object, not `value`).
 precision = float32 against the split float16 form (b in float16 hi + lo, float16 copy of u for
 the sweeps) on the 512 x 256 x 256 pipe at 270 sweeps per step, with the split form's per-field
 error against the stored FP64 oracle run of the 8 x 32 x 32 pipe after 2000 steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-precision]
+                       [--no-accel]
 HBM traffic of the sweep (rocprofv3 counters, scaled by a plain copy of known size):
   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --steps 1 \
-      --warmup 0 --profile-steps 1 --no-cpu --no-batch --no-precision --calib-copy-mib 1024
+      --warmup 0 --profile-steps 1 --no-cpu --no-batch --no-precision --no-accel --calib-copy-mib 1024
   (the same with WRITE_SIZE into D2), then
   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib 1024
 """
@@ -104,7 +107,7 @@ def traffic_summary(fetch_dir, write_dir, copy_mib):
         "# dispatches), each scaled by the ratio of the known size of a plain torch copy to what the",
         "# same counter reads for it. Commands:",
         f"#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --steps 1 "
-        f"--warmup 0 --profile-steps 1 --no-cpu --no-batch --no-precision --calib-copy-mib {copy_mib}",
+        f"--warmup 0 --profile-steps 1 --no-cpu --no-batch --no-precision --no-accel --calib-copy-mib {copy_mib}",
         "#   (the same with --pmc WRITE_SIZE into D2)",
         f"#   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib {copy_mib}",
         f"fetch_kib_raw = {out['fetch']['raw_kib']:.1f}",
@@ -221,6 +224,38 @@ def precision_leg(steps, with_error=True):
     return out
 
 
+def accelerated_leg(w, steps, warmup, res_plain):
+    """MLUPS of the accelerated iteration (Sec. 5.8: alpha = 1/2 with half the sweeps, the same
+    fixed point and the same error of the slow modes as the plain iteration with all of them) on
+    the headline box, with the induction residual after the next step next to the plain run's,
+    both after the same number of steps from the same state."""
+    import torch
+
+    from paper_2211_09370_amd import Sim
+
+    n_mag = (w.params.n_mag + 1) // 2
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+    sim.set_markers(w.markers)
+    sim.set_params(w.params, alpha=0.5, n_mag=n_mag)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    sim.step(1, 1)
+    res = sim.budgets()[-1]["res_mag"]
+    sim.close()
+    log(f"bench: accelerated alpha 1/2, {n_mag} sweeps: {steps} steps in {sec:.3f} s, res_mag {res:.3e} "
+        f"(plain {res_plain:.3e})")
+    return {"method": "accelerated magnetic iteration, alpha = 1/2 (Sec. 5.8)", "n_mag": n_mag, "steps": steps,
+            "value": round(w.n_cells * steps / sec / 1e6, 3), "unit": "MLUPS",
+            "res_mag_after_step": res, "res_mag_after_step_plain_270": res_plain}
+
+
 def cpu_baseline(w):
     """Oracle on the full 128^3 workload: one fluid step with 2 and one with 32 sweeps give the
     cost of a sweep and of the rest of a step; MLUPS is then scaled to 270 sweeps per step."""
@@ -256,6 +291,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-accel", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=3)
     ap.add_argument("--no-precision-error", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -326,7 +362,13 @@ def main():
     import numpy as np
 
     state_ok = bool(np.isfinite(sim.get_field("u")).all())
+    accel = None
+    if not args.no_accel:
+        sim.step(1, 1)  # one recorded step: the induction residual left by 270 plain sweeps
+        res_plain = sim.budgets()[-1]["res_mag"]
     sim.close()
+    if not args.no_accel:
+        accel = accelerated_leg(w, args.steps, args.warmup + args.profile_steps, res_plain)
 
     batched = None
     if not args.no_batch:
@@ -362,6 +404,7 @@ def main():
                      "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes},
         "sweep_glups": round(w.n_cells * (w.params.n_mag + 1) * args.steps / sec / 1e9, 3),
         "finite": state_ok,
+        "accelerated": accel,
         "batched": batched,
         "precision": precision,
         "cpu_baseline": cpu,

@@ -11,7 +11,6 @@
 #include <map>
 #include <new>
 #include <string>
-#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -608,15 +607,27 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
                 }
         tptr[j + 1] = (int)tcell.size();
     }
-    // 2. row sums d_j = sum_k D_jk (sum_i D_ik)
-    std::unordered_map<int, double> S;
-    S.reserve(tcell.size() * 2);
-    for (size_t t = 0; t < tcell.size(); ++t) S[tcell[t]] += tw[t];
+    // 2. row sums d_j = sum_k D_jk (sum_i D_ik): the taps grouped by cell with a stable sort
+    //    (each cell's weights summed in tap order), the cell sum handed back to every tap
+    const size_t T = tcell.size();
     std::vector<double> d0((size_t)M);
-    for (int64_t j = 0; j < M; ++j) {
-        double acc = 0.0;
-        for (int t = tptr[j]; t < tptr[j + 1]; ++t) acc += tw[t] * S[tcell[t]];
-        d0[j] = acc;
+    {
+        std::vector<uint32_t> ord(T);
+        for (size_t t = 0; t < T; ++t) ord[t] = (uint32_t)t;
+        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return tcell[a] < tcell[b]; });
+        std::vector<double> Stap(T);
+        for (size_t a = 0; a < T;) {
+            size_t b = a;
+            double acc = 0.0;
+            while (b < T && tcell[ord[b]] == tcell[ord[a]]) acc += tw[ord[b++]];
+            for (size_t k = a; k < b; ++k) Stap[ord[k]] = acc;
+            a = b;
+        }
+        for (int64_t j = 0; j < M; ++j) {
+            double acc = 0.0;
+            for (int t = tptr[j]; t < tptr[j + 1]; ++t) acc += tw[t] * Stap[t];
+            d0[j] = acc;
+        }
     }
     // 3. internal order: by the (y, z) of the first tap, then x, so that markers at the same
     //    cross-section position on neighbouring x planes sit next to each other
@@ -643,29 +654,39 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
             tap_w[(size_t)t * M + i] = real ? (float)tw[src] : 0.f;
         }
     }
-    // 4. band cells in increasing index, each with its (internal marker, weight) entries
-    std::map<int, std::vector<std::pair<int, double>>> band;
+    // 4. band cells in increasing index, each with its (internal marker, weight) entries in
+    //    internal marker order: the taps listed marker by marker, stably sorted by cell
+    struct Entry {
+        int cell, mk;
+        double w;
+    };
+    std::vector<Entry> ent;
+    ent.reserve(T);
     for (int64_t i = 0; i < M; ++i) {
         const int64_t j = perm[i];
-        for (int t = tptr[j]; t < tptr[j + 1]; ++t) band[tcell[t]].push_back({(int)i, tw[t]});
+        for (int t = tptr[j]; t < tptr[j + 1]; ++t) ent.push_back({tcell[t], (int)i, tw[t]});
     }
-    const int64_t nband = (int64_t)band.size();
+    std::stable_sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) { return a.cell < b.cell; });
+    std::vector<size_t> start;  // first entry of each band cell
+    for (size_t k = 0; k < ent.size(); ++k)
+        if (k == 0 || ent[k].cell != ent[k - 1].cell) start.push_back(k);
+    const int64_t nband = (int64_t)start.size();
+    start.push_back(ent.size());
     int km = 1;
-    for (auto &kv : band) km = std::max<int>(km, (int)kv.second.size());
+    for (int64_t e = 0; e < nband; ++e) km = std::max<int>(km, (int)(start[e + 1] - start[e]));
     if (nband * km > kBandSlots * s->Mcap)
         return fail(MHD_ERR_INVALID_ARG, "markers too dense: %lld wall cells x %d entries exceed the workspace",
                     (long long)nband, km);
     std::vector<int> band_cell((size_t)nband), band_mk((size_t)nband * km);
     std::vector<float> band_w((size_t)nband * km, 0.f);
-    int64_t e = 0;
-    for (auto &kv : band) {
-        band_cell[e] = kv.first;
+    for (int64_t e = 0; e < nband; ++e) {
+        const size_t a = start[e], cnt = start[e + 1] - a;
+        band_cell[e] = ent[a].cell;
         for (int q = 0; q < km; ++q) {
-            const bool real = q < (int)kv.second.size();
-            band_mk[(size_t)q * nband + e] = real ? kv.second[q].first : kv.second[0].first;
-            band_w[(size_t)q * nband + e] = real ? (float)kv.second[q].second : 0.f;
+            const bool real = q < (int)cnt;
+            band_mk[(size_t)q * nband + e] = real ? ent[a + q].mk : ent[a].mk;
+            band_w[(size_t)q * nband + e] = real ? (float)ent[a + q].w : 0.f;
         }
-        ++e;
     }
     // 5. wall values in internal order
     std::vector<float> uw((size_t)(3 * M), 0.f), bw((size_t)(3 * M), 0.f);

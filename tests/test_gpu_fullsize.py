@@ -107,3 +107,47 @@ def test_batch_64_pipes_full_size_sampled_cells():
         checked += 1
     B.close()
     assert checked >= 10
+
+
+def test_maximum_box_sampled_cells():
+    """The largest box the library takes (3 nx ny nz < 2^31): 1024 x 1024 x 680 = 713 M cells, so
+    a vector field spans 8.6 GB (the per-component 32-bit offsets stay below 4 GB), 1.93 M
+    markers on a radius-300 pipe; one step with one sweep, checked at sampled cells including the
+    box's last cell and its first."""
+    import time
+
+    from paper_2211_09370_amd import Sim
+
+    nx, ny, nz, R = 1024, 1024, 680, 300.0
+    assert 3 * nx * ny * nz < 2 ** 31
+    t0 = time.time()
+    w = W.pipe_workload("pipe_max", 8, nx, ny, nz, R, 500.0, 20.0, 1e-2, n_mag=1, noise=1e-2)
+    cells = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx - 1, int(w.params.yc) + 300, int(w.params.zc))]
+    cells += _sample_cells(w, 9, key=800)
+    ref = [oracle_cell(w, c, 1) for c in cells]  # before the full-size inputs are dropped
+    print(f"case maximum box: inputs and {len(cells)} oracle cells in {time.time() - t0:.0f} s", flush=True)
+    sim = Sim(nx, ny, nz, w.markers.shape[1])
+    sim.set_markers(w.markers)
+    sim.set_params(w.params)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    w.rho = w.u = w.b = None
+    print(f"maximum box: set up in {time.time() - t0:.0f} s, stepping", flush=True)
+    sim.step(1)
+    got = {}
+    for f in ("rho", "u", "b"):
+        a = sim.get_field(f)
+        assert np.isfinite(a).all(), f
+        got[f] = [a[(..., cz, cy, cx)].copy() for cx, cy, cz in cells]
+        got[f + "_max"] = float(np.abs(a - 1.0).max() if f == "rho" else np.abs(a).max())
+        del a
+    sim.close()
+    us, bs = got["u_max"], got["b_max"]
+    rs = max(got["rho_max"], math.sqrt(3.0) * us)
+    e = [max(abs(float(got["rho"][i]) - ref[i][0]) for i in range(len(cells))) / rs,
+         max(np.abs(got["u"][i] - ref[i][1]).max() for i in range(len(cells))) / us,
+         max(np.abs(got["b"][i] - ref[i][2]).max() for i in range(len(cells))) / bs]
+    print(f"maximum box: {len(cells)} cells, err rho-1 {e[0]:.2e} u {e[1]:.2e} b {e[2]:.2e}, "
+          f"{time.time() - t0:.0f} s", flush=True)
+    assert max(e) <= 1e-5, e

@@ -359,10 +359,13 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
 
 // -------------------------------------------------------------------------------------------
 // Paired magnetic sweep for boxes with n_x a multiple of 128: the same plane march and the same
-// per-cell arithmetic as k_mag_sweep, but every lane owns two neighbouring x cells, so a wave
-// covers a 128-cell row. Rows are loaded and stored as 8-byte (float32) or 4-byte (16-bit)
-// pairs — half the memory instructions per cell — and a lane reads the four values x-1 .. x+2
-// of a row from LDS with one 8-byte and two 4-byte reads serving both of its cells.
+// update as k_mag_sweep, but every lane owns two neighbouring x cells, so a wave covers a
+// 128-cell row. Rows are loaded and stored as 8-byte (float32) or 4-byte (16-bit) pairs — half
+// the memory instructions per cell — and a lane reads the four values x-1 .. x+2 of a staged
+// row from LDS with two aligned 8-byte reads serving both of its cells. The arithmetic shares
+// work between the two cells (differences against one reference, shared column sums, weights
+// with kappa and the relaxation folded in), so it rounds differently from k_mag_sweep at the
+// float32 level.
 // -------------------------------------------------------------------------------------------
 template <typename T>
 struct Pair;

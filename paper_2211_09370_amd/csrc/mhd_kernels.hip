@@ -64,6 +64,52 @@ __global__ void k_ctrl_begin_batch(const PipeStep *tab) {
     if (threadIdx.x == 0) ctrl_begin_body(tab[blockIdx.x].ctrl, tab[blockIdx.x].c);
 }
 
+// Sums and maxima over a wave with cross-lane shuffles in a fixed butterfly (every lane ends
+// with the same bits), then over the workgroup's waves through LDS in wave order: the result is
+// the same on every run. Results are valid in thread 0.
+constexpr int kRedWaves = kRedThreads / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+// NV sums and NM maxima of the workgroup, in place in thread 0's v and m
+template <int NV, int NM>
+__device__ __forceinline__ void block_reduce(double (*sh)[kRedWaves], double *v, double *m) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+#pragma unroll
+    for (int q = 0; q < NM; ++q) m[q] = wave_max(m[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sh[q][wv] = v[q];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) sh[NV + q][wv] = m[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double t = sh[q][0];
+            for (int i = 1; i < kRedWaves; ++i) t += sh[q][i];
+            v[q] = t;
+        }
+#pragma unroll
+        for (int q = 0; q < NM; ++q) {
+            double t = sh[NV + q][0];
+            for (int i = 1; i < kRedWaves; ++i) t = fmax(t, sh[NV + q][i]);
+            m[q] = t;
+        }
+    }
+}
+
 // Fixed-order sum of the flow partials (one block per box), integral control law, step counter.
 template <bool BATCH>
 __global__ void __launch_bounds__(kRedThreads) k_step_end(DevCtrl *ctrl, const double *part, StepConst c,
@@ -75,19 +121,14 @@ __global__ void __launch_bounds__(kRedThreads) k_step_end(DevCtrl *ctrl, const d
         c = q.c;
         inv_count = q.inv_count;
     }
-    __shared__ double sh[kRedThreads];
-    double s = 0.0;
+    __shared__ double sh[1][kRedWaves];
+    double s[1] = {0.0};
     if (c.flow_control)
-        for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += part[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
+        for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s[0] += part[i];
+    block_reduce<1, 0>(sh, s, nullptr);
     if (threadIdx.x == 0) {
         if (c.flow_control) {
-            double ub = sh[0] * inv_count;
+            double ub = s[0] * inv_count;
             ctrl->G = ctrl->G + c.k_c * (8.0 * c.nu / (c.radius * c.radius)) * (c.u_target - ub);
         } else {
             ctrl->G = ctrl->G_step;
@@ -471,22 +512,10 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
 
 // -------------------------------------------------------------------------------------------
 // Float64 reductions with a fixed summation order: a fixed grid of kRedBlocks workgroups walks
-// the cells with a fixed stride, each block tree-reduces in LDS and writes one partial; a
-// single block then sums the partials in index order.
+// the cells with a fixed stride, each block reduces its values with wave shuffles and one LDS
+// exchange between its waves (block_reduce above) and writes one partial; a single block then
+// sums the partials in the same way.
 // -------------------------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ void block_sum(double (*sh)[kRedThreads], double *v) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-}
 
 template <typename TU, bool BATCH>
 __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, double *part, StepConst c,
@@ -500,7 +529,7 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
         c = q.c;
         blk = blockIdx.x % kRedBlocks;
     }
-    __shared__ double sh[1][kRedThreads];
+    __shared__ double sh[1][kRedWaves];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const double R2 = c.radius * c.radius;
     double s = 0.0;
@@ -511,8 +540,8 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
         if (dy * dy + dz * dz <= R2) s += (double)(St<TU>::ld(u, k) * c.u_scale);
     }
     double v[1] = {s};
-    block_sum<1>(sh, v);
-    if (threadIdx.x == 0) part[blk] = sh[0][0];
+    block_reduce<1, 0>(sh, v, nullptr);
+    if (threadIdx.x == 0) part[blk] = v[0];
 }
 
 // partial layout: 0 Ek, 1 Em, 2 Eb, 3 sum u_x (Omega), 4 Pp, 5 Pnu/nu, 6 PL, 7 Meta/eta, 8 Madv,
@@ -522,8 +551,7 @@ template <typename TR, typename TU, typename TB>
 __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, const TU *u, const TB *b,
                                                                 const TB *bh, const float *bext,
                                                                 const float *bext_yz, double *part, StepConst c) {
-    __shared__ double sh[14][kRedThreads];
-    __shared__ double shm[kRedThreads];
+    __shared__ double sh[16][kRedWaves];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const double us = c.u_scale, bs = c.b_scale;
     const double R2 = c.radius * c.radius;
@@ -602,31 +630,20 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
             v[13] += res * res;
         }
     }
-    block_sum<14>(sh, v);
-    // max |u|^2 and "any non-finite" in the same fixed tree
-    __shared__ double shf[kRedThreads];
-    shm[threadIdx.x] = umax2;
-    shf[threadIdx.x] = nonfin;
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
-            shf[threadIdx.x] = fmax(shf[threadIdx.x], shf[threadIdx.x + w]);
-        }
-        __syncthreads();
-    }
+    // the 14 sums, max |u|^2 and "any non-finite" in the same fixed order
+    double mx[2] = {umax2, nonfin};
+    block_reduce<14, 2>(sh, v, mx);
     if (threadIdx.x == 0) {
         double *o = part + (int64_t)blockIdx.x * kBudgetVals;
-        for (int q = 0; q < 14; ++q) o[q] = sh[q][0];
-        o[14] = shm[0];
-        o[15] = shf[0];
+        for (int q = 0; q < 14; ++q) o[q] = v[q];
+        o[14] = mx[0];
+        o[15] = mx[1];
     }
 }
 
 __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part, DevCtrl *ctrl, mhd_budget *ring,
                                                               StepConst c) {
-    __shared__ double sh[14][kRedThreads];
-    __shared__ double shm[kRedThreads], shf[kRedThreads];
+    __shared__ double sh[16][kRedWaves];
     double v[14];
 #pragma unroll
     for (int q = 0; q < 14; ++q) v[q] = 0.0;
@@ -638,40 +655,31 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part
         m = fmax(m, p[14]);
         f = fmax(f, p[15]);
     }
-    block_sum<14>(sh, v);
-    shm[threadIdx.x] = m;
-    shf[threadIdx.x] = f;
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
-            shf[threadIdx.x] = fmax(shf[threadIdx.x], shf[threadIdx.x + w]);
-        }
-        __syncthreads();
-    }
+    double mx[2] = {m, f};
+    block_reduce<14, 2>(sh, v, mx);
     if (threadIdx.x == 0) {
-        const double n = sh[12][0];
+        const double n = v[12];
         const double inv = n > 0.0 ? 1.0 / n : 0.0;
         mhd_budget r;
         r.step = ctrl->t;
         r.G = ctrl->G_step;
-        r.E_k = sh[0][0] * inv;
-        r.E_m = sh[1][0] * inv;
-        r.E_b = sh[2][0] * inv;
-        r.P_in = r.G * sh[3][0] * inv;
-        r.P_p = sh[4][0] * inv;
-        r.P_nu = c.nu * sh[5][0] * inv;
-        r.P_L = sh[6][0] * inv;
-        r.M_eta = c.eta * sh[7][0] * inv;
-        r.M_adv = sh[8][0] * inv;
-        r.joule = c.eta * sh[9][0] * inv;
-        r.mass = sh[10][0];
-        r.Q = sh[11][0] / (double)c.nx;
-        r.u_max = sqrt(shm[0]);
+        r.E_k = v[0] * inv;
+        r.E_m = v[1] * inv;
+        r.E_b = v[2] * inv;
+        r.P_in = r.G * v[3] * inv;
+        r.P_p = v[4] * inv;
+        r.P_nu = c.nu * v[5] * inv;
+        r.P_L = v[6] * inv;
+        r.M_eta = c.eta * v[7] * inv;
+        r.M_adv = v[8] * inv;
+        r.joule = c.eta * v[9] * inv;
+        r.mass = v[10];
+        r.Q = v[11] / (double)c.nx;
+        r.u_max = sqrt(mx[0]);
         r.n_omega = n;
-        r.res_mag = sqrt(sh[13][0] * inv);
+        r.res_mag = sqrt(v[13] * inv);
         // |u| >= c_s or a non-finite value marks the run unstable
-        if (shf[0] != 0.0 || !(shm[0] < c.u_limit2) || !isfinite(sh[0][0])) ctrl->status |= 1;
+        if (mx[1] != 0.0 || !(mx[0] < c.u_limit2) || !isfinite(v[0])) ctrl->status |= 1;
         const int idx = ctrl->n_records;
         if (idx < kRingCap) {
             ring[idx] = r;
@@ -684,14 +692,14 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part
 
 // Residual only: the same fixed-order sum of the partials' slots 13 (residual) and 12 (cells).
 __global__ void __launch_bounds__(kRedThreads) k_residual_final(const double *part, double *out) {
-    __shared__ double sh[2][kRedThreads];
+    __shared__ double sh[2][kRedWaves];
     double v[2] = {0.0, 0.0};
     for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) {
         v[0] += part[(int64_t)i * kBudgetVals + 13];
         v[1] += part[(int64_t)i * kBudgetVals + 12];
     }
-    block_sum<2>(sh, v);
-    if (threadIdx.x == 0) *out = sh[1][0] > 0.0 ? sqrt(sh[0][0] / sh[1][0]) : 0.0;
+    block_reduce<2, 0>(sh, v, nullptr);
+    if (threadIdx.x == 0) *out = v[1] > 0.0 ? sqrt(v[0] / v[1]) : 0.0;
 }
 
 // -------------------------------------------------------------------------------------------

@@ -558,7 +558,6 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
     s->sweep = default_tiles(nx);
     // initial state: rho = 1, u = 0, b = 0, t = 0, G = 0
     DevCtrl hc{};
-    mhd_status st;
     auto cleanup = [&](mhd_status r) {
         delete s;
         return r;
@@ -569,7 +568,6 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
     if (e != hipSuccess) return cleanup(fail(MHD_ERR_HIP, "hipMemcpyAsync failed: %s", hipGetErrorString(e)));
     e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return cleanup(fail(MHD_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e)));
-    (void)st;
     *out = s;
     return MHD_OK;
 }

@@ -151,3 +151,42 @@ def test_maximum_box_sampled_cells():
     print(f"maximum box: {len(cells)} cells, err rho-1 {e[0]:.2e} u {e[1]:.2e} b {e[2]:.2e}, "
           f"{time.time() - t0:.0f} s", flush=True)
     assert max(e) <= 1e-5, e
+
+
+def test_fringe_pipe_long_run_budget_series():
+    """The 128^3 fringe configuration stepped for 3000 steps with the energy budgets logged every
+    100 steps: the state stays finite, the mass (float64 sum of the float32 density) stays
+    constant, and the kinetic-energy balance of Sec. 4 holds along the transient, dE_k/dt =
+    P_in + P_p + P_nu + P_L with dE_k/dt the central difference of the records (the same balance
+    the oracle pins step by step), here over the whole run of the full-size box."""
+    import time
+
+    from paper_2211_09370_amd import Sim
+
+    w = W.fringe_pipe()
+    steps, every = 3000, 100
+    print("case fringe pipe long run", steps, "steps", flush=True)
+    t0 = time.time()
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+    sim.set_markers(w.markers)
+    sim.set_params(w.params)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.record_budget()
+    for k in range(steps // 1000):
+        sim.step(1000, every)
+        print(f"fringe pipe long run: {1000 * (k + 1)} steps, {time.time() - t0:.0f} s", flush=True)
+    rec = sim.budgets()
+    assert np.isfinite(sim.get_field("u")).all()
+    sim.close()
+    assert len(rec) == steps // every + 1 and all(r["step"] == every * i for i, r in enumerate(rec))
+    mass = np.array([r["mass"] for r in rec])
+    assert np.abs(mass - mass[0]).max() <= 1e-7 * mass[0], np.abs(mass - mass[0]).max() / mass[0]
+    Ek = np.array([r["E_k"] for r in rec])
+    P = np.array([r["P_in"] + r["P_p"] + r["P_nu"] + r["P_L"] for r in rec])
+    dEk = (Ek[2:] - Ek[:-2]) / (2 * every)
+    resid = np.abs(dEk - P[1:-1]).max() / np.abs(P).max()
+    print(f"fringe pipe long run: E_k {Ek[0]:.3e} -> {Ek[-1]:.3e}, max |dE_k/dt - sum P| / max |sum P| "
+          f"{resid:.2e}, mass drift {np.abs(mass - mass[0]).max() / mass[0]:.1e}", flush=True)
+    assert resid <= 0.05

@@ -331,6 +331,20 @@ def test_dense_marker_cloud():
     compare(gpu_run(w, 2), oracle_run(w, 2), label="dense markers")
 
 
+def test_markers_across_box_faces():
+    """The box is periodic, so a ring centred near a corner crosses the y and z faces and its
+    Lagrange stencils wrap like every other stencil; markers at the coordinate extremes 0 and
+    just below n are taken too."""
+    w = random_box(16, 20, 22, key=206, n_mag=3, R=6.0)
+    ring = W.pipe_markers(w.nx, 6.0, 1.3, 20.6)
+    ring[1] %= w.ny
+    ring[2] %= w.nz
+    ends = np.array([[0.0, w.nx - 1e-9, 3.0], [0.0, 10.0, w.ny - 1e-9], [w.nz - 1e-9, 0.0, 11.0]])
+    w.markers = np.concatenate([ring, ends], axis=1)
+    print("case markers across faces", w.markers.shape[1], flush=True)
+    compare(gpu_run(w, 2), oracle_run(w, 2), label="markers across faces")
+
+
 # ---------------------------------------------------------------------------------------------
 # whole steps on the pipe workloads
 # ---------------------------------------------------------------------------------------------

@@ -85,7 +85,7 @@ def random_box(nx, ny, nz, key, bext_kind=W.BEXT_TANH_FRINGE_Y, n_mag=1, eta=3.0
 
 @pytest.mark.parametrize("shape", [(37, 21, 13), (8, 32, 32), (16, 16, 9), (32, 11, 17), (64, 8, 5),
                                    (100, 12, 10), (1, 24, 1), (130, 5, 3), (128, 13, 9), (256, 6, 5),
-                                   (128, 1, 3)])
+                                   (128, 1, 3), (1, 1, 1), (2, 3, 1)])
 def test_one_step_no_wall_ragged_shapes(shape):
     print("case", shape, flush=True)
     w = random_box(*shape, key=200, n_mag=2)

@@ -488,16 +488,41 @@ int env_int(const char *name, int dflt) {
 
 bool valid_tx(int tx) { return tx == 8 || tx == 16 || tx == 32 || tx == 64; }
 
+// Workgroups of one sweep launch with tiles L on an nx x ny x nz box.
+int64_t sweep_workgroups(const SweepLaunch &L, int nx, int ny, int nz) {
+    const bool pair = L.pair && nx % 128 == 0;
+    const int64_t tx = pair ? 128 : L.tx, ty = pair ? (L.ty >= 8 ? 8 : 4) : 256 / L.tx;
+    return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + L.zchunk - 1) / L.zchunk);
+}
+
 // Default sweep tiles of a box (environment overrides for experiments: MHD_SWEEP_TX,
-// MHD_SWEEP_ZCHUNK, MHD_SWEEP_PAIR, MHD_SWEEP_PAIR_TY).
-SweepLaunch default_tiles(int nx) {
+// MHD_SWEEP_ZCHUNK, MHD_SWEEP_PAIR, MHD_SWEEP_PAIR_TY). Each z chunk re-reads two halo planes,
+// which costs HBM traffic on large boxes, while small boxes need short chunks for enough
+// workgroups. The chunk is the longest of 64, 32, 16 planes that still gives 512 workgroups
+// (two per CU) for the paired float32 sweep, 2048 for the other forms, else 8 planes. Measured
+// per sweep: 512 x 256^2 float32 353 -> 283 us (64 planes), split form 282 -> 252 us (32);
+// 256^3 171 -> 140 us (64); 200^3 single-cell tiles 102 -> 96 us (16); 128^3 stays at 8
+// (20 us; 16 planes, one workgroup per CU: 26 us).
+SweepLaunch default_tiles(const mhd_grid_desc &g) {
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
     SweepLaunch L;
     L.tx = nx >= 64 ? 64 : nx >= 32 ? 32 : nx >= 16 ? 16 : 8;
     const int etx = env_int("MHD_SWEEP_TX", L.tx);
     if (valid_tx(etx)) L.tx = etx;
-    L.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", 8));
     L.pair = (nx % 128 == 0) && env_int("MHD_SWEEP_PAIR", 1) != 0;
     L.ty = env_int("MHD_SWEEP_PAIR_TY", 4) >= 8 ? 8 : 4;
+    L.zchunk = 8;
+    const bool plain_pair = L.pair && g.b_storage == MHD_STORE_F32 && g.u_storage == MHD_STORE_F32;
+    const int64_t need = plain_pair ? 512 : 2048;
+    for (int zc : {64, 32, 16}) {
+        SweepLaunch t = L;
+        t.zchunk = zc;
+        if (sweep_workgroups(t, nx, ny, nz) >= need) {
+            L.zchunk = zc;
+            break;
+        }
+    }
+    L.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", L.zchunk));
     return L;
 }
 
@@ -553,9 +578,9 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
         return fail(MHD_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
     }
     // tile shape: widest x tile that the box fills, 256 work-items per workgroup; two x cells
-    // per lane whenever a row splits into 128-cell tiles (fewer LDS reads per cell)
-    const int nx = g->nx;
-    s->sweep = default_tiles(nx);
+    // per lane whenever a row splits into 128-cell tiles (fewer LDS reads per cell); z chunk by
+    // box size
+    s->sweep = default_tiles(*g);
     // initial state: rho = 1, u = 0, b = 0, t = 0, G = 0
     DevCtrl hc{};
     auto cleanup = [&](mhd_status r) {

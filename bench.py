@@ -181,7 +181,7 @@ def precision_leg(steps, with_error=True):
     out = {"workload": w.name, "box": [w.nx, w.ny, w.nz], "n_mag": w.params.n_mag,
            "markers": int(w.markers.shape[1]), "steps": steps}
     for name, st in forms.items():
-        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], **st)
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], stream=torch.cuda.Stream(), **st)
         sim.set_markers(w.markers)
         sim.set_params(w.params)
         sim.set_field("rho", w.rho)
@@ -203,8 +203,8 @@ def precision_leg(steps, with_error=True):
     if with_error and os.path.exists(gold):
         ref = np.load(gold)
         ws = W.small_pipe()
-        sim = Sim(ws.nx, ws.ny, ws.nz, ws.markers.shape[1], b_storage="f16split", u_scale=W.U0,
-                  b_scale=1e-3 * ws.params.B0)
+        sim = Sim(ws.nx, ws.ny, ws.nz, ws.markers.shape[1], stream=torch.cuda.Stream(), b_storage="f16split",
+                  u_scale=W.U0, b_scale=1e-3 * ws.params.B0)
         sim.set_markers(ws.markers)
         sim.set_params(ws.params)
         sim.set_field("rho", ws.rho)
@@ -234,7 +234,7 @@ def accelerated_leg(w, steps, warmup, res_plain):
     from paper_2211_09370_amd import Sim
 
     n_mag = (w.params.n_mag + 1) // 2
-    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], stream=torch.cuda.Stream())
     sim.set_markers(w.markers)
     sim.set_params(w.params, alpha=0.5, n_mag=n_mag)
     sim.set_field("rho", w.rho)
@@ -324,7 +324,9 @@ def main():
     w = W.fringe_pipe()
     M = w.markers.shape[1]
     log(f"bench: {w.name} N={w.n_cells} M={M} n_mag={w.params.n_mag}")
-    sim = Sim(w.nx, w.ny, w.nz, M)
+    # the solver's own stream: steps replay as captured HIP graphs (the NULL stream cannot be captured)
+    stream = torch.cuda.Stream()
+    sim = Sim(w.nx, w.ny, w.nz, M, stream=stream)
     sim.set_markers(w.markers)
     sim.set_params(w.params)
     sim.set_field("rho", w.rho)
@@ -334,7 +336,6 @@ def main():
     sim.step(args.warmup)
     torch.cuda.synchronize()
     log(f"bench: warmup {args.warmup} steps done")
-    stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

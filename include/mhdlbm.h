@@ -182,8 +182,16 @@ mhd_status mhd_set_time(mhd_sim *s, int64_t t, double G);
 /* Advance n_steps fluid steps (each: n_mag magnetic sweeps with the b correction after each,
  * Lorentz force, fluid predictor, u correction). Asynchronous on the stream: returns after
  * the launches. If budget_every > 0 a budget record is taken after every step whose new step
- * count is a multiple of budget_every. */
+ * count is a multiple of budget_every. On a caller stream (hip_stream != NULL at mhd_create)
+ * with graphs enabled and profiling off, the first step from each state of the double buffers
+ * is captured into a HIP graph (stream capture, relaxed mode: do not enqueue other work on
+ * that stream from another thread meanwhile) and every step is one graph launch; the graphs
+ * are dropped when parameters, markers or tiles change. Results are the same as with direct
+ * launches. */
 mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every);
+
+/* Graph replay of mhd_step (performance only): enable = 1 (default) or 0 (direct launches). */
+mhd_status mhd_set_graph(mhd_sim *s, int32_t enable);
 
 /* Synchronise the stream and move the budget records taken since the last call (oldest first,
  * at most cap) to out. Returns MHD_ERR_UNSTABLE if a record found non-finite values or

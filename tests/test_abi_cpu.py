@@ -112,3 +112,7 @@ def test_tile_calls_reject_null_sim():
     t = (C.c_int32 * 4)(64, 8, 0, 4)
     assert _abi.lib().mhd_set_tiles(None, t) == _abi.MHD_ERR_INVALID_ARG
     assert _abi.lib().mhd_get_tiles(None, t) == _abi.MHD_ERR_INVALID_ARG
+
+
+def test_graph_call_rejects_null_sim_and_bad_flag():
+    assert _abi.lib().mhd_set_graph(None, 1) == _abi.MHD_ERR_INVALID_ARG

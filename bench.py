@@ -14,9 +14,10 @@ batched = the batched form on 64 independent pipes of uneven size and physics (~
 ~2.3 M markers, tiles autotuned), MLUPS over all their cells (an extra object, not `value`).
 accelerated = the accelerated magnetic iteration (alpha = 1/2, 135 sweeps) on the same box, with the
 induction residual after a step next to the plain method's (an extra object, not `value`).
-precision = float32 against the split float16 form (b in float16 hi + lo, float16 copy of u for
-the sweeps) on the 512 x 256 x 256 pipe at 270 sweeps per step, with the split form's per-field
-error against the stored FP64 oracle run of the 8 x 32 x 32 pipe after 2000 steps.
+precision = float32 against the 16-bit storage forms on the 512 x 256 x 256 pipe at 270 sweeps
+per step: the split form (b in float16 hi + lo, float16 copy of u for the sweeps) and the plain
+offset forms (all float16; float16 / bfloat16 / float16), each with its per-field error against
+the stored FP64 oracle run of the 8 x 32 x 32 pipe after 2000 steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-precision]
                        [--no-accel]
@@ -165,8 +166,9 @@ def batched_leg(steps):
 
 
 def precision_leg(steps, with_error=True):
-    """MLUPS of float32 and of the split float16 form on the large pipe, and the split form's
-    per-field error after 2000 steps of the small pipe against the stored oracle run."""
+    """MLUPS of float32 and of the 16-bit storage forms on the large pipe, and each form's
+    per-field error after 2000 steps of the small pipe against the stored oracle run (the split
+    form is the accurate one; the plain offset forms are reported with theirs)."""
     import math
 
     import numpy as np
@@ -177,7 +179,10 @@ def precision_leg(steps, with_error=True):
 
     w = W.large_pipe(Rm=1e-2)
     B_ind = 1e-2 * w.params.B0  # induced-field scale Rm B0
-    forms = {"f32": {}, "f16split": dict(b_storage="f16split", u_scale=W.U0, b_scale=B_ind)}
+    forms = {"f32": {}, "f16split": dict(b_storage="f16split", u_scale=W.U0, b_scale=B_ind),
+             "f16_f16_f16": dict(rho_storage="f16", u_storage="f16", b_storage="f16", u_scale=W.U0, b_scale=B_ind),
+             "f16_bf16_f16": dict(rho_storage="f16", u_storage="bf16", b_storage="f16", u_scale=W.U0,
+                                  b_scale=w.params.B0)}
     out = {"workload": w.name, "box": [w.nx, w.ny, w.nz], "n_mag": w.params.n_mag,
            "markers": int(w.markers.shape[1]), "steps": steps}
     for name, st in forms.items():
@@ -203,24 +208,31 @@ def precision_leg(steps, with_error=True):
     if with_error and os.path.exists(gold):
         ref = np.load(gold)
         ws = W.small_pipe()
-        sim = Sim(ws.nx, ws.ny, ws.nz, ws.markers.shape[1], stream=torch.cuda.Stream(), b_storage="f16split",
-                  u_scale=W.U0, b_scale=1e-3 * ws.params.B0)
-        sim.set_markers(ws.markers)
-        sim.set_params(ws.params)
-        sim.set_field("rho", ws.rho)
-        sim.set_field("u", ws.u)
-        sim.set_field("b", ws.b)
-        sim.step(int(ref["steps"]))
+        Rm_B0 = 1e-3 * ws.params.B0
+        small = {"f16split": dict(b_storage="f16split", u_scale=W.U0, b_scale=Rm_B0),
+                 "f16_f16_f16": dict(rho_storage="f16", u_storage="f16", b_storage="f16", u_scale=W.U0,
+                                     b_scale=Rm_B0),
+                 "f16_bf16_f16": dict(rho_storage="f16", u_storage="bf16", b_storage="f16", u_scale=W.U0,
+                                      b_scale=ws.params.B0)}
 
         def e(a, r):
             return float(np.abs(a - r).max() / np.abs(r).max())
 
         rs = max(np.abs(ref["rho"] - 1).max(), math.sqrt(3) * np.abs(ref["u"]).max())
-        out["f16split_error_vs_oracle"] = {
-            "case": "8x32x32 pipe, Ha 5, 2000 steps, max-normalised",
-            "u": e(sim.get_field("u"), ref["u"]), "b": e(sim.get_field("b"), ref["b"]),
-            "rho": float(np.abs(sim.get_field("rho") - ref["rho"]).max() / rs)}
-        sim.close()
+        for name, st in small.items():
+            sim = Sim(ws.nx, ws.ny, ws.nz, ws.markers.shape[1], stream=torch.cuda.Stream(), **st)
+            sim.set_markers(ws.markers)
+            sim.set_params(ws.params)
+            sim.set_field("rho", ws.rho)
+            sim.set_field("u", ws.u)
+            sim.set_field("b", ws.b)
+            sim.step(int(ref["steps"]))
+            out[name + "_error_vs_oracle"] = {
+                "case": "8x32x32 pipe, Ha 5, 2000 steps, max-normalised",
+                "u": e(sim.get_field("u"), ref["u"]), "b": e(sim.get_field("b"), ref["b"]),
+                "rho": float(np.abs(sim.get_field("rho") - ref["rho"]).max() / rs)}
+            sim.close()
+            log(f"bench: precision {name} error after {int(ref['steps'])} steps: u {out[name + '_error_vs_oracle']['u']:.2e}")
     return out
 
 

@@ -300,6 +300,50 @@ def test_macroscopic_branch_split_form():
     compare(sim, oracle_run(w, 2), tol=2e-3, label="mac split")
 
 
+# ---------------------------------------------------------------------------------------------
+# Variants combined (each is tested alone above; here they run together)
+# ---------------------------------------------------------------------------------------------
+
+def test_d3q27_with_rescaling_and_with_six_magnets():
+    print("case d3q27 + gamma 2, pipe8 10 steps", flush=True)
+    w = W.small_pipe()
+    compare(gpu_run(w, 10, lattice=27, gamma=2.0), oracle_run(w, 10, lattice=27, gamma=2.0),
+            label="d3q27 gamma 2 pipe8 10 steps")
+    print("case d3q27 + six magnets, paired sweep", flush=True)
+    w = W.pipe_workload("six_magnets", 7, 128, 33, 33, 14.0, 50.0, 10.0, 1e-2, bext_kind=W.BEXT_SIX_MAGNETS,
+                        n_mag=4, b_amp=1e-4, noise=1e-2)
+    compare(gpu_run(w, 2, lattice=27), oracle_run(w, 2, lattice=27), label="d3q27 six magnets 128x33x33")
+
+
+def test_accelerated_iteration_with_rescaling_six_magnets_and_flow_control():
+    print("case alpha 1/2 + gamma 0.5 + six magnets + flow control", flush=True)
+    w = W.pipe_workload("six_magnets", 8, 8, 33, 33, 14.0, 50.0, 10.0, 1e-2, bext_kind=W.BEXT_SIX_MAGNETS,
+                        n_mag=60, b_amp=1e-4, noise=1e-2)
+    w.params.flow_control = 1
+    w.params.u_bulk_target = 0.01
+    w.params.k_c = 0.5
+    over = dict(alpha=0.5, gamma=0.5)
+    compare(gpu_run(w, 5, **over), oracle_run(w, 5, **over), label="alpha gamma six magnets flow control")
+
+
+def test_accelerated_iteration_in_the_split_form():
+    """alpha = 1/2 with half the sweeps, b in the split float16 form (bar as for the split form's
+    short runs)."""
+    from paper_2211_09370_amd import Sim
+
+    print("case alpha 1/2 split pipe8 10 steps", flush=True)
+    w = W.small_pipe()
+    over = dict(alpha=0.5, n_mag=135)
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], b_storage="f16split", u_scale=W.U0, b_scale=1e-3 * w.params.B0)
+    sim.set_markers(w.markers)
+    sim.set_params(w.params, **over)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.step(10)
+    compare(sim, oracle_run(w, 10, **over), tol=2e-3, label="alpha split pipe8 10 steps")
+
+
 @pytest.mark.parametrize("bext", [W.BEXT_NONE, W.BEXT_UNIFORM_Y, W.BEXT_TANH_FRINGE_Y])
 def test_one_step_with_wall(bext):
     w = random_box(24, 30, 28, key=201, bext_kind=bext, n_mag=3, R=11.3)

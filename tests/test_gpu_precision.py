@@ -130,3 +130,33 @@ def test_split_form_quarter_fringe_20_steps():
     e_r, e_u, e_b = field_errors(sim, o.rho, o.u, o.b)
     print(f"split fringe32 20 steps err rho-1 {e_r:.2e} u {e_u:.2e} b {e_b:.2e}", flush=True)
     assert e_u <= 1e-3 and e_r <= 1e-3 and e_b <= 2e-2, (e_r, e_u, e_b)
+
+
+def test_sixteen_bit_forms_with_the_six_magnet_field():
+    """The (y, z) table of the six-magnet field staged with 16-bit u and b (every storage form,
+    paired sweep), one step of four sweeps against the oracle: the split form within its
+    one-step bar, the plain offset forms within loose bounds recorded from measurement."""
+    from paper_2211_09370_amd import Sim
+
+    w = W.pipe_workload("six_magnets", 7, 128, 33, 33, 14.0, 50.0, 10.0, 1e-2, bext_kind=W.BEXT_SIX_MAGNETS,
+                        n_mag=4, b_amp=1e-4, noise=1e-2)
+    o = oracle_run(w, 1)
+    Rm_B0 = 1e-2 * w.params.B0
+    cases = {"split": (dict(b_storage="f16split", u_scale=W.U0, b_scale=Rm_B0), 2e-3),
+             "f16/f16/f16": (dict(rho_storage="f16", u_storage="f16", b_storage="f16", u_scale=W.U0,
+                                  b_scale=Rm_B0), 3e-3),  # measured 7.6e-4 (u)
+             "f16/bf16/f16": (dict(rho_storage="f16", u_storage="bf16", b_storage="f16", u_scale=W.U0,
+                                   b_scale=w.params.B0), 2e-2)}  # measured 6.1e-3 (u)
+    for name, (store, bound) in cases.items():
+        print("case six magnets", name, flush=True)
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], **store)
+        sim.set_markers(w.markers)
+        sim.set_params(w.params)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.step(1)
+        e = field_errors(sim, o.rho, o.u, o.b)
+        print(f"six magnets {name}: err rho-1 {e[0]:.2e} u {e[1]:.2e} b {e[2]:.2e}", flush=True)
+        sim.close()
+        assert max(e) <= bound, (name, e)

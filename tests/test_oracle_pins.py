@@ -308,6 +308,34 @@ def _random_state(n, key, F_mean=1e-4):
 
 
 @pytest.mark.parametrize("lattice", [19, 27])
+def test_lorentz_force_of_a_shear_mode_is_its_closed_form(lattice):
+    """Sec. 5.1: J = curl_h b with the isotropic difference d_a f = 3 sum_i w_i e_ia f(x + e_i),
+    which for a field varying along one axis is the central difference on both lattices (the
+    weights of the velocities with e_a = 1 sum to 1/6), so d sin(k s) = sin(k) cos(k s) exactly;
+    F = G x + J x (B_ext + b). With B_ext = B0 y: b = (0, 0, A sin(k y)) gives J = (A sin(k) cos(k y),
+    0, 0) and F = (G, -J_x A sin(k y), J_x B0); b = (A sin(k z), 0, 0) gives J = (0, A sin(k) cos(k z), 0)
+    and F = (G, 0, -J_y A sin(k z))."""
+    n, A, B0, G = 12, 0.3, 0.8, 1e-4
+    k = 2 * math.pi / n
+    p = oracle.make_params(n, n, n, bext_kind=W.BEXT_UNIFORM_Y, B0=B0, lattice=lattice)
+    s = np.sin(k * np.arange(n)); c = np.cos(k * np.arange(n))
+    b = np.zeros((3, n, n, n))
+    b[2] = A * s[None, :, None]                      # b_z(y)
+    F = oracle.lorentz(p, b, G)
+    Jx = A * math.sin(k) * c[None, :, None]
+    assert np.abs(F[0] - G).max() < 1e-15
+    assert np.abs(F[1] - (-Jx * A * s[None, :, None])).max() < 1e-14
+    assert np.abs(F[2] - Jx * B0).max() < 1e-14
+    b = np.zeros((3, n, n, n))
+    b[0] = A * s[:, None, None]                      # b_x(z)
+    F = oracle.lorentz(p, b, G)
+    Jy = A * math.sin(k) * c[:, None, None]
+    assert np.abs(F[0] - G).max() < 1e-15
+    assert np.abs(F[1]).max() < 1e-15
+    assert np.abs(F[2] - (-Jy * A * s[:, None, None])).max() < 1e-14
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
 def test_density_update_conserves_mass_exactly(lattice):
     rho, u, F = _random_state(7, 103)
     p = oracle.make_params(7, 7, 7, nu=0.05, lattice=lattice)

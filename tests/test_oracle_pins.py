@@ -336,6 +336,43 @@ def test_lorentz_force_of_a_shear_mode_is_its_closed_form(lattice):
 
 
 @pytest.mark.parametrize("lattice", [19, 27])
+def test_budget_terms_of_shear_modes_are_their_closed_forms(lattice):
+    """Sec. 4: every budget term on fields that vary along y only, averaged over a region Omega
+    that holds the whole box (large radius). On such fields the isotropic gradient is the
+    central difference (d sin ky = sin k cos ky) and the isotropic Laplacian the 1D second
+    difference (2 (cos k - 1) sin ky) on both lattices, so each average is a closed form:
+    with u = (U0 + A sin ky, 0, C cos ky), b = (0, 0, Bb sin ky), B_ext = B0 y, rho = 1,
+      E_k = (U0^2 + A^2/2 + C^2/2)/2, E_m = (B0^2 + Bb^2/2)/2, E_b = Bb^2/4, P_in = G U0,
+      P_nu = nu (cos k - 1)(A^2 + C^2), P_L = C Bb B0 sin(k)/2 = -M_adv,
+      M_eta = eta (cos k - 1) Bb^2, joule = eta Bb^2 sin(k)^2/2, P_p = 0,
+      residual^2 = ([2 eta (cos k - 1) Bb - B0 C sin k]^2 + (B0 A sin k)^2)/2;
+    and with rho = 1 + e sin ky, u = (0, D cos ky, 0), b = 0: P_p = -D e sin(k)/6 (c_s^2 = 1/3)."""
+    n, U0, A, C, Bb, B0, G, nu, eta = 12, 0.03, 0.02, 0.015, 0.01, 0.7, 2e-5, 0.05, 1.3
+    k = 2 * math.pi / n
+    sy = np.sin(k * np.arange(n))[None, :, None] * np.ones((n, n, n))
+    cy = np.cos(k * np.arange(n))[None, :, None] * np.ones((n, n, n))
+    p = oracle.make_params(n, n, n, nu=nu, eta=eta, bext_kind=W.BEXT_UNIFORM_Y, B0=B0, lattice=lattice,
+                           yc=n / 2, zc=n / 2, radius=100.0)
+    rho = np.ones((n, n, n))
+    u = np.stack([U0 + A * sy, 0 * sy, C * cy])
+    b = np.stack([0 * sy, 0 * sy, Bb * sy])
+    r = oracle.budgets(p, rho, u, b, G)
+    cm, sk = math.cos(k) - 1.0, math.sin(k)
+    want = {"E_k": (U0 ** 2 + A ** 2 / 2 + C ** 2 / 2) / 2, "E_m": (B0 ** 2 + Bb ** 2 / 2) / 2, "E_b": Bb ** 2 / 4,
+            "P_in": G * U0, "P_p": 0.0, "P_nu": nu * cm * (A ** 2 + C ** 2), "P_L": C * Bb * B0 * sk / 2,
+            "M_eta": eta * cm * Bb ** 2, "M_adv": -C * Bb * B0 * sk / 2, "joule": eta * Bb ** 2 * sk ** 2 / 2,
+            "mass": float(n ** 3), "Q": n * n * U0,
+            "res_mag": math.sqrt(((2 * eta * cm * Bb - B0 * C * sk) ** 2 + (B0 * A * sk) ** 2) / 2)}
+    assert r["n_omega"] == n ** 3
+    for key, v in want.items():
+        assert abs(r[key] - v) <= 1e-13 * max(1.0, abs(v)), (key, r[key], v)
+    e, D = 1e-3, 0.02
+    r = oracle.budgets(p, 1.0 + e * sy, np.stack([0 * sy, D * cy, 0 * sy]), np.zeros((3, n, n, n)), 0.0)
+    assert abs(r["P_p"] - (-D * e * sk / 6)) <= 1e-15, r["P_p"]
+    assert abs(r["E_k"] - D ** 2 / 4) <= 1e-15
+
+
+@pytest.mark.parametrize("lattice", [19, 27])
 def test_density_update_conserves_mass_exactly(lattice):
     rho, u, F = _random_state(7, 103)
     p = oracle.make_params(7, 7, 7, nu=0.05, lattice=lattice)

@@ -60,3 +60,30 @@ def test_graph_replay_equals_direct_launches(store):
         assert g.budgets()[-1]["step"] == d.budgets()[-1]["step"] == 101
         g.close()
         d.close()
+
+
+def test_two_solvers_on_two_streams_step_independently():
+    """Two boxes, each on a stream of its own, stepped in interleaved calls (each replaying its
+    own graphs, with profiling switched on and off in between for one of them) end where each
+    ends when stepped alone."""
+    import torch
+
+    w = W.pipe_workload("graph", 13, 128, 30, 28, 10.0, 50.0, 10.0, 1e-2, bext_kind=W.BEXT_TANH_FRINGE_Y,
+                        fringe_x0=64.0, fringe_w=4.0, noise=1e-2, rho_amp=1e-3, b_amp=1e-3)
+    w2 = W.small_pipe(noise=1e-2)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a, b = _sim(w, s1, True, {}), _sim(w2, s2, True, {})
+    for k in range(4):
+        a.step(1)
+        b.step(1)
+        if k == 1:
+            a.set_profiling(True)
+        if k == 2:
+            a.set_profiling(False)
+    ra, rb = _sim(w, s1, False, {}), _sim(w2, s2, False, {})
+    ra.step(4)
+    rb.step(4)
+    _same(a, ra, "interleaved box 1")
+    _same(b, rb, "interleaved box 2")
+    for s in (a, b, ra, rb):
+        s.close()

@@ -184,7 +184,7 @@ def precision_leg(steps, with_error=True):
              "f16_bf16_f16": dict(rho_storage="f16", u_storage="bf16", b_storage="f16", u_scale=W.U0,
                                   b_scale=w.params.B0)}
     out = {"workload": w.name, "box": [w.nx, w.ny, w.nz], "n_mag": w.params.n_mag,
-           "markers": int(w.markers.shape[1]), "steps": steps}
+           "markers": int(w.markers.shape[1]), "steps": steps, "tiles": "autotuned per form (mhd_tune)"}
     for name, st in forms.items():
         sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], stream=torch.cuda.Stream(), **st)
         sim.set_markers(w.markers)
@@ -192,6 +192,7 @@ def precision_leg(steps, with_error=True):
         sim.set_field("rho", w.rho)
         sim.set_field("u", w.u)
         sim.set_field("b", w.b)
+        sim.tune(5)
         sim.step(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -199,6 +200,7 @@ def precision_leg(steps, with_error=True):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         out[name + "_MLUPS"] = round(w.n_cells * steps / sec / 1e6, 3)
+        out[name + "_tiles"] = list(sim.tiles)
         sim.close()
         del sim
         torch.cuda.empty_cache()

@@ -238,6 +238,12 @@ mhd_status mhd_destroy(mhd_sim *s);
 mhd_status mhd_get_tiles(mhd_sim *s, int32_t tiles[4]);
 mhd_status mhd_set_tiles(mhd_sim *s, const int32_t tiles[4]);
 
+/* Autotuner of the sweep tiles of one box: every valid choice (x tile 8-64, the paired form with
+ * 4 or 8 rows when nx % 128 == 0, z chunks 4-64 planes) is timed by reps sweeps (default 5 if
+ * reps <= 0) of the live fields into the box's other buffer of b, and the fastest is kept. The
+ * state is unchanged. Synchronous. STATE before mhd_set_params or on a box of a batch. */
+mhd_status mhd_tune(mhd_sim *s, int32_t reps);
+
 /* ---------------------------------------------------------------------------------------------
  * Batched form: many independent pipes (boxes), each with its own size, markers, parameters and
  * number of magnetic sweeps, advanced together. One fluid step of the whole batch is a fixed

@@ -24,7 +24,7 @@ from ._abi import (MHD_BEXT_NONE, MHD_BEXT_SIX_MAGNETS, MHD_BEXT_TANH_FRINGE_Y, 
 __all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
-           "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles", "mhd_set_graph",
+           "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles", "mhd_set_graph", "mhd_tune",
            "mhd_mag_residual_curve",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
            "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
@@ -152,6 +152,10 @@ def mhd_get_tiles(h):
 def mhd_set_tiles(h, tiles):
     t = (C.c_int32 * 4)(*[int(v) for v in tiles])
     _abi.check(_abi.lib().mhd_set_tiles(h, t), "mhd_set_tiles")
+
+
+def mhd_tune(h, reps=5):
+    _abi.check(_abi.lib().mhd_tune(h, int(reps)), "mhd_tune")
 
 
 def mhd_set_graph(h, enable):
@@ -303,6 +307,10 @@ class Sim:
     def step(self, n: int = 1, budget_every: int = 0):
         mhd_step(self._h, n, budget_every)
 
+    def tune(self, reps: int = 5):
+        """Time every valid sweep tile choice on the live fields and keep the fastest (state unchanged)."""
+        mhd_tune(self._h, reps)
+
     def set_graph(self, on: bool):
         """Graph replay of the steps on a caller stream (default on; no effect on the default stream)."""
         mhd_set_graph(self._h, on)
@@ -393,6 +401,10 @@ class Batch:
 
     def step(self, n: int = 1, budget_every: int = 0):
         mhd_batch_step(self._h, n, budget_every)
+
+    def tune(self, reps: int = 5):
+        """Time every valid sweep tile choice on the live fields and keep the fastest (state unchanged)."""
+        mhd_tune(self._h, reps)
 
     def set_graph(self, on: bool):
         mhd_batch_set_graph(self._h, on)

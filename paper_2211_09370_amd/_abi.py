@@ -31,7 +31,7 @@ EXPORTS = ("mhd_last_error", "mhd_workspace_size", "mhd_create", "mhd_set_marker
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
            "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles",
-           "mhd_set_graph", "mhd_mag_residual_curve",
+           "mhd_set_graph", "mhd_tune", "mhd_mag_residual_curve",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
            "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
            "mhd_batch_kernel_stats", "mhd_batch_destroy")
@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
         L.mhd_get_tiles.argtypes = [P, I4]
         L.mhd_set_tiles.argtypes = [P, I4]
         L.mhd_set_graph.argtypes = [P, C.c_int32]
+        L.mhd_tune.argtypes = [P, C.c_int32]
         PD = C.POINTER(mhd_pipe_desc)
         L.mhd_batch_workspace_size.argtypes = [PD, C.c_int32, C.POINTER(C.c_size_t)]
         L.mhd_batch_create.argtypes = [PD, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,

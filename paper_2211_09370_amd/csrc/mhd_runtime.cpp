@@ -960,6 +960,69 @@ mhd_status mhd_set_graph(mhd_sim *s, int32_t enable) {
     return MHD_OK;
 }
 
+mhd_status mhd_tune(mhd_sim *s, int32_t reps) {
+    g_err.clear();
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (s->owner) return fail(MHD_ERR_STATE, "this box belongs to a batch: tune it with mhd_batch_tune");
+    if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called before mhd_tune");
+    if (reps <= 0) reps = 5;
+    const StepConst c = step_const(s);
+    const int nx = s->g.nx, nz = s->g.nz;
+    std::vector<SweepLaunch> cand;
+    for (int zc : {4, 8, 16, 32, 64}) {
+        if (zc > 2 * nz && zc != 4) continue;
+        if (nx % 128 == 0)
+            for (int ty : {4, 8}) cand.push_back({64, ty, zc, 1});
+        for (int tx : {64, 32, 16, 8})
+            if (tx <= std::max(8, nx)) cand.push_back({tx, 4, zc, 0});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MHD_ERR_HIP, "hipEventCreate failed");
+    }
+    // Each candidate runs reps sweeps of the live state into the other buffer of b, which the
+    // next step overwrites (the split form's hi part is only read): the state is unchanged.
+    SweepLaunch best_L = s->sweep;
+    float best = 0.f;
+    mhd_status st = MHD_OK;
+    for (size_t i = 0; i < cand.size() && st == MHD_OK; ++i) {
+        const SweepLaunch L = cand[i];
+        SweepArgs a = make_sweep_args(s->split() ? s->u16() : s->u(s->cu), s->b(s->cb), s->b(1 - s->cb),
+                                      s->at<float>(s->L.bext), c, L);
+        a.bext_yz = s->byz();
+        if (s->split()) {
+            a.u_scale = c.copy_scale;
+            a.bh = s->bh(s->ch);
+        }
+        hipError_t e = launch_mag_sweep(s->stream, s->kinds, a, L);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_mag_sweep(s->stream, s->kinds, a, L);
+        if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = fail(MHD_ERR_HIP, "timing a sweep failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (i == 0 || ms < best) {
+            best = ms;
+            best_L = L;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MHD_OK) return st;
+    s->sweep.tx = best_L.tx;
+    s->sweep.ty = best_L.ty;
+    s->sweep.zchunk = best_L.zchunk;
+    s->sweep.pair = best_L.pair;
+    drop_step_graphs(s);
+    return MHD_OK;
+}
+
 mhd_status mhd_mag_residual_curve(mhd_sim *s, int32_t n_sweeps, double *res_out) {
     g_err.clear();
     if (!s || !res_out) return fail(MHD_ERR_INVALID_ARG, "NULL argument");

@@ -116,3 +116,7 @@ def test_tile_calls_reject_null_sim():
 
 def test_graph_call_rejects_null_sim_and_bad_flag():
     assert _abi.lib().mhd_set_graph(None, 1) == _abi.MHD_ERR_INVALID_ARG
+
+
+def test_tune_rejects_null_sim():
+    assert _abi.lib().mhd_tune(None, 3) == _abi.MHD_ERR_INVALID_ARG

@@ -586,3 +586,31 @@ def test_default_tiles_follow_the_box_size():
         sim = Sim(*shape, 0, **store)
         assert tuple(sim.tiles) == want, (shape, store, tuple(sim.tiles))
         sim.close()
+
+
+@pytest.mark.parametrize("store", [{}, dict(b_storage="f16split", u_scale=0.05, b_scale=0.01)], ids=["f32", "split"])
+def test_tune_keeps_the_state_and_parity(store):
+    """mhd_tune times every tile choice on the live fields: the state is unchanged bit for bit,
+    the chosen tiles are valid, and stepping on with them stays on the oracle."""
+    from paper_2211_09370_amd import Sim
+
+    print("case tune", store, flush=True)
+    w = W.pipe_workload("tune", 17, 128, 26, 24, 8.0, 50.0, 10.0, 1e-2, bext_kind=W.BEXT_TANH_FRINGE_Y,
+                        fringe_x0=64.0, fringe_w=4.0, n_mag=4, noise=1e-2, rho_amp=1e-3, b_amp=1e-3)
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], **store)
+    sim.set_markers(w.markers)
+    sim.set_params(w.params)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.step(1)
+    before = [sim.get_field(f) for f in ("rho", "u", "b")]
+    sim.tune(2)
+    after = [sim.get_field(f) for f in ("rho", "u", "b")]
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    t = tuple(sim.tiles)
+    assert t[0] in (8, 16, 32, 64) and t[1] in (4, 8, 16, 32, 64) and t[2] in (0, 1) and t[3] in (4, 8), t
+    print("tuned tiles", t, flush=True)
+    sim.step(2)
+    compare(sim, oracle_run(w, 3), tol=TOL if not store else 2e-3, label=f"tuned {t}")
+    sim.close()

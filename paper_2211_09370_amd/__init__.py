@@ -402,10 +402,6 @@ class Batch:
     def step(self, n: int = 1, budget_every: int = 0):
         mhd_batch_step(self._h, n, budget_every)
 
-    def tune(self, reps: int = 5):
-        """Time every valid sweep tile choice on the live fields and keep the fastest (state unchanged)."""
-        mhd_tune(self._h, reps)
-
     def set_graph(self, on: bool):
         mhd_batch_set_graph(self._h, on)
 

@@ -120,3 +120,13 @@ def test_graph_call_rejects_null_sim_and_bad_flag():
 
 def test_tune_rejects_null_sim():
     assert _abi.lib().mhd_tune(None, 3) == _abi.MHD_ERR_INVALID_ARG
+
+
+def test_binding_methods_call_their_own_entry_points():
+    """Sim and Batch methods of the same name reach the single-box and the batched calls."""
+    from paper_2211_09370_amd import Batch, Sim
+
+    for cls, name, call in ((Sim, "tune", "mhd_tune"), (Batch, "tune", "mhd_batch_tune"),
+                            (Sim, "set_graph", "mhd_set_graph"), (Batch, "set_graph", "mhd_batch_set_graph"),
+                            (Sim, "step", "mhd_step"), (Batch, "step", "mhd_batch_step")):
+        assert call in getattr(cls, name).__code__.co_names, (cls.__name__, name)

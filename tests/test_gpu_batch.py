@@ -158,16 +158,14 @@ def test_batch_replans_after_parameter_change():
 
 
 def test_batch_member_rules():
-    from paper_2211_09370_amd import MhdError, mhd_destroy, mhd_step
+    from paper_2211_09370_amd import MhdError, mhd_destroy, mhd_step, mhd_tune
 
     spec = batch_spec()[:2]
     B = make_batch(spec)
-    with pytest.raises(MhdError) as e:
-        mhd_step(B.pipes[0]._h, 1)
-    assert e.value.status == -5
-    with pytest.raises(MhdError) as e:
-        mhd_destroy(B.pipes[0]._h)
-    assert e.value.status == -5
+    for call in (lambda h: mhd_step(h, 1), mhd_destroy, lambda h: mhd_tune(h, 1)):
+        with pytest.raises(MhdError) as e:
+            call(B.pipes[0]._h)
+        assert e.value.status == -5
     B.close()
 
 

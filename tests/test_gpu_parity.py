@@ -546,6 +546,9 @@ def test_argument_checks():
     with pytest.raises(MhdError) as e:
         sim.step(1)
     assert e.value.status == _abi.MHD_ERR_STATE
+    with pytest.raises(MhdError) as e:  # the tuner needs parameters too
+        sim.tune(1)
+    assert e.value.status == _abi.MHD_ERR_STATE
     for over, st in ((dict(nu=0.5, gamma=2.0), _abi.MHD_ERR_UNSUPPORTED), (dict(nu=0.0), _abi.MHD_ERR_INVALID_ARG),
                      (dict(n_mag=0), _abi.MHD_ERR_INVALID_ARG), (dict(eta=-1.0), _abi.MHD_ERR_INVALID_ARG),
                      (dict(alpha=0.4), _abi.MHD_ERR_INVALID_ARG)):

@@ -255,7 +255,10 @@ def make_params(src=None, **over) -> mhd_params:
 
 
 class Sim:
-    """One periodic box with an immersed pipe wall, stepped on the current torch CUDA stream."""
+    """One periodic box with an immersed pipe wall, stepped on a torch CUDA stream of its own
+    unless one is given (steps on such a stream replay as captured HIP graphs; the NULL stream
+    cannot be captured). `get_field` and `budgets` synchronise with it; use
+    `torch.cuda.synchronize()` before timing or before reading its results by other means."""
 
     def __init__(self, nx: int, ny: int, nz: int, n_markers: int = 0, *, rho_storage="f32",
                  u_storage="f32", b_storage="f32", u_scale: float = 1.0, b_scale: float = 1.0,
@@ -275,9 +278,11 @@ class Sim:
 
         nbytes = mhd_workspace_size(self.desc, self.n_markers)
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self._stream = stream if stream is not None else torch.cuda.current_stream(dev)
-        # 256-byte aligned workspace carved out of one uint8 tensor
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        # 256-byte aligned workspace carved out of one uint8 tensor; the allocation is ordered on
+        # torch's current stream, the solver's stream may differ
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize(dev)
         base = self._ws.data_ptr()
         self._ptr = (base + 255) & ~255
         self.workspace_bytes = nbytes

@@ -233,8 +233,9 @@ mhd_status mhd_destroy(mhd_sim *s);
  * tiles[2] = 1 for two x cells per lane with 128-cell x tiles (used only when nx is a multiple
  * of 128), tiles[3] = rows per workgroup of that form (4 or 8). Results do not depend on the
  * choice beyond float32 rounding of contracted multiply-adds. Default: the widest x tile the box
- * fills, the paired form when it applies, 4 rows, and the longest z chunk of 64, 32 or 16 planes
- * that leaves 512 workgroups (paired float32 sweep) or 2048 (other forms), else 8. */
+ * fills, the paired form when it applies, and the longest z chunk of 64, 32 or 16 planes that
+ * leaves 512 workgroups (paired float32 sweep) or 2048 (other forms), else 8; rows 4, or 8 for
+ * paired float32 chunks of 32 planes or more when 256 workgroups remain. */
 mhd_status mhd_get_tiles(mhd_sim *s, int32_t tiles[4]);
 mhd_status mhd_set_tiles(mhd_sim *s, const int32_t tiles[4]);
 

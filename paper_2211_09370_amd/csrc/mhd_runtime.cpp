@@ -517,9 +517,10 @@ int64_t sweep_workgroups(const SweepLaunch &L, int nx, int ny, int nz) {
 // which costs HBM traffic on large boxes, while small boxes need short chunks for enough
 // workgroups. The chunk is the longest of 64, 32, 16 planes that still gives 512 workgroups
 // (two per CU) for the paired float32 sweep, 2048 for the other forms, else 8 planes. Measured
-// per sweep: 512 x 256^2 float32 353 -> 283 us (64 planes), split form 282 -> 252 us (32);
-// 256^3 171 -> 140 us (64); 200^3 single-cell tiles 102 -> 96 us (16); 128^3 stays at 8
-// (20 us; 16 planes, one workgroup per CU: 26 us).
+// per sweep: 512 x 256^2 float32 353 -> 283 us (64 planes; 272 us with 8-row tiles), split
+// form 282 -> 252 us (32); 256^3 171 -> 140 us (64; 136 us with 8 rows); 200^3 single-cell
+// tiles 102 -> 96 us (16); 128^3 stays at 8 planes and 4 rows (19 us; 16 planes, one
+// workgroup per CU: 26 us; 8 rows: 20 us).
 SweepLaunch default_tiles(const mhd_grid_desc &g) {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     SweepLaunch L;
@@ -538,6 +539,13 @@ SweepLaunch default_tiles(const mhd_grid_desc &g) {
             L.zchunk = zc;
             break;
         }
+    }
+    // long chunks of the paired float32 sweep: 8-row tiles when that still leaves 256
+    // workgroups (the same 2048 waves); 2-4% shorter sweeps on 128 x 256^2 to 512 x 256^2 boxes
+    if (plain_pair && L.zchunk >= 32 && env_int("MHD_SWEEP_PAIR_TY", 0) == 0) {
+        SweepLaunch t = L;
+        t.ty = 8;
+        if (sweep_workgroups(t, nx, ny, nz) >= 256) L.ty = 8;
     }
     L.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", L.zchunk));
     return L;

@@ -365,7 +365,11 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
 // row from LDS with two aligned 8-byte reads serving both of its cells. The arithmetic shares
 // work between the two cells (differences against one reference, shared column sums, weights
 // with kappa and the relaxation folded in), so it rounds differently from k_mag_sweep at the
-// float32 level.
+// float32 level. Single boxes with n_x = 128 (XWRAP: one tile spans the periodic row) stage no
+// halo columns: a lane reads its own two cells with one 8-byte LDS read and takes x-1 and x+2
+// from the neighbouring lanes by wave rotation, the ends wrapping as the row does. The values
+// are the same, so the results are bit for bit those of the halo form (which the batch keeps,
+// since one of its launches can mix pipes of different n_x).
 // -------------------------------------------------------------------------------------------
 template <typename T>
 struct Pair;
@@ -396,12 +400,25 @@ struct Pair<__hip_bfloat16> {
     }
 };
 
-template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ, bool Q27>
+// Neighbouring lane's value across the whole wave (DPP wave rotation): lane l receives the value
+// of lane l - 1 (ror) or l + 1 (rol), lane 0 that of lane 63 and lane 63 that of lane 0.
+__device__ __forceinline__ float wave_ror1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_rol1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+}
+
+template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ, bool Q27, bool XWRAP>
 __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
                                                             int which, int nbatch) {
     using LW = Lat<Q27>;
     constexpr int HY = TY + 2;        // staged rows
-    constexpr int RS = 132;           // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129
+    // LDS row stride: x0-1 at 0, x0 .. x0+127 at 1 .. 128, x0+128 at 129. XWRAP (n_x = 128, one tile
+    // per row, periodic in x): x0 .. x0+127 at 0 .. 127 and no halo columns; the x neighbours of a
+    // lane's two cells come from the neighbouring lanes, across the wave ends for the wrap.
+    constexpr int RS = 132;
+    constexpr int X0 = XWRAP ? 0 : 1;
     __shared__ __align__(16) float s_pl[2][6][HY * RS];
 
     const int per = gridDim.x >> 3;
@@ -450,15 +467,15 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     // Staging: wave w stages row hy = w (its own pair of cells per lane); the two remaining rows
     // hy = TY, TY + 1 are staged one cell per lane by waves 0 .. 3 (lane -> x = 64 (w & 1) + l),
     // so the staging work is the same on every wave; lanes 0 .. 2*HY-1 of the last wave stage the
-    // halo columns x0 - 1 and x0 + 128.
+    // halo columns x0 - 1 and x0 + 128 (not with XWRAP).
     const int pyr = wrapi(y0 - 1 + w, ny);
     const unsigned poff = (unsigned)(xa + nx * pyr);
     const bool sval = w < 4;
     const int shy = TY + (w >> 1), sxl = ((w & 1) << 6) + l;
     const int syr = wrapi(y0 - 1 + shy, ny);
     const unsigned soff = (unsigned)(x0 + sxl + nx * syr);
-    const int sidx = shy * RS + 1 + sxl;
-    const bool hval = (w == TY - 1) && (l < 2 * HY);
+    const int sidx = shy * RS + X0 + sxl;
+    const bool hval = !XWRAP && (w == TY - 1) && (l < 2 * HY);
     const int hhy = l >> 1, hside = l & 1;
     const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
     const int hyg = wrapi(y0 - 1 + min(hhy, HY - 1), ny);
@@ -566,7 +583,7 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                     eb[q] += tp[q] * ib;
                 }
             }
-            const int idx = w * RS + 1 + 2 * l;
+            const int idx = w * RS + X0 + 2 * l;
             put(S, idx, b[0][0], b[0][1], b[0][2], PU::lo(ru[0], us), PU::lo(ru[1], us), PU::lo(ru[2], us), ea);
             put(S, idx + 1, b[1][0], b[1][1], b[1][2], PU::hi(ru[0], us), PU::hi(ru[1], us), PU::hi(ru[2], us), eb);
         }
@@ -634,12 +651,20 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const float *row = &s_pl[P][k][(w + r) * RS + 2 * l];
-                    const float2 lo = *reinterpret_cast<const float2 *>(row);
-                    const float2 hi = *reinterpret_cast<const float2 *>(row + 2);
-                    v[r][0] = lo.x;
-                    v[r][1] = lo.y;
-                    v[r][2] = hi.x;
-                    v[r][3] = hi.y;
+                    if constexpr (XWRAP) {
+                        const float2 c = *reinterpret_cast<const float2 *>(row);
+                        v[r][0] = wave_ror1(c.y);
+                        v[r][1] = c.x;
+                        v[r][2] = c.y;
+                        v[r][3] = wave_rol1(c.x);
+                    } else {
+                        const float2 lo = *reinterpret_cast<const float2 *>(row);
+                        const float2 hi = *reinterpret_cast<const float2 *>(row + 2);
+                        v[r][0] = lo.x;
+                        v[r][1] = lo.y;
+                        v[r][2] = hi.x;
+                        v[r][3] = hi.y;
+                    }
                 }
             };
             // b components: face and corner sums of differences to each centre, taken against
@@ -825,11 +850,22 @@ static hipError_t sweep_typed(hipStream_t s, const SweepArgs &a, SweepLaunch L, 
                               const BlockMap *map, int which, int nblocks, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(sweep_grid(nblocks));
     if (L.pair) {
+        if constexpr (!BATCH) {
+            if (a.nx == 128) {  // one tile per row: x neighbours by wave rotation
+                if (L.ty >= 8)
+                    hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, false, SPLIT, BYZ, Q27, true>, grid, dim3(512), 0, s, e0, e1,
+                                          0, a, tab, map, which, nblocks);
+                else
+                    hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, false, SPLIT, BYZ, Q27, true>, grid, dim3(256), 0, s, e0, e1,
+                                          0, a, tab, map, which, nblocks);
+                return hipGetLastError();
+            }
+        }
         if (L.ty >= 8)
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<8, TU, TB, BATCH, SPLIT, BYZ, Q27, false>, grid, dim3(512), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
         else
-            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT, BYZ, Q27>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
+            hipExtLaunchKernelGGL(k_mag_sweep_pair<4, TU, TB, BATCH, SPLIT, BYZ, Q27, false>, grid, dim3(256), 0, s, e0, e1, 0, a, tab, map,
                                   which, nblocks);
         return hipGetLastError();
     }

@@ -16,7 +16,9 @@ pytestmark = pytest.mark.gpu
 
 def batch_spec():
     """Six boxes: odd / even sweep counts, the paired sweep form (nx = 128, 256), a box without
-    wall, flow-rate control, an oscillating force, uniform, fringe and six-magnet fields."""
+    wall, flow-rate control, an oscillating force, uniform, fringe and six-magnet fields. Alone,
+    the nx = 128 box takes its x neighbours by wave rotation; in the batch the same kernel stages
+    halo columns, so the bitwise comparison also checks the two forms against each other."""
     a = random_box(8, 32, 32, key=300, n_mag=7, R=12.0)
     b = random_box(32, 32, 32, key=301, n_mag=4, R=13.0, bext_kind=W.BEXT_UNIFORM_Y)
     c = random_box(128, 20, 20, key=302, n_mag=5, R=7.0)

@@ -62,6 +62,18 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// Periodic index of a neighbour one cell away (v in [-1, n]): no integer division.
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Coordinates of cell k of an nx * ny * nz box in 32-bit arithmetic (boxes hold fewer than 2^31
+// values per field).
+__device__ __forceinline__ void cell_xyz(int64_t k, int nx, int ny, int &x, int &y, int &z) {
+    const unsigned ku = (unsigned)k, q = ku / (unsigned)nx, r = q / (unsigned)ny;
+    x = (int)(ku - q * (unsigned)nx);
+    y = (int)(q - r * (unsigned)ny);
+    z = (int)r;
+}
+
 #define W0 (1.0f / 3.0f)
 #define WF (1.0f / 18.0f)
 #define WE (1.0f / 36.0f)

@@ -275,9 +275,8 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const int64_t k = blk * kCellThreads + threadIdx.x;
     if (k >= N) return;
-    const int x = (int)(k % c.nx);
-    const int y = (int)((k / c.nx) % c.ny);
-    const int z = (int)(k / ((int64_t)c.nx * c.ny));
+    int x, y, z;
+    cell_xyz(k, c.nx, c.ny, x, y, z);
     // value of component a at cell i (the split form adds its hi part)
     auto bv = [&](int64_t i) {
         if constexpr (SPLIT)
@@ -290,7 +289,7 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
     for (int i = 0; i < (Q27 ? 26 : 18); ++i) {
         const int ex = c_dir[i][0], ey = c_dir[i][1], ez = c_dir[i][2];
         const float w = 3.0f * dir_weight(i, Q27);
-        const int64_t kn = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
+        const int kn = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
         const float v0 = bv(kn) * bs, v1 = bv(N + kn) * bs, v2 = bv(2 * N + kn) * bs;
         const float e3[3] = {(float)ex, (float)ey, (float)ez};
 #pragma unroll
@@ -378,9 +377,8 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const int64_t k = blk * kCellThreads + threadIdx.x;
     if (k >= N) return;
-    const int x = (int)(k % c.nx);
-    const int y = (int)((k / c.nx) % c.ny);
-    const int z = (int)(k / ((int64_t)c.nx * c.ny));
+    int x, y, z;
+    cell_xyz(k, c.nx, c.ny, x, y, z);
     const float us = c.u_scale;
     if (c.mac) {
         const float ic = c.inv_mac_c, ic2 = ic * ic;
@@ -394,8 +392,8 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         for (int i = 0; i < (Q27 ? 13 : 9); ++i) {
             const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
             const float w = Q27 ? (i < 3 ? 2.0f / 27.0f : i < 9 ? 1.0f / 54.0f : 1.0f / 216.0f) : (i < 3 ? WF : WE);
-            const int64_t kp = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
-            const int64_t km = wrapi(x - ex, c.nx) + (int64_t)c.nx * (wrapi(y - ey, c.ny) + (int64_t)c.ny * wrapi(z - ez, c.nz));
+            const int kp = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
+            const int km = wrap1(x - ex, c.nx) + c.nx * (wrap1(y - ey, c.ny) + c.ny * wrap1(z - ez, c.nz));
             const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
             const float vpx = St<TU>::ld(u, kp) * us * ic, vpy = St<TU>::ld(u, N + kp) * us * ic,
                         vpz = St<TU>::ld(u, 2 * N + kp) * us * ic;
@@ -457,8 +455,8 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
     for (int i = 0; i < (Q27 ? 13 : 9); ++i) {
         const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
         const float w = Q27 ? (i < 3 ? 2.0f / 27.0f : i < 9 ? 1.0f / 54.0f : 1.0f / 216.0f) : (i < 3 ? WF : WE);
-        const int64_t kp = wrapi(x + ex, c.nx) + (int64_t)c.nx * (wrapi(y + ey, c.ny) + (int64_t)c.ny * wrapi(z + ez, c.nz));
-        const int64_t km = wrapi(x - ex, c.nx) + (int64_t)c.nx * (wrapi(y - ey, c.ny) + (int64_t)c.ny * wrapi(z - ez, c.nz));
+        const int kp = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
+        const int km = wrap1(x - ex, c.nx) + c.nx * (wrap1(y - ey, c.ny) + c.ny * wrap1(z - ez, c.nz));
         const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
         const float upx = St<TU>::ld(u, kp) * us, upy = St<TU>::ld(u, N + kp) * us, upz = St<TU>::ld(u, 2 * N + kp) * us;
         const float umx = St<TU>::ld(u, km) * us, umy = St<TU>::ld(u, N + km) * us, umz = St<TU>::ld(u, 2 * N + km) * us;
@@ -534,8 +532,8 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
     const double R2 = c.radius * c.radius;
     double s = 0.0;
     for (int64_t k = (int64_t)blk * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
-        const int y = (int)((k / c.nx) % c.ny);
-        const int z = (int)(k / ((int64_t)c.nx * c.ny));
+        int x, y, z;
+        cell_xyz(k, c.nx, c.ny, x, y, z);
         const double dy = y - c.yc, dz = z - c.zc;
         if (dy * dy + dz * dz <= R2) s += (double)(St<TU>::ld(u, k) * c.u_scale);
     }
@@ -562,9 +560,8 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
     double umax2 = 0.0;
     double nonfin = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
-        const int x = (int)(k % c.nx);
-        const int y = (int)((k / c.nx) % c.ny);
-        const int z = (int)(k / ((int64_t)c.nx * c.ny));
+        int x, y, z;
+        cell_xyz(k, c.nx, c.ny, x, y, z);
         const double r = 1.0 + (double)St<TR>::ld(rho, k);
         double uu[3], bb[3], B[3];
         for (int a = 0; a < 3; ++a) {
@@ -588,8 +585,8 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
         for (int i = 0; i < (q27 ? 26 : 18); ++i) {
             const int e[3] = {c_dir[i][0], c_dir[i][1], c_dir[i][2]};
             const double w = dir_weight_d(i, q27);
-            const int xn = wrapi(x + e[0], c.nx);
-            const int64_t kn = xn + (int64_t)c.nx * (wrapi(y + e[1], c.ny) + (int64_t)c.ny * wrapi(z + e[2], c.nz));
+            const int xn = wrap1(x + e[0], c.nx);
+            const int kn = xn + c.nx * (wrap1(y + e[1], c.ny) + c.ny * wrap1(z + e[2], c.nz));
             const double rn = 1.0 + (double)St<TR>::ld(rho, kn);
             double un[3], bn[3], Bn[3];
             for (int a = 0; a < 3; ++a) {
@@ -598,8 +595,8 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
                 if (bh) bn[a] += (double)St<TB>::ld(bh, a * N + kn) * bs;
                 Bn[a] = bn[a] + (double)bext[a * c.nx + xn];
                 if (bext_yz)
-                    Bn[a] += (double)bext_yz[a * (int64_t)c.ny * c.nz + wrapi(y + e[1], c.ny) +
-                                             (int64_t)c.ny * wrapi(z + e[2], c.nz)];
+                    Bn[a] += (double)bext_yz[a * (int64_t)c.ny * c.nz + wrap1(y + e[1], c.ny) +
+                                             (int64_t)c.ny * wrap1(z + e[2], c.nz)];
             }
             for (int a = 0; a < 3; ++a) {
                 grho[a] += 3.0 * w * e[a] * rn;

@@ -464,17 +464,19 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const float l0f = LW::A0F * ko, l0c = LW::A0C * ko, l1c = LW::A1C * ko, l1f = LW::A1F * ko, l1k = LW::A1K * ko;
     const float w6 = (1.0f / 6.0f) * om;  // total weight of a neighbouring plane (both lattices)
 
-    // Staging: wave w stages row hy = w (its own pair of cells per lane); the two remaining rows
-    // hy = TY, TY + 1 are staged one cell per lane by waves 0 .. 3 (lane -> x = 64 (w & 1) + l),
-    // so the staging work is the same on every wave; lanes 0 .. 2*HY-1 of the last wave stage the
-    // halo columns x0 - 1 and x0 + 128 (not with XWRAP).
+    // Staging: wave w stages row hy = w (its own pair of cells per lane). With 4-row tiles the
+    // two remaining rows hy = TY, TY + 1 are staged as pairs by waves 0 and 1 (fewer memory
+    // instructions); with 8-row tiles one cell per lane by waves 0 .. 3 (lane -> x = 64 (w & 1)
+    // + l), which measured faster there. Lanes 0 .. 2*HY-1 of the last wave stage the halo
+    // columns x0 - 1 and x0 + 128 (not with XWRAP).
     const int pyr = wrapi(y0 - 1 + w, ny);
     const unsigned poff = (unsigned)(xa + nx * pyr);
-    const bool sval = w < 4;
-    const int shy = TY + (w >> 1), sxl = ((w & 1) << 6) + l;
+    constexpr bool SPAIR = TY == 4;
+    const bool sval = SPAIR ? w < 2 : w < 4;
+    const int shy = SPAIR ? TY + min(w, 1) : TY + (w >> 1), sxl = ((w & 1) << 6) + l;
     const int syr = wrapi(y0 - 1 + shy, ny);
-    const unsigned soff = (unsigned)(x0 + sxl + nx * syr);
-    const int sidx = shy * RS + X0 + sxl;
+    const unsigned soff = SPAIR ? (unsigned)(xa + nx * syr) : (unsigned)(x0 + sxl + nx * syr);
+    const int sidx = SPAIR ? shy * RS + X0 + 2 * l : shy * RS + X0 + sxl;
     const bool hval = !XWRAP && (w == TY - 1) && (l < 2 * HY);
     const int hhy = l >> 1, hside = l & 1;
     const int hx = hside ? wrapi(x0 + 128, nx) : wrapi(x0 - 1, nx);
@@ -490,8 +492,8 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
 
     RU ru[3];
     RB rb[3], rq[3];        // pair row (rq: SPLIT hi part)
-    TU su[3];
-    TB sb[3], sq[3];        // single cell
+    std::conditional_t<SPAIR, RU, TU> su[3];
+    std::conditional_t<SPAIR, RB, TB> sb[3], sq[3];  // pair of rows TY, TY + 1, or single cell
     TU hu[3];
     TB hb[3], hq[3];        // halo column
     float tp[3], ts[3], th[3];  // BYZ: B_ext (y, z) part at the pair row, single cell, halo column
@@ -523,17 +525,19 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
             }
         }
         if (sval) {
+            using SU = std::conditional_t<SPAIR, RU, TU>;
+            using SB = std::conditional_t<SPAIR, RB, TB>;
             const unsigned ku = (off + soff) * (unsigned)sizeof(TU), kb = (off + soff) * (unsigned)sizeof(TB);
-            su[0] = ld_off(u0, ku);
-            su[1] = ld_off(u1, ku);
-            su[2] = ld_off(u2, ku);
-            sb[0] = ld_off(b0, kb);
-            sb[1] = ld_off(b1, kb);
-            sb[2] = ld_off(b2, kb);
+            su[0] = ld_off(reinterpret_cast<const SU *>(u0), ku);
+            su[1] = ld_off(reinterpret_cast<const SU *>(u1), ku);
+            su[2] = ld_off(reinterpret_cast<const SU *>(u2), ku);
+            sb[0] = ld_off(reinterpret_cast<const SB *>(b0), kb);
+            sb[1] = ld_off(reinterpret_cast<const SB *>(b1), kb);
+            sb[2] = ld_off(reinterpret_cast<const SB *>(b2), kb);
             if constexpr (SPLIT) {
-                sq[0] = ld_off(bh0, kb);
-                sq[1] = ld_off(bh1, kb);
-                sq[2] = ld_off(bh2, kb);
+                sq[0] = ld_off(reinterpret_cast<const SB *>(bh0), kb);
+                sq[1] = ld_off(reinterpret_cast<const SB *>(bh1), kb);
+                sq[2] = ld_off(reinterpret_cast<const SB *>(bh2), kb);
             }
         }
         if (hval) {
@@ -587,15 +591,41 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
             put(S, idx, b[0][0], b[0][1], b[0][2], PU::lo(ru[0], us), PU::lo(ru[1], us), PU::lo(ru[2], us), ea);
             put(S, idx + 1, b[1][0], b[1][1], b[1][2], PU::hi(ru[0], us), PU::hi(ru[1], us), PU::hi(ru[2], us), eb);
         }
-        if (sval) {
-            float b[3], e[3] = {bes[0], bes[1], bes[2]};
+        if constexpr (SPAIR) {
+            if (sval) {
+                float b[2][3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                b[q] = St<TB>::cvt(sb[q]);
-                if constexpr (SPLIT) b[q] += St<TB>::cvt(sq[q]);
-                if constexpr (BYZ) e[q] += ts[q] * ib;
+                for (int q = 0; q < 3; ++q) {
+                    b[0][q] = PB::lo(sb[q], bs);
+                    b[1][q] = PB::hi(sb[q], bs);
+                    if constexpr (SPLIT) {
+                        b[0][q] += PB::lo(sq[q], bs);
+                        b[1][q] += PB::hi(sq[q], bs);
+                    }
+                }
+                float ea[3] = {bea[0], bea[1], bea[2]}, eb[3] = {beb[0], beb[1], beb[2]};
+                if constexpr (BYZ) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        ea[q] += ts[q] * ib;
+                        eb[q] += ts[q] * ib;
+                    }
+                }
+                put(S, sidx, b[0][0], b[0][1], b[0][2], PU::lo(su[0], us), PU::lo(su[1], us), PU::lo(su[2], us), ea);
+                put(S, sidx + 1, b[1][0], b[1][1], b[1][2], PU::hi(su[0], us), PU::hi(su[1], us), PU::hi(su[2], us),
+                    eb);
             }
-            put(S, sidx, b[0], b[1], b[2], St<TU>::cvt(su[0]), St<TU>::cvt(su[1]), St<TU>::cvt(su[2]), e);
+        } else {
+            if (sval) {
+                float b[3], e[3] = {bes[0], bes[1], bes[2]};
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    b[q] = St<TB>::cvt(sb[q]);
+                    if constexpr (SPLIT) b[q] += St<TB>::cvt(sq[q]);
+                    if constexpr (BYZ) e[q] += ts[q] * ib;
+                }
+                put(S, sidx, b[0], b[1], b[2], St<TU>::cvt(su[0]), St<TU>::cvt(su[1]), St<TU>::cvt(su[2]), e);
+            }
         }
         if (hval) {
             float b[3], e[3] = {hbe[0], hbe[1], hbe[2]};

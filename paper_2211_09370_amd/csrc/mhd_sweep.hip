@@ -369,7 +369,9 @@ __global__ void __launch_bounds__(TX *TY) k_mag_sweep(SweepArgs a, const PipeSte
 // halo columns: a lane reads its own two cells with one 8-byte LDS read and takes x-1 and x+2
 // from the neighbouring lanes by wave rotation, the ends wrapping as the row does. The values
 // are the same, so the results are bit for bit those of the halo form (which the batch keeps,
-// since one of its launches can mix pipes of different n_x).
+// since one of its launches can mix pipes of different n_x). In float32 this form also stages
+// by 16-byte loads, four cells per lane and two rows per wave, which halves the load
+// instructions of a plane.
 // -------------------------------------------------------------------------------------------
 template <typename T>
 struct Pair;
@@ -464,7 +466,8 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const float l0f = LW::A0F * ko, l0c = LW::A0C * ko, l1c = LW::A1C * ko, l1f = LW::A1F * ko, l1k = LW::A1K * ko;
     const float w6 = (1.0f / 6.0f) * om;  // total weight of a neighbouring plane (both lattices)
 
-    // Staging: wave w stages row hy = w (its own pair of cells per lane). With 4-row tiles the
+    // Staging (float32 with XWRAP: QUAD below, 16-byte loads staging two rows per wave): wave w
+    // stages row hy = w (its own pair of cells per lane). With 4-row tiles the
     // two remaining rows hy = TY, TY + 1 are staged as pairs by waves 0 and 1 (fewer memory
     // instructions); with 8-row tiles one cell per lane by waves 0 .. 3 (lane -> x = 64 (w & 1)
     // + l), which measured faster there. Lanes 0 .. 2*HY-1 of the last wave stage the halo
@@ -489,6 +492,21 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     const int xs = x0 + sxl;
     const float bes[3] = {a.bext[xs] * ib, a.bext[nx + xs] * ib, a.bext[2 * nx + xs] * ib};
     const float hbe[3] = {a.bext[hx] * ib, a.bext[nx + hx] * ib, a.bext[2 * nx + hx] * ib};
+    // QUAD (float32 with XWRAP): staging by 16-byte loads, wave w < HY/2 staging rows 2w (lanes
+    // 0 .. 31) and 2w + 1 (lanes 32 .. 63), four cells per lane
+    constexpr bool QUAD = XWRAP && std::is_same<TU, float>::value && std::is_same<TB, float>::value;
+    const int qhy = min(2 * w + (l >> 5), HY - 1), qxl = 4 * (l & 31);
+    const bool qval = QUAD && w < HY / 2;
+    const int qyr = wrapi(y0 - 1 + qhy, ny);
+    const unsigned qoff = (unsigned)(x0 + qxl + nx * qyr);
+    const int qidx = qhy * RS + X0 + qxl;
+    float qbe[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) qbe[c][i] = QUAD ? a.bext[c * nx + x0 + qxl + i] * ib : 0.0f;
+    float4 qu[3], qb[3];
+    float tq[3];
 
     RU ru[3];
     RB rb[3], rq[3];        // pair row (rq: SPLIT hi part)
@@ -508,8 +526,20 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                 tp[q] = a.bext_yz[q * pyz + op];
                 ts[q] = a.bext_yz[q * pyz + os];
                 th[q] = a.bext_yz[q * pyz + oh];
+                if constexpr (QUAD) tq[q] = a.bext_yz[q * pyz + (unsigned)(qyr + ny * zz)];
             }
         }
+        if constexpr (QUAD) {
+            if (qval) {
+                const unsigned kq = (off + qoff) * (unsigned)sizeof(float);
+                qu[0] = ld_off(reinterpret_cast<const float4 *>(u0), kq);
+                qu[1] = ld_off(reinterpret_cast<const float4 *>(u1), kq);
+                qu[2] = ld_off(reinterpret_cast<const float4 *>(u2), kq);
+                qb[0] = ld_off(reinterpret_cast<const float4 *>(b0), kq);
+                qb[1] = ld_off(reinterpret_cast<const float4 *>(b1), kq);
+                qb[2] = ld_off(reinterpret_cast<const float4 *>(b2), kq);
+            }
+        } else {
         {
             const unsigned ku = (off + poff) * (unsigned)sizeof(TU), kb = (off + poff) * (unsigned)sizeof(TB);
             ru[0] = ld_off(reinterpret_cast<const RU *>(u0), ku);
@@ -540,6 +570,7 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                 sq[2] = ld_off(reinterpret_cast<const SB *>(bh2), kb);
             }
         }
+        }
         if (hval) {
             const unsigned ku = (off + hoff) * (unsigned)sizeof(TU), kb = (off + hoff) * (unsigned)sizeof(TB);
             hu[0] = ld_off(u0, ku);
@@ -568,6 +599,23 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
     auto stage = [&](auto bufc) {
         constexpr int S = decltype(bufc)::value;
         constexpr float us = 1.0f, bs = 1.0f;  // stored units
+        if constexpr (QUAD) {
+            if (qval) {
+                const float ub[3][4] = {{qu[0].x, qu[0].y, qu[0].z, qu[0].w}, {qu[1].x, qu[1].y, qu[1].z, qu[1].w},
+                                        {qu[2].x, qu[2].y, qu[2].z, qu[2].w}};
+                const float bb[3][4] = {{qb[0].x, qb[0].y, qb[0].z, qb[0].w}, {qb[1].x, qb[1].y, qb[1].z, qb[1].w},
+                                        {qb[2].x, qb[2].y, qb[2].z, qb[2].w}};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float e[3] = {qbe[0][i], qbe[1][i], qbe[2][i]};
+                    if constexpr (BYZ) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) e[q] += tq[q] * ib;
+                    }
+                    put(S, qidx + i, bb[0][i], bb[1][i], bb[2][i], ub[0][i], ub[1][i], ub[2][i], e);
+                }
+            }
+        } else {
         {
             float b[2][3];
 #pragma unroll
@@ -626,6 +674,7 @@ __global__ void __launch_bounds__(64 * TY) k_mag_sweep_pair(SweepArgs a, const P
                 }
                 put(S, sidx, b[0], b[1], b[2], St<TU>::cvt(su[0]), St<TU>::cvt(su[1]), St<TU>::cvt(su[2]), e);
             }
+        }
         }
         if (hval) {
             float b[3], e[3] = {hbe[0], hbe[1], hbe[2]};

@@ -619,3 +619,34 @@ def test_tune_keeps_the_state_and_parity(store):
     sim.step(2)
     compare(sim, oracle_run(w, 3), tol=TOL if not store else 2e-3, label=f"tuned {t}")
     sim.close()
+
+
+@pytest.mark.parametrize("bext", [W.BEXT_TANH_FRINGE_Y, W.BEXT_SIX_MAGNETS])
+def test_paired_tiles_agree_bitwise_on_a_128_wide_box(bext):
+    """The paired sweep's per-cell arithmetic does not depend on the tile, so 4- and 8-row tiles
+    and any z chunk give the same fields bit for bit (on an n_x = 128 box the float32 form takes
+    the x neighbours by wave rotation and stages by 16-byte loads; 26 rows leave a ragged last
+    tile). The first choice is also checked against the oracle."""
+    from paper_2211_09370_amd import Sim
+
+    print("case paired tiles", bext, flush=True)
+    w = W.pipe_workload("tiles128", 18, 128, 26, 21, 8.0, 50.0, 10.0, 1e-2, bext_kind=bext,
+                        fringe_x0=64.0, fringe_w=4.0, n_mag=5, noise=1e-2, rho_amp=1e-3, b_amp=1e-3)
+    ref = None
+    for tiles in [(64, 8, 1, 4), (64, 8, 1, 8), (64, 16, 1, 8), (64, 4, 1, 4), (64, 32, 1, 4)]:
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+        sim.set_markers(w.markers)
+        sim.set_params(w.params)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.tiles = tiles
+        sim.step(3)
+        got = [sim.get_field(f) for f in ("rho", "u", "b")]
+        if ref is None:
+            ref = got
+            compare(sim, oracle_run(w, 3), tol=TOL, label=f"tiles {tiles}")
+        else:
+            for f, x, y in zip(("rho", "u", "b"), ref, got):
+                assert np.array_equal(x, y), (tiles, f, float(np.abs(x - y).max()))
+        sim.close()

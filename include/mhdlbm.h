@@ -34,9 +34,9 @@ typedef int32_t mhd_status;
 #define MHD_ERR_INVALID_ARG (-1) /* argument out of range or inconsistent                   */
 #define MHD_ERR_OOM (-2)         /* workspace too small / host allocation failed            */
 #define MHD_ERR_HIP (-3)         /* a HIP runtime call failed (message names it)            */
-#define MHD_ERR_UNSTABLE (-4)    /* non-finite state or |u| >= c_s found by a budget pass
-                                    (c_s = 1/sqrt(3); 6 nu / sqrt(3) on the macroscopic
-                                    fluid branch)                                           */
+#define MHD_ERR_UNSTABLE (-4)    /* non-finite state or |u| >= c_s found by the fluid update
+                                    of any step or by a budget pass (c_s = 1/sqrt(3);
+                                    6 nu / sqrt(3) on the macroscopic fluid branch)         */
 #define MHD_ERR_STATE (-5)       /* call out of order (e.g. step before params/markers)     */
 #define MHD_ERR_UNSUPPORTED (-6) /* valid request outside this build (e.g. gamma != 1 with
                                     tau >= 1)                                               */
@@ -118,12 +118,16 @@ typedef struct {
                              does not depend on gamma and a transient takes gamma times as many
                              steps. <= 0 or 1: no rescaling. The magnetic iteration is unchanged
                              (quasi-static: it has no time step).                             */
+    double omega_radius;  /* radius of the budget region Omega = {(y-yc)^2 + (z-zc)^2 <
+                             omega_radius^2}; <= 0 -> avg_radius - 2 (inside the band the wall
+                             kernel touches). avg_radius selects the whole conductor, where the
+                             steady power balance P_in = -P_nu + D_eta holds (Sec. 4).        */
 } mhd_params;
 
 typedef enum { MHD_FIELD_RHO = 0, MHD_FIELD_U = 1, MHD_FIELD_B_INDUCED = 2 } mhd_field;
 
 /* One budget record (Sec. 4 energy balance): averages over Omega = {(y-yc)^2 + (z-zc)^2 <
- * (R-2)^2} of E_k = <rho |u|^2 / 2>, E_m = <|B|^2 / 2> (B = B_ext + b), E_b = <|b|^2 / 2>,
+ * R_omega^2} (R_omega = omega_radius, default R - 2) of E_k = <rho |u|^2 / 2>, E_m = <|B|^2 / 2> (B = B_ext + b), E_b = <|b|^2 / 2>,
  * P_in = G <u_x>, P_p = -<u . grad(rho/3)>, P_nu = nu <u . lap u>, P_L = <u . (J x B)>,
  * M_eta = eta <B . lap b>, M_adv = -<B . div(u B - B u)>, joule = eta <|J|^2>; plus
  * mass = sum of rho over the box, Q = (1/nx) sum over r <= R of u_x, u_max = max |u|.
@@ -136,6 +140,10 @@ typedef struct {
     double res_mag; /* induction residual (Sec. 5.8 eq. "Error l2 decay"): root mean square
                        over Omega of |eta lap b - div(u B - B u)|; the paper normalises it by
                        its value at the first iteration                                      */
+    double D_eta;   /* Joule dissipation in lattice Dirichlet form, -eta <b . lap b> (equal to
+                       eta <|J|^2> for a divergence-free b vanishing on the boundary of Omega;
+                       with -P_nu, the viscous dissipation in the same form, a steady state over
+                       the conductor satisfies P_in = -P_nu + D_eta and -P_L = D_eta)        */
 } mhd_budget;
 
 typedef struct mhd_sim mhd_sim;
@@ -171,7 +179,9 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p);
 
 /* Copy a field in / out (host float64, layout above; rho has 1 component, u and b 3).
  * Synchronous with respect to the host buffer. mhd_get_field also reports a deferred
- * MHD_ERR_UNSTABLE (the data is still copied). */
+ * MHD_ERR_UNSTABLE: set by the fluid update of any step whose new velocity at some cell is
+ * non-finite or has |u| >= c_s, or by a budget pass, whatever budget_every is (the data is
+ * still copied; the flag stays set for the life of the solver). */
 mhd_status mhd_set_field(mhd_sim *s, mhd_field f, const double *host);
 mhd_status mhd_get_field(mhd_sim *s, mhd_field f, double *host);
 
@@ -194,8 +204,8 @@ mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every);
 mhd_status mhd_set_graph(mhd_sim *s, int32_t enable);
 
 /* Synchronise the stream and move the budget records taken since the last call (oldest first,
- * at most cap) to out. Returns MHD_ERR_UNSTABLE if a record found non-finite values or
- * |u| >= 1/sqrt(3) (the records are still returned). */
+ * at most cap) to out. Returns MHD_ERR_UNSTABLE if a fluid step or a record found non-finite
+ * values or |u| >= c_s (the records are still returned). */
 mhd_status mhd_get_budgets(mhd_sim *s, mhd_budget *out, int64_t cap, int64_t *n_out);
 
 /* Take one budget record of the current state now (asynchronous). */

@@ -15,7 +15,8 @@ Functions and the passage each follows:
                  (Sec. 7); for tau >= 1 the macroscopic tau = 1 update with speed 6 nu (Sec. 5.7)
   fluid_tau    - tau = 3 nu / gamma + 1/2 (Sec. 7)
   Oracle.step  - whole step in the order of Sec. 5.7 (magnetic iteration, then velocity)
-  budgets      - energy budget averages of Sec. 4 over r < R - 2, mass, flow rate
+  budgets      - energy budget averages of Sec. 4 over r < R_omega (default R - 2), mass, flow
+                 rate, and the Joule dissipation in lattice Dirichlet form
 """
 from __future__ import annotations
 
@@ -30,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 BUDGET_NAMES = ("E_k", "E_m", "E_b", "P_in", "P_p", "P_nu", "P_L", "M_eta", "M_adv", "joule",
-                "mass", "Q", "u_max", "n_omega", "G", "nonfinite", "res_mag")
+                "mass", "Q", "u_max", "n_omega", "G", "nonfinite", "res_mag", "D_eta")
 
 
 class OrcParams(C.Structure):
@@ -43,7 +44,7 @@ class OrcParams(C.Structure):
                 ("radius", C.c_double), ("flow_control", C.c_int), ("u_target", C.c_double),
                 ("k_c", C.c_double), ("ib_u", C.c_int), ("ib_b", C.c_int),
                 ("alpha", C.c_double), ("magnet_L", C.c_double), ("magnet_D", C.c_double),
-                ("lattice", C.c_int), ("gamma", C.c_double)]
+                ("lattice", C.c_int), ("gamma", C.c_double), ("omega_radius", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -99,7 +100,7 @@ def make_params(nx, ny, nz, prm=None, *, ib_u=1, ib_b=1, **over) -> OrcParams:
     fields = dict(nu=0.1, eta=1.0, n_mag=1, lambda_u=1.0, lambda_b=0.0, G0=0.0, G1=0.0, period=0.0,
                   bext_kind=0, B0=0.0, fringe_x0=0.0, fringe_w=1.0, yc=0.0, zc=0.0, radius=0.0,
                   flow_control=0, u_target=0.0, k_c=0.1, alpha=1.0, magnet_L=0.0, magnet_D=0.0,
-                  lattice=19, gamma=1.0)
+                  lattice=19, gamma=1.0, omega_radius=0.0)
     if prm is not None:
         for k in list(fields):
             src = {"radius": "avg_radius", "u_target": "u_bulk_target"}.get(k, k)

@@ -69,6 +69,7 @@ typedef struct {
                                   of the strip centres from the axis (<= 0: see magnet_geometry) */
     int lattice;    /* 27: D3Q27 (the paper's set, Table I); otherwise D3Q19 */
     double gamma;   /* time-step rescaling of Sec. 7 (dt -> dt / gamma); <= 0 means 1 */
+    double omega_radius; /* budget region Omega = {r < omega_radius}; <= 0 means radius - 2 */
 } orc_params;
 
 /* D3Q19 velocity set and weights (textbook values). */
@@ -684,18 +685,25 @@ void orc_step(orc_ctx *c, double *rho, double *u, double *b, int64_t n, int64_t 
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Energy budgets (Sec. 4): averages over Omega = {r < R - 2}                                 */
-/* out[0..15] = E_k, E_m, E_b, P_in, P_p, P_nu, P_L, M_eta, M_adv, joule, mass, Q, u_max,       */
-/*              n_omega, G, nonfinite                                                         */
+/* Energy budgets (Sec. 4): averages over Omega = {r < R_omega}, R_omega = omega_radius, or   */
+/* R - 2 (inside the band the wall kernel touches) when omega_radius <= 0                     */
+/* out[0..17] = E_k, E_m, E_b, P_in, P_p, P_nu, P_L, M_eta, M_adv, joule, mass, Q, u_max,       */
+/*              n_omega, G, nonfinite, res_mag, D_eta                                         */
+/* D_eta = -eta <b . lap b>: the Joule dissipation eta <|J|^2> written as the lattice Dirichlet */
+/* form (equal to it for a divergence-free b that vanishes on the boundary of Omega), so that */
+/* with -P_nu (the viscous dissipation in the same form) the steady power balance             */
+/* P_in = -P_nu + D_eta closes over the conductor.                                            */
 /* ------------------------------------------------------------------------------------------ */
 void orc_budgets(const orc_params *p, const double *rho, const double *u, const double *b, double G,
                  double *out) {
     const int64_t N = ncells(p);
     double Ek = 0, Em = 0, Eb = 0, Pin = 0, Pp = 0, Pnu = 0, PL = 0, Meta = 0, Madv = 0, Jl = 0, Res = 0;
+    double Deta = 0;
     double mass = 0, Q = 0, umax2 = 0;
     int64_t nom = 0;
     int nonfinite = 0;
-    const double Ro = p->radius - 2.0, Ro2 = Ro * Ro, R2 = p->radius * p->radius;
+    const double Ro = p->omega_radius > 0.0 ? p->omega_radius : p->radius - 2.0;
+    const double Ro2 = Ro * Ro, R2 = p->radius * p->radius;
     double *prs = (double *)malloc((size_t)N * sizeof(double));
     double *lam = (double *)malloc((size_t)(9 * N) * sizeof(double)); /* Lambda_ac = u_c B_a - B_c u_a */
     for (int z = 0; z < p->nz; ++z)
@@ -752,6 +760,7 @@ void orc_budgets(const orc_params *p, const double *rho, const double *u, const 
                     /* Sec. 5.8 eq. "Error l2 decay": eta lap b - div(u B - B u) */
                     Res += (p->eta * lapb - div) * (p->eta * lapb - div);
                     Jl += p->eta * J[a] * J[a];
+                    Deta += -p->eta * bb[a] * lapb;
                 }
             }
     free(prs);
@@ -774,6 +783,7 @@ void orc_budgets(const orc_params *p, const double *rho, const double *u, const 
     out[14] = G;
     out[15] = (double)nonfinite;
     out[16] = sqrt(Res * inv); /* root mean square over Omega of the induction residual */
+    out[17] = Deta * inv;
 }
 
 int orc_num_threads(void) {

@@ -56,7 +56,7 @@ class mhd_params(C.Structure):
                 ("flow_control", C.c_int32), ("lattice", C.c_int32),
                 ("u_bulk_target", C.c_double), ("k_c", C.c_double), ("alpha", C.c_double),
                 ("magnet_half_width", C.c_double), ("magnet_distance", C.c_double),
-                ("gamma", C.c_double)]
+                ("gamma", C.c_double), ("omega_radius", C.c_double)]
 
 
 class mhd_budget(C.Structure):
@@ -65,7 +65,7 @@ class mhd_budget(C.Structure):
                 ("P_nu", C.c_double), ("P_L", C.c_double), ("M_eta", C.c_double),
                 ("M_adv", C.c_double), ("joule", C.c_double), ("mass", C.c_double),
                 ("Q", C.c_double), ("u_max", C.c_double), ("n_omega", C.c_double),
-                ("res_mag", C.c_double)]
+                ("res_mag", C.c_double), ("D_eta", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)

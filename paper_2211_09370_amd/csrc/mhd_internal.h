@@ -29,7 +29,9 @@ struct StepConst {
     float inv_gamma;   // 1 / gamma of the rescaled fluid update (1: none)
     int mac;           // 1: macroscopic tau = 1 fluid update with particle speed mac_c = 6 nu
     float mac_c, inv_mac_c;
-    double u_limit2;   // |u|^2 at or above which a budget pass flags the state (c_s^2)
+    double u_limit2;   // |u|^2 at or above which the state is flagged unstable (c_s^2)
+    int32_t *status;   // the box's DevCtrl::status: the fluid update stores 1 there when a new
+                       // velocity is non-finite or reaches c_s
     float u_scale, inv_u_scale, b_scale, inv_b_scale;
     float copy_scale, inv_copy_scale;  // split form: scale of the float16 copy of u
     float omega;                       // 1 / alpha of the accelerated magnetic iteration
@@ -37,13 +39,14 @@ struct StepConst {
     double nu, eta;
     double G0, G1, period;
     double yc, zc, radius;
+    double omega_radius;  // budget region r < omega_radius
     int flow_control;
     double u_target, k_c;
 };
 
 constexpr int kRedBlocks = 1024;   // fixed grid of the float64 reductions (fixed summation order)
 constexpr int kRedThreads = 256;
-constexpr int kBudgetVals = 16;    // per-block partial sums of a budget pass
+constexpr int kBudgetVals = 17;    // per-block partial sums of a budget pass
 constexpr int kRingCap = 4096;     // budget records held on the device
 constexpr int kResCap = 4096;      // residual values of one mhd_mag_residual_curve call
 

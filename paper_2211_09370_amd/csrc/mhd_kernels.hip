@@ -432,6 +432,9 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         const float un0 = cu * (vx0 + ((m0 + px0) - dr * vx0) * inv);
         const float un1 = cu * (vy0 + ((m1 + py0) - dr * vy0) * inv);
         const float un2 = cu * (vz0 + ((m2 + pz0) - dr * vz0) * inv);
+        // blow-up: a non-finite or supersonic velocity marks the box (every such lane stores the
+        // same value, so the plain store needs no atomic)
+        if (!((double)(un0 * un0 + un1 * un1 + un2 * un2) < c.u_limit2) || !(dnew == dnew)) *c.status = 1;
         St<TU>::st(u_o, k, un0 * c.inv_u_scale);
         St<TU>::st(u_o, N + k, un1 * c.inv_u_scale);
         St<TU>::st(u_o, 2 * N + k, un2 * c.inv_u_scale);
@@ -498,6 +501,9 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
     St<TR>::st(rho_o, k, dnew);
     const float un0 = ux0 + (Dm0 - dr * ux0) * inv, un1 = uy0 + (Dm1 - dr * uy0) * inv,
                 un2 = uz0 + (Dm2 - dr * uz0) * inv;
+    // blow-up: a non-finite or supersonic velocity marks the box (plain store of the same value
+    // from every such lane, no atomic)
+    if (!((double)(un0 * un0 + un1 * un1 + un2 * un2) < c.u_limit2) || !(dnew == dnew)) *c.status = 1;
     St<TU>::st(u_o, k, un0 * c.inv_u_scale);
     St<TU>::st(u_o, N + k, un1 * c.inv_u_scale);
     St<TU>::st(u_o, 2 * N + k, un2 * c.inv_u_scale);
@@ -544,19 +550,20 @@ __global__ void __launch_bounds__(kRedThreads) k_flow_partial(const TU *u, doubl
 
 // partial layout: 0 Ek, 1 Em, 2 Eb, 3 sum u_x (Omega), 4 Pp, 5 Pnu/nu, 6 PL, 7 Meta/eta, 8 Madv,
 // 9 sum |J|^2, 10 mass, 11 Q sum, 12 n_omega, 13 sum |eta lap b - div(uB - Bu)|^2 (the induction
-// residual of Sec. 5.8), 14 max |u|^2, 15 nonfinite
+// residual of Sec. 5.8), 14 sum b . lap b (Joule dissipation in Dirichlet form, times -eta),
+// 15 max |u|^2, 16 nonfinite
 template <typename TR, typename TU, typename TB>
 __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, const TU *u, const TB *b,
                                                                 const TB *bh, const float *bext,
                                                                 const float *bext_yz, double *part, StepConst c) {
-    __shared__ double sh[16][kRedWaves];
+    __shared__ double sh[17][kRedWaves];
     const int64_t N = (int64_t)c.nx * c.ny * c.nz;
     const double us = c.u_scale, bs = c.b_scale;
     const double R2 = c.radius * c.radius;
-    const double Ro = c.radius - 2.0, Ro2 = Ro * Ro;
-    double v[14];
+    const double Ro2 = c.omega_radius * c.omega_radius;
+    double v[15];
 #pragma unroll
-    for (int q = 0; q < 14; ++q) v[q] = 0.0;
+    for (int q = 0; q < 15; ++q) v[q] = 0.0;
     double umax2 = 0.0;
     double nonfin = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < N; k += (int64_t)kRedBlocks * kRedThreads) {
@@ -625,35 +632,36 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_partial(const TR *rho, c
             v[9] += J[a] * J[a];
             const double res = c.eta * lb[a] - divL[a];
             v[13] += res * res;
+            v[14] += bb[a] * lb[a];
         }
     }
-    // the 14 sums, max |u|^2 and "any non-finite" in the same fixed order
+    // the 15 sums, max |u|^2 and "any non-finite" in the same fixed order
     double mx[2] = {umax2, nonfin};
-    block_reduce<14, 2>(sh, v, mx);
+    block_reduce<15, 2>(sh, v, mx);
     if (threadIdx.x == 0) {
         double *o = part + (int64_t)blockIdx.x * kBudgetVals;
-        for (int q = 0; q < 14; ++q) o[q] = v[q];
-        o[14] = mx[0];
-        o[15] = mx[1];
+        for (int q = 0; q < 15; ++q) o[q] = v[q];
+        o[15] = mx[0];
+        o[16] = mx[1];
     }
 }
 
 __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part, DevCtrl *ctrl, mhd_budget *ring,
                                                               StepConst c) {
-    __shared__ double sh[16][kRedWaves];
-    double v[14];
+    __shared__ double sh[17][kRedWaves];
+    double v[15];
 #pragma unroll
-    for (int q = 0; q < 14; ++q) v[q] = 0.0;
+    for (int q = 0; q < 15; ++q) v[q] = 0.0;
     double m = 0.0, f = 0.0;
     for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) {
         const double *p = part + (int64_t)i * kBudgetVals;
 #pragma unroll
-        for (int q = 0; q < 14; ++q) v[q] += p[q];
-        m = fmax(m, p[14]);
-        f = fmax(f, p[15]);
+        for (int q = 0; q < 15; ++q) v[q] += p[q];
+        m = fmax(m, p[15]);
+        f = fmax(f, p[16]);
     }
     double mx[2] = {m, f};
-    block_reduce<14, 2>(sh, v, mx);
+    block_reduce<15, 2>(sh, v, mx);
     if (threadIdx.x == 0) {
         const double n = v[12];
         const double inv = n > 0.0 ? 1.0 / n : 0.0;
@@ -675,6 +683,7 @@ __global__ void __launch_bounds__(kRedThreads) k_budget_final(const double *part
         r.u_max = sqrt(mx[0]);
         r.n_omega = n;
         r.res_mag = sqrt(v[13] * inv);
+        r.D_eta = -c.eta * v[14] * inv;
         // |u| >= c_s or a non-finite value marks the run unstable
         if (mx[1] != 0.0 || !(mx[0] < c.u_limit2) || !isfinite(v[0])) ctrl->status |= 1;
         const int idx = ctrl->n_records;

@@ -20,8 +20,8 @@ using namespace mhd;
 
 // The Python binding mirrors these structs field by field (tests check the same sizes).
 static_assert(sizeof(mhd_grid_desc) == 40, "mhd_grid_desc layout");
-static_assert(sizeof(mhd_params) == 168, "mhd_params layout");
-static_assert(sizeof(mhd_budget) == 136, "mhd_budget layout");
+static_assert(sizeof(mhd_params) == 176, "mhd_params layout");
+static_assert(sizeof(mhd_budget) == 144, "mhd_budget layout");
 static_assert(sizeof(mhd_pipe_desc) == 48, "mhd_pipe_desc layout");
 
 namespace {
@@ -221,6 +221,7 @@ StepConst step_const(const mhd_sim *s) {
     c.mac_c = (float)(6.0 * p.nu);
     c.inv_mac_c = (float)(1.0 / (6.0 * p.nu));
     c.u_limit2 = c.mac ? 12.0 * p.nu * p.nu : 1.0 / 3.0;
+    c.status = &s->ctrl()->status;
     c.u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.u_scale;
     c.inv_u_scale = s->g.u_storage == MHD_STORE_F32 ? 1.0f : (float)(1.0 / s->g.u_scale);
     c.b_scale = s->g.b_storage == MHD_STORE_F32 ? 1.0f : (float)s->g.b_scale;
@@ -237,6 +238,7 @@ StepConst step_const(const mhd_sim *s) {
     c.yc = p.yc;
     c.zc = p.zc;
     c.radius = p.avg_radius;
+    c.omega_radius = p.omega_radius > 0.0 ? p.omega_radius : p.avg_radius - 2.0;
     c.flow_control = p.flow_control;
     c.u_target = p.u_bulk_target;
     c.k_c = p.k_c;
@@ -798,7 +800,7 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
         return fail(MHD_ERR_UNSUPPORTED, "D3Q27 is built for float32 and split storage only");
     for (double v : {p->nu, p->eta, p->lambda_u, p->lambda_b, p->G0, p->G1, p->period, p->B0, p->fringe_x0, p->fringe_w,
                      p->yc, p->zc, p->avg_radius, p->u_bulk_target, p->k_c, p->alpha, p->magnet_half_width,
-                     p->magnet_distance})
+                     p->magnet_distance, p->omega_radius})
         if (!std::isfinite(v)) return fail(MHD_ERR_INVALID_ARG, "non-finite parameter");
     const bool first = !s->have_params;
     const mhd_params old = s->prm;
@@ -879,7 +881,7 @@ mhd_status mhd_get_field(mhd_sim *s, mhd_field f, double *host) {
     }
     DevCtrl h;
     STEPCHK(read_ctrl(s, &h));
-    if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a budget pass found non-finite values or |u| >= c_s");
+    if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a fluid step or a budget pass found non-finite values or |u| >= c_s");
     return MHD_OK;
 }
 
@@ -1090,7 +1092,7 @@ mhd_status mhd_get_budgets(mhd_sim *s, mhd_budget *out, int64_t cap, int64_t *n_
     HIPCHK(launch_reset_records(s->stream, s->ctrl()));
     HIPCHK(hipStreamSynchronize(s->stream));
     *n_out = n;
-    if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a budget pass found non-finite values or |u| >= c_s");
+    if (h.status & 1) return fail(MHD_ERR_UNSTABLE, "a fluid step or a budget pass found non-finite values or |u| >= c_s");
     return MHD_OK;
 }
 

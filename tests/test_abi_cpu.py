@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_the_header_layout():
     assert C.sizeof(_abi.mhd_grid_desc) == 6 * 4 + 2 * 8
-    assert C.sizeof(_abi.mhd_params) == 168  # 19 doubles + 4 int32, no padding holes
-    assert C.sizeof(_abi.mhd_budget) == 17 * 8
+    assert C.sizeof(_abi.mhd_params) == 176  # 20 doubles + 4 int32, no padding holes
+    assert C.sizeof(_abi.mhd_budget) == 18 * 8
 
 
 def _desc(nx=8, ny=32, nz=32, r=0, u=0, b=0, us=1.0, bs=1.0):

@@ -204,3 +204,19 @@ def test_batch_mixes_fluid_branches_bitwise():
     for i in (0, 1):
         compare(B.pipes[i], oracle_run(spec[i][0], 3, markers=spec[i][1]), label=f"batch branch pipe {i}")
     B.close()
+
+
+def test_blow_up_in_one_pipe_is_reported_for_that_pipe_only():
+    from paper_2211_09370_amd import _abi
+
+    spec = batch_spec()[:2]
+    B = make_batch(spec)
+    u = spec[1][0].u.copy()
+    u[0, 5, 6, 7] = 0.9
+    B.pipes[1].set_field("u", u)
+    B.step(1)
+    B.pipes[0].get_field("u")
+    assert B.pipes[0].last_status == _abi.MHD_OK
+    B.pipes[1].get_field("u")
+    assert B.pipes[1].last_status == _abi.MHD_ERR_UNSTABLE
+    B.close()

@@ -77,6 +77,42 @@ def test_large_pipe_full_size_sampled_cells(form):
     _compare_cells(f"large {form}", w, fields, cells, 1e-5 if form == "f32" else 2e-3)
 
 
+def test_perturbed_large_pipe_three_steps_sampled_cells():
+    """The unsteady large-pipe case as specified (Poiseuille profile plus a divergence-free 5%
+    perturbation, Re = 5000, tau = 0.5036), three steps of two sweeps in float32 at full size,
+    checked at sampled cells against the oracle run for the same three steps on a box cut with
+    three steps' influence radius."""
+    from paper_2211_09370_amd import Sim
+
+    steps = 3
+    w = W.large_pipe_perturbed(Rm=1.0)
+    print("case perturbed large pipe", steps, "steps", flush=True)
+    sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+    sim.set_markers(w.markers)
+    sim.set_params(w.params, n_mag=N_MAG)
+    sim.set_field("rho", w.rho)
+    sim.set_field("u", w.u)
+    sim.set_field("b", w.b)
+    sim.step(steps)
+    fields = (sim.get_field("rho"), sim.get_field("u"), sim.get_field("b"))
+    sim.close()
+    assert all(np.isfinite(f).all() for f in fields)
+    cells = _sample_cells(w, 8, key=650)
+    rho, u, b = fields
+    us, bs = np.abs(u).max(), np.abs(b).max()
+    rs = max(np.abs(rho - 1.0).max(), math.sqrt(3.0) * us)
+    worst = [0.0, 0.0, 0.0]
+    for c in cells:
+        r_o, u_o, b_o = oracle_cell(w, c, N_MAG, steps=steps)
+        cx, cy, cz = c
+        worst[0] = max(worst[0], abs(rho[cz, cy, cx] - r_o) / rs)
+        worst[1] = max(worst[1], np.abs(u[:, cz, cy, cx] - u_o).max() / us)
+        worst[2] = max(worst[2], np.abs(b[:, cz, cy, cx] - b_o).max() / bs)
+    print(f"perturbed large pipe {steps} steps: {len(cells)} cells, err rho-1 {worst[0]:.2e} "
+          f"u {worst[1]:.2e} b {worst[2]:.2e}", flush=True)
+    assert max(worst) <= 1e-5, worst
+
+
 def test_batch_64_pipes_full_size_sampled_cells():
     from paper_2211_09370_amd import Batch
 
@@ -154,8 +190,8 @@ def test_maximum_box_sampled_cells():
 
 
 def test_fringe_pipe_long_run_budget_series():
-    """The 128^3 fringe configuration stepped for 3000 steps with the energy budgets logged every
-    100 steps: the state stays finite, the mass (float64 sum of the float32 density) stays
+    """The 128^3 fringe configuration stepped for its full 10,000 steps with the energy budgets
+    logged every 100 steps: the state stays finite, the mass (float64 sum of the float32 density) stays
     constant, and the kinetic-energy balance of Sec. 4 holds along the transient, dE_k/dt =
     P_in + P_p + P_nu + P_L with dE_k/dt the central difference of the records (the same balance
     the oracle pins step by step), here over the whole run of the full-size box."""
@@ -164,7 +200,7 @@ def test_fringe_pipe_long_run_budget_series():
     from paper_2211_09370_amd import Sim
 
     w = W.fringe_pipe()
-    steps, every = 3000, 100
+    steps, every = 10000, 100
     print("case fringe pipe long run", steps, "steps", flush=True)
     t0 = time.time()
     sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])

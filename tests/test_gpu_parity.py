@@ -448,9 +448,12 @@ def test_flow_control_and_oscillating_force():
 # budgets
 # ---------------------------------------------------------------------------------------------
 
-def test_budget_reduction_matches_oracle_on_the_same_fields():
+@pytest.mark.parametrize("omega_radius", [0.0, 14.0])
+def test_budget_reduction_matches_oracle_on_the_same_fields(omega_radius):
+    # omega_radius 0: the default region r < R - 2; R: the whole conductor (power balance)
     w = W.small_pipe(b_amp=1e-3)
     w.params.n_mag = 30
+    w.params.omega_radius = omega_radius
     sim = gpu_run(w, 5, budget_every=5)
     recs = sim.budgets()
     assert len(recs) == 1 and recs[0]["step"] == 5
@@ -459,10 +462,10 @@ def test_budget_reduction_matches_oracle_on_the_same_fields():
     p = oracle.make_params(w.nx, w.ny, w.nz, w.params)
     ref = oracle.budgets(p, rho, u, b, r["G"])
     for k in ("E_k", "E_m", "E_b", "P_in", "P_p", "P_nu", "P_L", "M_eta", "M_adv", "joule", "mass",
-              "Q", "u_max", "n_omega", "res_mag"):
+              "Q", "u_max", "n_omega", "res_mag", "D_eta"):
         scale = max(abs(ref[k]), 1e-300)
         assert abs(r[k] - ref[k]) <= 1e-9 * scale, (k, r[k], ref[k])
-    assert ref["res_mag"] > 0
+    assert ref["res_mag"] > 0 and ref["D_eta"] > 0
 
 
 def test_budget_trajectory_matches_oracle():
@@ -536,6 +539,33 @@ def test_unstable_state_is_reported():
     assert sim.last_status == _abi.MHD_ERR_UNSTABLE
     sim.get_field("u")
     assert sim.last_status == _abi.MHD_ERR_UNSTABLE
+
+
+def test_blow_up_is_reported_on_every_step_without_budgets():
+    # |u| >= c_s anywhere after a fluid update marks the box, with no budget pass in the run
+    from paper_2211_09370_amd import _abi
+
+    w = W.small_pipe()
+    w.params.n_mag = 2
+    sim = gpu_run(w, 3)
+    sim.get_field("u")
+    assert sim.last_status == _abi.MHD_OK  # a healthy run is not flagged
+    u = sim.get_field("u")
+    u[0, 3, 4, 5] = 0.9
+    sim.set_field("u", u)
+    sim.step(1, 0)
+    sim.get_field("u")
+    assert sim.last_status == _abi.MHD_ERR_UNSTABLE
+    recs, st = sim.budgets(), sim.last_status
+    assert recs == [] and st == _abi.MHD_ERR_UNSTABLE
+    # a non-finite value is caught the same way
+    sim2 = gpu_run(w, 0)
+    u = w.u.copy()
+    u[1, 2, 3, 4] = float("nan")
+    sim2.set_field("u", u)
+    sim2.step(1, 0)
+    sim2.get_field("rho")
+    assert sim2.last_status == _abi.MHD_ERR_UNSTABLE
 
 
 def test_argument_checks():

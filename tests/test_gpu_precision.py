@@ -5,7 +5,9 @@ Forms (all arithmetic float32; budgets and the flow-rate sum float64):
   u in bfloat16 scaled by U0, b in float16 scaled by B0. Every stored value is rounded at every
   write; the magnetic iteration rewrites b 270 times per fluid step and its slowest modes
   contract by only ~1/150 per sweep, so the rounding piles up in b and, through the Lorentz force,
-  in u. Its errors are recorded here (loose bounds: what the form gives, not a target).
+  in u (measured u errors 4.2e-1 and 8.0e-2 after 2000 steps). The 1e-3 velocity target is
+  asserted for them as an expected failure (strict: the test fails if a form ever meets it, so
+  the claim that it cannot is checked too); their measured errors are reported by the benchmark.
 * offsets, all float16, with b scaled by the induced-field scale Rm B0 (b / b_scale ~ 0.1 instead
   of ~1e-4, i.e. out of float16's subnormal range).
 * split (f16split): rho and u float32, b = (hi + lo) Rm B0 in two float16 arrays, hi re-quantised
@@ -39,12 +41,13 @@ def forms(w):
     }
 
 
-# measured bounds of the offset forms (recorded, with margin), and the target of the split form
-BOUNDS = {
-    "f16/bf16/f16 (b / B0)": 1.0,
-    "f16/f16/f16 (b / Rm B0)": 0.5,
-    "f32/f32/f16-split (b / Rm B0)": 1e-3,
-}
+TARGET = 1e-3  # velocity error of the 16-bit forms (max-normalised) after 2000 steps
+CANNOT_MEET = pytest.mark.xfail(strict=True, reason=(
+    "plain 16-bit offsets round b at each of the 270 sweeps of a step and the slowest modes "
+    "contract by ~1/150 per sweep: the rounding accumulates about 150-fold (u 4e-1 / 8e-2)"))
+NAMES = [pytest.param("f16/bf16/f16 (b / B0)", marks=CANNOT_MEET),
+         pytest.param("f16/f16/f16 (b / Rm B0)", marks=CANNOT_MEET),
+         "f32/f32/f16-split (b / Rm B0)"]
 
 
 def run(w, steps, store, **over):
@@ -77,7 +80,7 @@ def f32_reference(w, steps):
     return _F32[steps]
 
 
-@pytest.mark.parametrize("name", list(BOUNDS))
+@pytest.mark.parametrize("name", NAMES)
 def test_small_pipe_2000_steps_per_field_error(name):
     if not os.path.exists(GOLD):
         pytest.skip("stored oracle run missing (tests/golden/make_oracle_pipe8.py writes it)")
@@ -91,9 +94,9 @@ def test_small_pipe_2000_steps_per_field_error(name):
     print(f"{name}: vs oracle rho-1 {e_o[0]:.2e} u {e_o[1]:.2e} b {e_o[2]:.2e} | "
           f"vs GPU f32 rho-1 {e_g[0]:.2e} u {e_g[1]:.2e} b {e_g[2]:.2e}", flush=True)
     assert all(np.isfinite(e_o))
-    assert e_o[1] <= BOUNDS[name], ("u", e_o[1])
+    assert e_o[1] <= TARGET, ("u", e_o[1])
     if "split" in name:
-        assert e_o[2] <= BOUNDS[name] and e_o[0] <= BOUNDS[name], e_o
+        assert e_o[2] <= TARGET and e_o[0] <= TARGET, e_o
 
 
 SPLIT = dict(b_storage="f16split", u_scale=0.05, b_scale=0.01)
@@ -120,8 +123,12 @@ def test_split_form_one_step(shape):
 
 
 def test_split_form_quarter_fringe_20_steps():
-    """From rest, b grows from zero: in this transient lo carries the whole change of each step,
-    so b is held to 2e-2 (recorded: ~9e-3); the velocity keeps the 1e-3 target."""
+    """From rest, b grows from zero. In this transient lo carries the whole change of b within a
+    step, O(b), and the iteration's slowest mode contracts by only ~1/150 per sweep, so the
+    float16 rounding of lo (half an ulp, 2^-12 of lo) is carried ~150-fold: up to ~4e-2 of b
+    (measured 9e-3). b is therefore held to 2e-2 here; u feels b only through the Lorentz force
+    and keeps the 1e-3 velocity target (measured 7e-5). Near steady state lo is small and the
+    2000-step run meets 1e-3 in every field."""
     w = W.quarter_fringe_pipe()
     Rm_B0 = 1e-2 * w.params.B0
     print("case split fringe32", flush=True)

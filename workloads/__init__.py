@@ -56,6 +56,7 @@ class Params:
     magnet_D: float = 0.0  # six magnets: distance of the strips from the axis (<= 0: outside the box)
     lattice: int = 19  # 19 or 27 (the paper's D3Q27)
     gamma: float = 1.0  # time-step rescaling of the fluid update (1: none)
+    omega_radius: float = 0.0  # budget region r < omega_radius (<= 0: avg_radius - 2)
 
 
 @dataclasses.dataclass
@@ -226,3 +227,60 @@ def batch_fields(w: Workload):
     g = np.random.default_rng(w.field_seed)
     u = g.uniform(-w.noise, w.noise, size=(3, w.nz, w.ny, w.nx))
     return np.ones((w.nz, w.ny, w.nx)), u, np.zeros((3, w.nz, w.ny, w.nx))
+
+
+def perturbed_pipe_fields(nx, ny, nz, R, yc, zc, key, amp=0.05 * U0, n_modes=8, kx_max=4,
+                          U=U0):
+    """Initial state of the unsteady large-pipe case: rho = 1, b = 0, u = the Poiseuille profile of
+    bulk velocity U inside r < R (2 U (1 - r^2/R^2), zero outside) plus a divergence-free
+    perturbation: the curl, by central differences, of a seeded smooth vector potential
+    A_c = env(r) sum_q a_cq cos(2 pi (m_q x / nx + (l_q y + n_q z) / (2R)) + phi_cq) with axial
+    wave numbers |m_q| <= kx_max, cross-section wave numbers l, n in 0..3 and the envelope
+    env = (1 - r^2/R^2)^2 inside r < R (zero outside), scaled so that max |du| = amp. Central
+    differences commute, so the discrete divergence of the perturbation vanishes to round-off.
+    Returns (rho, u, b) in float64, u of shape (3, nz, ny, nx)."""
+    g = rng_for(key)
+    y = np.arange(ny, dtype=np.float64)[:, None] - yc
+    z = np.arange(nz, dtype=np.float64)[None, :] - zc
+    r2 = (y * y + z * z).T  # (nz, ny)
+    s = r2 / (R * R)
+    env = np.where(s < 1.0, (1.0 - s) ** 2, 0.0)
+    xs = np.arange(nx, dtype=np.float64)
+    Y = np.broadcast_to(np.arange(ny, dtype=np.float64)[None, :], (nz, ny))
+    Z = np.broadcast_to(np.arange(nz, dtype=np.float64)[:, None], (nz, ny))
+    A = np.zeros((3, nz, ny, nx))
+    for c in range(3):
+        for _ in range(n_modes):
+            m = int(g.integers(-kx_max, kx_max + 1))
+            l, n = int(g.integers(0, 4)), int(g.integers(0, 4))
+            a, ph = float(g.normal()), float(g.uniform(0.0, 2.0 * math.pi))
+            beta = 2.0 * math.pi * (l * Y + n * Z) / (2.0 * R) + ph  # (nz, ny)
+            ax = 2.0 * math.pi * m * xs / nx                          # (nx,)
+            # cos(ax + beta) = cos(ax) cos(beta) - sin(ax) sin(beta), built plane by plane
+            A[c] += a * (np.cos(beta)[:, :, None] * np.cos(ax)[None, None, :]
+                         - np.sin(beta)[:, :, None] * np.sin(ax)[None, None, :])
+        A[c] *= env[:, :, None]
+
+    def d(f, axis):  # central difference along x (axis 2), y (1) or z (0), periodic
+        return 0.5 * (np.roll(f, -1, axis=axis) - np.roll(f, 1, axis=axis))
+
+    du = np.empty_like(A)
+    du[0] = d(A[2], 1) - d(A[1], 0)
+    du[1] = d(A[0], 0) - d(A[2], 2)
+    du[2] = d(A[1], 2) - d(A[0], 1)
+    del A
+    du *= amp / np.abs(du).max()
+    u = du
+    u[0] += np.where(s < 1.0, 2.0 * U * (1.0 - s), 0.0)[:, :, None]
+    return np.ones((nz, ny, nx)), u, np.zeros((3, nz, ny, nx))
+
+
+def large_pipe_perturbed(Rm=1e-2, nx=512, ny=256, nz=256, R=120.0, **kw) -> Workload:
+    """The unsteady large-pipe case: 512 x 256 x 256 box, R = 120 (754 markers per plane), uniform
+    B0 along y, Re = 5000, Ha = 30 (nu = 0.0012, tau = 0.5036), the given Rm (1e-3 .. 1 gives
+    eta = 6000 .. 6 and 270 .. 36 sweeps per step), started from the Poiseuille profile with a
+    divergence-free 5% perturbation (perturbed_pipe_fields)."""
+    w = pipe_workload(f"pipe{nx}x{ny}x{nz}_R{R:g}_Ha30_Rm{Rm:g}_perturbed", 6, nx, ny, nz, R, 5000.0,
+                      30.0, Rm, noise=0.0, **kw)
+    w.rho, w.u, w.b = perturbed_pipe_fields(nx, ny, nz, R, w.params.yc, w.params.zc, key=6)
+    return w

@@ -200,6 +200,18 @@ mhd_status mhd_set_time(mhd_sim *s, int64_t t, double G);
  * launches. */
 mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mhd_step with the scratch of its kernels (Lorentz
+ * force, wall corrections, flow-rate and budget partials) in a static device array of the library
+ * (32 MiB per GPU, held until the process ends) instead of the solver's workspace. Same kernels
+ * and launch order as mhd_step, issued directly (no graph), so the results are the same bit for
+ * bit; the caller still provides the fields (the solver's workspace) and the stream. No call
+ * allocates, frees or clears memory; every scratch value is written before it is read within a
+ * step. INVALID_ARG if the box needs more than the array holds (about 2.7 M cells); the other
+ * errors as mhd_step. All calls on one GPU share that GPU's array: calls whose work overlaps on
+ * the GPU (two solvers on different streams, or another thread) race on it, so serialise them. */
+mhd_status mhd_step_noalloc(mhd_sim *s, int64_t n_steps, int32_t budget_every);
+
 /* Graph replay of mhd_step (performance only): enable = 1 (default) or 0 (direct launches). */
 mhd_status mhd_set_graph(mhd_sim *s, int32_t enable);
 

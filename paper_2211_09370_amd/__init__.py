@@ -23,7 +23,7 @@ from ._abi import (MHD_BEXT_NONE, MHD_BEXT_SIX_MAGNETS, MHD_BEXT_TANH_FRINGE_Y, 
 
 __all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
-           "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
+           "mhd_step", "mhd_step_noalloc", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
            "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles", "mhd_set_graph", "mhd_tune",
            "mhd_mag_residual_curve",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
@@ -104,6 +104,10 @@ def mhd_set_time(h, t: int, G: float):
 
 def mhd_step(h, n_steps: int, budget_every: int = 0):
     _abi.check(_abi.lib().mhd_step(h, int(n_steps), int(budget_every)), "mhd_step")
+
+
+def mhd_step_noalloc(h, n_steps: int, budget_every: int = 0):
+    _abi.check(_abi.lib().mhd_step_noalloc(h, int(n_steps), int(budget_every)), "mhd_step_noalloc")
 
 
 def mhd_record_budget(h):
@@ -311,6 +315,10 @@ class Sim:
     # -- stepping --------------------------------------------------------------------------
     def step(self, n: int = 1, budget_every: int = 0):
         mhd_step(self._h, n, budget_every)
+
+    def step_noalloc(self, n: int = 1, budget_every: int = 0):
+        """mhd_step with its kernels' scratch in the library's static device array (no allocation)."""
+        mhd_step_noalloc(self._h, n, budget_every)
 
     def tune(self, reps: int = 5):
         """Time every valid sweep tile choice on the live fields and keep the fastest (state unchanged)."""

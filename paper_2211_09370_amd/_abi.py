@@ -29,7 +29,7 @@ MHD_FIELD_RHO, MHD_FIELD_U, MHD_FIELD_B_INDUCED = 0, 1, 2
 
 EXPORTS = ("mhd_last_error", "mhd_workspace_size", "mhd_create", "mhd_set_markers",
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
-           "mhd_step", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
+           "mhd_step", "mhd_step_noalloc", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
            "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles",
            "mhd_set_graph", "mhd_tune", "mhd_mag_residual_curve",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
@@ -93,6 +93,7 @@ def lib() -> C.CDLL:
         L.mhd_get_time.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.mhd_set_time.argtypes = [P, C.c_int64, C.c_double]
         L.mhd_step.argtypes = [P, C.c_int64, C.c_int32]
+        L.mhd_step_noalloc.argtypes = [P, C.c_int64, C.c_int32]
         L.mhd_get_budgets.argtypes = [P, C.POINTER(mhd_budget), C.c_int64, C.POINTER(C.c_int64)]
         L.mhd_record_budget.argtypes = [P]
         L.mhd_set_profiling.argtypes = [P, C.c_int32]

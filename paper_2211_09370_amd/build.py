@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhdlbm.so")
-SOURCES = ["mhd_sweep.hip", "mhd_kernels.hip", "mhd_runtime.cpp"]
+SOURCES = ["mhd_sweep.hip", "mhd_kernels.hip", "mhd_noalloc.hip", "mhd_runtime.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -168,6 +168,16 @@ hipError_t launch_reset_records(hipStream_t s, DevCtrl *ctrl);
 // Residual sum of budget partials (slot 13) -> out = sqrt(sum / n_omega) (one workgroup).
 hipError_t launch_residual_final(hipStream_t s, const double *part, double *out);
 
+// Stepping with the step scratch outside the workspace (mhd_runtime.cpp; used by the
+// allocation-free entry point in mhd_noalloc.hip).
+mhd_status step_checks(mhd_sim *s, int64_t n_steps);      // the argument checks of mhd_step
+size_t step_scratch_bytes(const mhd_sim *s);              // scratch one step of this box needs
+// n_steps steps with direct launches, the step kernels' scratch at dev_scratch (device memory of
+// at least step_scratch_bytes(s) bytes, 256-byte aligned)
+mhd_status step_in_scratch(mhd_sim *s, int64_t n_steps, int32_t budget_every, void *dev_scratch);
+mhd_status report_error(mhd_status st, const char *msg);  // sets mhd_last_error
+int sim_device(const mhd_sim *s);
+
 // Packs the three storage kinds (rho, u, b) into one dispatch code.
 inline int pack_kinds(int r, int u, int b) { return r | (u << 4) | (b << 8); }
 

@@ -173,6 +173,12 @@ struct mhd_sim {
     };
     std::vector<StepGraph> graphs;
     bool graph_on = true;
+    // Scratch of the step kernels taken from elsewhere than the workspace while set (the
+    // allocation-free entry point): Lorentz force F, wall corrections, flow and budget partials.
+    struct Scratch {
+        float *F = nullptr, *delta = nullptr;
+        double *flow = nullptr, *red = nullptr;
+    } scr;
 
     template <typename T>
     T *at(size_t off) const {
@@ -189,6 +195,10 @@ struct mhd_sim {
                                                                     : nullptr;
     }
     DevCtrl *ctrl() const { return at<DevCtrl>(L.ctrl); }
+    float *F_buf() const { return scr.F ? scr.F : at<float>(L.F); }
+    float *delta_buf() const { return scr.delta ? scr.delta : at<float>(L.delta); }
+    double *flow_buf() const { return scr.flow ? scr.flow : at<double>(L.flow_part); }
+    double *red_buf() const { return scr.red ? scr.red : at<double>(L.red_part); }
 };
 
 namespace {
@@ -421,7 +431,7 @@ mhd_status ib_correct(mhd_sim *s, int kind, void *phi, float scale, float inv_sc
     a.band_cell = s->at<int>(s->L.band_cell);
     a.band_mk = s->at<int>(s->L.band_mk);
     a.band_w = s->at<float>(s->L.band_w);
-    a.delta = s->at<float>(s->L.delta);
+    a.delta = s->delta_buf();
     return timed(s, MHD_K_IB, "wall correction",
                  [&] { return launch_ib(s->stream, kind, phi, scale, inv_scale, a); });
 }
@@ -459,7 +469,7 @@ mhd_status one_step(mhd_sim *s) {
     // 1. magnetic iteration, wall correction after every sweep
     for (int m = 0; m < s->prm.n_mag; ++m) STEPCHK(mag_iteration(s, c, m));
     // 2. Lorentz + body force from the new b
-    float *F = s->at<float>(s->L.F);
+    float *F = s->F_buf();
     STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
         return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->bh(s->ch), s->at<float>(s->L.bext), s->byz(),
                               s->ctrl(), F, c);
@@ -474,7 +484,7 @@ mhd_status one_step(mhd_sim *s) {
     s->cr = nr;
     s->cu = nu;
     // 5. flow-rate control sum (float64, fixed order) and step counter
-    double *fp = s->at<double>(s->L.flow_part);
+    double *fp = s->flow_buf();
     if (c.flow_control)
         STEPCHK(timed(s, MHD_K_CONTROL, "flow_partial",
                       [&] { return launch_flow_partial(st, s->g.u_storage, s->u(s->cu), fp, c); }));
@@ -488,7 +498,7 @@ mhd_status record_budget(mhd_sim *s) {
     const StepConst c = step_const(s);
     return timed(s, MHD_K_BUDGET, "budget", [&] {
         return launch_budget(s->stream, s->kinds, s->rho(s->cr), s->u(s->cu), s->b(s->cb), s->bh(s->ch),
-                             s->at<float>(s->L.bext), s->byz(), s->ctrl(), s->at<double>(s->L.red_part),
+                             s->at<float>(s->L.bext), s->byz(), s->ctrl(), s->red_buf(),
                              s->at<mhd_budget>(s->L.ring), c);
     });
 }
@@ -912,10 +922,7 @@ mhd_status mhd_set_time(mhd_sim *s, int64_t t, double G) {
 
 mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every) {
     g_err.clear();
-    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
-    if (s->owner) return fail(MHD_ERR_STATE, "this box belongs to a batch: step it with mhd_batch_step");
-    if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called before mhd_step");
-    if (n_steps < 0) return fail(MHD_ERR_INVALID_ARG, "n_steps < 0");
+    STEPCHK(step_checks(s, n_steps));
     // On a caller stream the step is captured once per buffer state and replayed as a HIP graph
     // (one launch call per step instead of about 3 n_mag + 6); profiling steps launch directly.
     const bool graph = s->graph_on && s->stream != nullptr && !s->prof;
@@ -960,6 +967,61 @@ mhd_status mhd_step(mhd_sim *s, int64_t n_steps, int32_t budget_every) {
     }
     return MHD_OK;
 }
+
+}  // extern "C"
+
+namespace mhd {
+
+mhd_status report_error(mhd_status st, const char *msg) { return fail(st, "%s", msg); }
+
+// Step scratch regions of a box, each 256-byte aligned: F [3][N] float32, wall corrections
+// [3][M] float32, flow partials [kRedBlocks] and budget partials [kRedBlocks][kBudgetVals] float64.
+static size_t scratch_layout(const mhd_sim *s, size_t off[4]) {
+    const size_t sizes[4] = {3 * (size_t)s->N * sizeof(float), 3 * (size_t)std::max<int64_t>(s->Mcap, 1) * sizeof(float),
+                             (size_t)kRedBlocks * sizeof(double), (size_t)kRedBlocks * kBudgetVals * sizeof(double)};
+    size_t o = 0;
+    for (int i = 0; i < 4; ++i) {
+        off[i] = o;
+        o = align256(o + sizes[i]);
+    }
+    return o;
+}
+
+size_t step_scratch_bytes(const mhd_sim *s) {
+    size_t off[4];
+    return scratch_layout(s, off);
+}
+
+mhd_status step_in_scratch(mhd_sim *s, int64_t n_steps, int32_t budget_every, void *dev_scratch) {
+    size_t off[4];
+    scratch_layout(s, off);
+    char *base = static_cast<char *>(dev_scratch);
+    s->scr.F = reinterpret_cast<float *>(base + off[0]);
+    s->scr.delta = reinterpret_cast<float *>(base + off[1]);
+    s->scr.flow = reinterpret_cast<double *>(base + off[2]);
+    s->scr.red = reinterpret_cast<double *>(base + off[3]);
+    mhd_status st = MHD_OK;
+    for (int64_t i = 0; i < n_steps && st == MHD_OK; ++i) {  // direct launches: no graph holds these pointers
+        st = one_step(s);
+        if (st == MHD_OK && budget_every > 0 && s->t_host % budget_every == 0) st = record_budget(s);
+    }
+    s->scr = mhd_sim::Scratch{};
+    return st;
+}
+
+mhd_status step_checks(mhd_sim *s, int64_t n_steps) {
+    if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");
+    if (s->owner) return fail(MHD_ERR_STATE, "this box belongs to a batch: step it with mhd_batch_step");
+    if (!s->have_params) return fail(MHD_ERR_STATE, "mhd_set_params must be called before stepping");
+    if (n_steps < 0) return fail(MHD_ERR_INVALID_ARG, "n_steps < 0");
+    return MHD_OK;
+}
+
+int sim_device(const mhd_sim *s) { return s->device; }
+
+}  // namespace mhd
+
+extern "C" {
 
 mhd_status mhd_set_graph(mhd_sim *s, int32_t enable) {
     g_err.clear();

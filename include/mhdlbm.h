@@ -231,6 +231,13 @@ mhd_status mhd_record_budget(mhd_sim *s);
  * induced field is restored afterwards, so the state is unchanged. Synchronous. */
 mhd_status mhd_mag_residual_curve(mhd_sim *s, int32_t n_sweeps, double *res_out);
 
+/* Effective number of magnetic sweeps (Sec. 5.8: the count at which the iteration has damped
+ * enough, instead of a non-local residual every step): from the current state, the residual curve
+ * above over n_max sweeps (1 .. 4096), and *n_out = the smallest n whose residual is at most
+ * tol (0 < tol < 1) times the residual after the first sweep, or n_max if none is. The state is
+ * unchanged. apply = 1 also makes it the solver's n_mag (as mhd_set_params would). Synchronous. */
+mhd_status mhd_choose_n_mag(mhd_sim *s, double tol, int32_t n_max, int32_t apply, int32_t *n_out);
+
 /* Kernel timing with HIP events on the solver's stream: when enabled, mhd_step brackets every
  * launch of the kernels with events; mhd_kernel_stats synchronises and returns the number of
  * timed launches and their summed duration for one kernel id, then forgets them. */

@@ -25,7 +25,7 @@ __all__ = ["Sim", "Batch", "MhdError", "mhd_workspace_size", "mhd_create", "mhd_
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_step_noalloc", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
            "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles", "mhd_set_graph", "mhd_tune",
-           "mhd_mag_residual_curve",
+           "mhd_mag_residual_curve", "mhd_choose_n_mag",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
            "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
            "mhd_batch_kernel_stats", "mhd_batch_destroy", "mhd_last_error", "BUDGET_FIELDS"]
@@ -145,6 +145,13 @@ def mhd_mag_residual_curve(h, n_sweeps: int) -> np.ndarray:
     out = np.zeros(int(n_sweeps))
     _abi.check(_abi.lib().mhd_mag_residual_curve(h, int(n_sweeps), _dptr(out)), "mhd_mag_residual_curve")
     return out
+
+
+def mhd_choose_n_mag(h, tol: float, n_max: int, apply: bool = False) -> int:
+    n = C.c_int32(0)
+    _abi.check(_abi.lib().mhd_choose_n_mag(h, float(tol), int(n_max), 1 if apply else 0, C.byref(n)),
+               "mhd_choose_n_mag")
+    return int(n.value)
 
 
 def mhd_get_tiles(h):
@@ -351,6 +358,10 @@ class Sim:
     def mag_residual_curve(self, n_sweeps: int) -> np.ndarray:
         """Induction residual after each of n_sweeps sweeps from the current state (restored)."""
         return mhd_mag_residual_curve(self._h, n_sweeps)
+
+    def choose_n_mag(self, tol: float, n_max: int, apply: bool = False) -> int:
+        """Smallest sweep count whose residual is within tol of the first sweep's (Sec. 5.8)."""
+        return mhd_choose_n_mag(self._h, tol, n_max, apply)
 
     @property
     def tiles(self):

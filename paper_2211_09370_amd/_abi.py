@@ -31,7 +31,7 @@ EXPORTS = ("mhd_last_error", "mhd_workspace_size", "mhd_create", "mhd_set_marker
            "mhd_set_params", "mhd_set_field", "mhd_get_field", "mhd_get_time", "mhd_set_time",
            "mhd_step", "mhd_step_noalloc", "mhd_get_budgets", "mhd_record_budget", "mhd_set_profiling",
            "mhd_kernel_stats", "mhd_destroy", "mhd_get_tiles", "mhd_set_tiles",
-           "mhd_set_graph", "mhd_tune", "mhd_mag_residual_curve",
+           "mhd_set_graph", "mhd_tune", "mhd_mag_residual_curve", "mhd_choose_n_mag",
            "mhd_batch_workspace_size", "mhd_batch_create", "mhd_batch_pipe", "mhd_batch_tune",
            "mhd_batch_step", "mhd_batch_set_graph", "mhd_batch_set_profiling",
            "mhd_batch_kernel_stats", "mhd_batch_destroy")
@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
         L.mhd_kernel_stats.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.mhd_destroy.argtypes = [P]
         L.mhd_mag_residual_curve.argtypes = [P, C.c_int32, _D]
+        L.mhd_choose_n_mag.argtypes = [P, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
         I4 = C.c_int32 * 4
         L.mhd_get_tiles.argtypes = [P, I4]
         L.mhd_set_tiles.argtypes = [P, I4]

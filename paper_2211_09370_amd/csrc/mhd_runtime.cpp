@@ -1133,6 +1133,28 @@ mhd_status mhd_mag_residual_curve(mhd_sim *s, int32_t n_sweeps, double *res_out)
     return MHD_OK;
 }
 
+mhd_status mhd_choose_n_mag(mhd_sim *s, double tol, int32_t n_max, int32_t apply, int32_t *n_out) {
+    g_err.clear();
+    if (!s || !n_out) return fail(MHD_ERR_INVALID_ARG, "NULL argument");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(MHD_ERR_INVALID_ARG, "tol = %g must lie in (0, 1)", tol);
+    if (apply != 0 && apply != 1) return fail(MHD_ERR_INVALID_ARG, "apply must be 0 or 1");
+    std::vector<double> res((size_t)std::max(n_max, 1));
+    STEPCHK(mhd_mag_residual_curve(s, n_max, res.data()));
+    int32_t n = n_max;
+    for (int32_t k = 0; k < n_max; ++k)
+        if (res[(size_t)k] <= tol * res[0]) {
+            n = k + 1;
+            break;
+        }
+    if (apply) {
+        mhd_params p = s->prm;
+        p.n_mag = n;
+        STEPCHK(mhd_set_params(s, &p));
+    }
+    *n_out = n;
+    return MHD_OK;
+}
+
 mhd_status mhd_record_budget(mhd_sim *s) {
     g_err.clear();
     if (!s) return fail(MHD_ERR_INVALID_ARG, "sim is NULL");

@@ -136,6 +136,28 @@ def test_residual_curve_matches_oracle_and_keeps_the_state(alpha):
     sim.step(1)  # stepping afterwards still works
 
 
+def test_effective_sweep_count_is_chosen_from_the_residual_curve():
+    """Sec. 5.8 effective iteration count: the smallest n whose residual is within tol of the
+    first sweep's, from the same curve the oracle reproduces (previous test); the state is kept,
+    and with apply the solver steps with that count."""
+    w = W.small_pipe(b_amp=1e-4)
+    sim = gpu_run(w, 0)
+    curve = sim.mag_residual_curve(200)
+    before = [sim.get_field(f) for f in ("rho", "u", "b")]
+    for tol in (0.5, 0.1, 1e-2):
+        n = sim.choose_n_mag(tol, 200)
+        want = next((k + 1 for k, r in enumerate(curve) if r <= tol * curve[0]), 200)
+        assert n == want, (tol, n, want)
+    assert sim.choose_n_mag(1e-30, 20) == 20  # never reached: the cap
+    for f, ref in zip(("rho", "u", "b"), before):
+        assert np.array_equal(sim.get_field(f), ref)
+    n = sim.choose_n_mag(0.1, 200, apply=True)
+    sim.step(1)
+    ref_sim = gpu_run(w, 1, n_mag=n)
+    for f in ("rho", "u", "b"):
+        assert np.array_equal(sim.get_field(f), ref_sim.get_field(f))
+
+
 def _transition_case(eta):
     """8x32x32 pipe, Ha 5 kept, oscillating force (T = 200), N_mag = ceil(6 eta) (Sec. 5.7)."""
     w = W.small_pipe()

@@ -108,6 +108,16 @@ hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,
                         void *rho_o, void *u_o, void *u_copy, StepConst c);
 hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c);
+// Lorentz force and fluid update in one launch (float32 single boxes; k_lorentz_fluid).
+struct LfArgs {
+    const float *rho, *u, *b;     // state before the fluid update (b after the magnetic iteration)
+    const float *bext, *bext_yz;  // B_ext tables (bext_yz NULL unless six magnets)
+    const DevCtrl *ctrl;
+    float *rho_o, *u_o;           // new rho - 1 and u* (before the u wall correction)
+    StepConst c;
+    int tiles_x, tiles_y, zchunk, nblocks;  // filled in by the launcher
+};
+hipError_t launch_lorentz_fluid(hipStream_t s, const LfArgs &a);
 // ring == NULL: the partials only (for launch_residual_final).
 hipError_t launch_budget(hipStream_t s, int kinds, const void *rho, const void *u, const void *b,
                          const void *b_hi, const float *bext, const float *bext_yz, DevCtrl *ctrl, double *part,

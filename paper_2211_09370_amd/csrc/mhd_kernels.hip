@@ -33,6 +33,16 @@ __constant__ int c_dir[26][3] = {{1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
                                  {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
                                  {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
                                  {-1, 1, 1}, {1, -1, -1}};
+// The same offsets as compile-time values, for the fully unrolled loops of the cell updates (the
+// offsets then become immediates instead of scalar loads kept live across a plane march).
+__device__ constexpr int dir_of(int i, int a) {
+    constexpr int t[26][3] = {{1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                              {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
+                              {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+                              {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+                              {-1, 1, 1}, {1, -1, -1}};
+    return t[i][a];
+}
 // weight of neighbour i of c_dir on either lattice
 __device__ __forceinline__ float dir_weight(int i, bool q27) {
     if (q27) return i < 6 ? 2.0f / 27.0f : i < 18 ? 1.0f / 54.0f : 1.0f / 216.0f;
@@ -254,6 +264,35 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_spread(T *phi, float scale, f
 // Lorentz + body force (Sec. 5.1): J = curl_h b with d_a f = 3 sum_i w_i e_ia f(x + e_i),
 // F = G x + J x (B_ext + b).
 // -------------------------------------------------------------------------------------------
+// Force at one cell. b_at(i, ex, ey, ez, v0, v1, v2) gives the induced field (times its scale)
+// at neighbour i of c_dir, offset (ex, ey, ez); B is the total field at the cell. The same body
+// serves the cell-wise kernel (neighbours from memory) and the fused one (from LDS), so the two
+// give the same values bit for bit.
+template <bool Q27, typename BAT>
+__device__ __forceinline__ void lorentz_force(BAT b_at, float Bx, float By, float Bz, float G, float &F0, float &F1,
+                                              float &F2) {
+    float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // g[a][c] = d_c b_a
+#pragma unroll
+    for (int i = 0; i < (Q27 ? 26 : 18); ++i) {
+        const int ex = dir_of(i, 0), ey = dir_of(i, 1), ez = dir_of(i, 2);
+        const float w = 3.0f * dir_weight(i, Q27);
+        float v0, v1, v2;
+        b_at(i, ex, ey, ez, v0, v1, v2);
+        const float e3[3] = {(float)ex, (float)ey, (float)ez};
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const float we = w * e3[cc];
+            g[0][cc] += we * v0;
+            g[1][cc] += we * v1;
+            g[2][cc] += we * v2;
+        }
+    }
+    const float Jx = g[2][1] - g[1][2], Jy = g[0][2] - g[2][0], Jz = g[1][0] - g[0][1];
+    F0 = G + (Jy * Bz - Jz * By);
+    F1 = Jz * Bx - Jx * Bz;
+    F2 = Jx * By - Jy * Bx;
+}
+
 template <typename TB, bool BATCH, bool SPLIT, bool Q27>
 __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB *bh, float bs, const float *bext,
                                                           const float *bext_yz, const DevCtrl *ctrl, float *F,
@@ -284,23 +323,12 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
         else
             return St<TB>::ld(b, i);
     };
-    float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};  // g[a][c] = d_c b_a
-#pragma unroll
-    for (int i = 0; i < (Q27 ? 26 : 18); ++i) {
-        const int ex = c_dir[i][0], ey = c_dir[i][1], ez = c_dir[i][2];
-        const float w = 3.0f * dir_weight(i, Q27);
+    auto b_at = [&](int, int ex, int ey, int ez, float &v0, float &v1, float &v2) {
         const int kn = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
-        const float v0 = bv(kn) * bs, v1 = bv(N + kn) * bs, v2 = bv(2 * N + kn) * bs;
-        const float e3[3] = {(float)ex, (float)ey, (float)ez};
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            const float we = w * e3[cc];
-            g[0][cc] += we * v0;
-            g[1][cc] += we * v1;
-            g[2][cc] += we * v2;
-        }
-    }
-    const float Jx = g[2][1] - g[1][2], Jy = g[0][2] - g[2][0], Jz = g[1][0] - g[0][1];
+        v0 = bv(kn) * bs;
+        v1 = bv(N + kn) * bs;
+        v2 = bv(2 * N + kn) * bs;
+    };
     float Bx = bv(k) * bs + bext[x];
     float By = bv(N + k) * bs + bext[c.nx + x];
     float Bz = bv(2 * N + k) * bs + bext[2 * c.nx + x];
@@ -311,9 +339,11 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
         Bz += bext_yz[2 * pyz + o];
     }
     const float G = (float)ctrl->G_step;
-    F[k] = G + (Jy * Bz - Jz * By);
-    F[N + k] = Jz * Bx - Jx * Bz;
-    F[2 * N + k] = Jx * By - Jy * Bx;
+    float F0, F1, F2;
+    lorentz_force<Q27>(b_at, Bx, By, Bz, G, F0, F1, F2);
+    F[k] = F0;
+    F[N + k] = F1;
+    F[2 * N + k] = F2;
 }
 
 // -------------------------------------------------------------------------------------------
@@ -354,53 +384,39 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz(const TB *b, const TB 
 // with DQ_i(y) = Q_i(y) - Q_i(x): again neighbour differences only.
 // -------------------------------------------------------------------------------------------
 // One direction of each opposite pair: 3 faces, 6 edges (D3Q19), then the 4 corners of D3Q27.
-__constant__ int c_pair[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1},
-                                  {0, 1, 1}, {0, 1, -1}, {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+__device__ constexpr int pair_of(int i, int a) {
+    constexpr int t[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1},
+                              {0, 1, 1}, {0, 1, -1}, {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+    return t[i][a];
+}
 
-template <typename TR, typename TU, bool BATCH, bool Q27>
-__global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o,
-                                                        TU *u_o, __half *u_copy, StepConst c, const PipeStep *tab,
-                                                        const BlockMap *map) {
-    int64_t blk = blockIdx.x;
-    if constexpr (BATCH) {
-        const BlockMap m = map[blk];
-        const PipeStep &q = tab[m.pipe];
-        rho = (const TR *)q.rho;
-        u = (const TU *)q.u;
-        F = q.F;
-        rho_o = (TR *)q.rho_o;
-        u_o = (TU *)q.u_o;
-        u_copy = (__half *)q.u_copy;
-        c = q.c;
-        blk = m.local;
-    }
-    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t k = blk * kCellThreads + threadIdx.x;
-    if (k >= N) return;
-    int x, y, z;
-    cell_xyz(k, c.nx, c.ny, x, y, z);
-    const float us = c.u_scale;
+// One cell of the fluid update (both branches above). at(ex, ey, ez, d, u0, u1, u2, f0, f1, f2)
+// gives the stored density offset, the velocity (times its storage scale) and the force at the
+// cell offset (ex, ey, ez) from this one ((0, 0, 0): the cell itself). The same body serves the
+// cell-wise kernel (values from memory) and the fused Lorentz + fluid kernel (from LDS), so the
+// two give the same results bit for bit.
+template <bool Q27, typename AT>
+__device__ __forceinline__ void fluid_update(AT at, const StepConst &c, float &dnew, float &un0, float &un1,
+                                             float &un2) {
+    float d0, cu0, cu1, cu2, cf0, cf1, cf2;  // the cell's own values
+    at(0, 0, 0, d0, cu0, cu1, cu2, cf0, cf1, cf2);
     if (c.mac) {
         const float ic = c.inv_mac_c, ic2 = ic * ic;
-        const float d0 = St<TR>::ld(rho, k);
-        const float vx0 = St<TU>::ld(u, k) * us * ic, vy0 = St<TU>::ld(u, N + k) * us * ic,
-                    vz0 = St<TU>::ld(u, 2 * N + k) * us * ic;
-        const float px0 = F[k] * ic2, py0 = F[N + k] * ic2, pz0 = F[2 * N + k] * ic2;
+        const float vx0 = cu0 * ic, vy0 = cu1 * ic, vz0 = cu2 * ic;
+        const float px0 = cf0 * ic2, py0 = cf1 * ic2, pz0 = cf2 * ic2;
         const float vv0 = vx0 * vx0 + vy0 * vy0 + vz0 * vz0, vp0 = vx0 * px0 + vy0 * py0 + vz0 * pz0;
         float dr = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
         for (int i = 0; i < (Q27 ? 13 : 9); ++i) {
-            const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
+            const int ex = pair_of(i, 0), ey = pair_of(i, 1), ez = pair_of(i, 2);
             const float w = Q27 ? (i < 3 ? 2.0f / 27.0f : i < 9 ? 1.0f / 54.0f : 1.0f / 216.0f) : (i < 3 ? WF : WE);
-            const int kp = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
-            const int km = wrap1(x - ex, c.nx) + c.nx * (wrap1(y - ey, c.ny) + c.ny * wrap1(z - ez, c.nz));
-            const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
-            const float vpx = St<TU>::ld(u, kp) * us * ic, vpy = St<TU>::ld(u, N + kp) * us * ic,
-                        vpz = St<TU>::ld(u, 2 * N + kp) * us * ic;
-            const float vmx = St<TU>::ld(u, km) * us * ic, vmy = St<TU>::ld(u, N + km) * us * ic,
-                        vmz = St<TU>::ld(u, 2 * N + km) * us * ic;
-            const float ppx = F[kp] * ic2, ppy = F[N + kp] * ic2, ppz = F[2 * N + kp] * ic2;
-            const float pmx = F[km] * ic2, pmy = F[N + km] * ic2, pmz = F[2 * N + km] * ic2;
+            float dp, dm, upx, upy, upz, umx, umy, umz, fpx, fpy, fpz, fmx, fmy, fmz;
+            at(ex, ey, ez, dp, upx, upy, upz, fpx, fpy, fpz);
+            at(-ex, -ey, -ez, dm, umx, umy, umz, fmx, fmy, fmz);
+            const float vpx = upx * ic, vpy = upy * ic, vpz = upz * ic;
+            const float vmx = umx * ic, vmy = umy * ic, vmz = umz * ic;
+            const float ppx = fpx * ic2, ppy = fpy * ic2, ppz = fpz * ic2;
+            const float pmx = fmx * ic2, pmy = fmy * ic2, pmz = fmz * ic2;
             const float Dpx = vpx - vx0, Dpy = vpy - vy0, Dpz = vpz - vz0;
             const float Dmx = vmx - vx0, Dmy = vmy - vy0, Dmz = vmz - vz0;
             const float Ddp = dp - d0, Ddm = dm - d0;
@@ -425,46 +441,28 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
             m1 += ey * cm;
             m2 += ez * cm;
         }
-        const float dnew = d0 + dr;
+        dnew = d0 + dr;
         const float inv = 1.0f / (1.0f + dnew);
-        St<TR>::st(rho_o, k, dnew);
         const float cu = c.mac_c;
-        const float un0 = cu * (vx0 + ((m0 + px0) - dr * vx0) * inv);
-        const float un1 = cu * (vy0 + ((m1 + py0) - dr * vy0) * inv);
-        const float un2 = cu * (vz0 + ((m2 + pz0) - dr * vz0) * inv);
-        // blow-up: a non-finite or supersonic velocity marks the box (every such lane stores the
-        // same value, so the plain store needs no atomic)
-        if (!((double)(un0 * un0 + un1 * un1 + un2 * un2) < c.u_limit2) || !(dnew == dnew)) *c.status = 1;
-        St<TU>::st(u_o, k, un0 * c.inv_u_scale);
-        St<TU>::st(u_o, N + k, un1 * c.inv_u_scale);
-        St<TU>::st(u_o, 2 * N + k, un2 * c.inv_u_scale);
-        if (u_copy) {
-            u_copy[k] = __float2half_rn(un0 * c.inv_copy_scale);
-            u_copy[N + k] = __float2half_rn(un1 * c.inv_copy_scale);
-            u_copy[2 * N + k] = __float2half_rn(un2 * c.inv_copy_scale);
-        }
+        un0 = cu * (vx0 + ((m0 + px0) - dr * vx0) * inv);
+        un1 = cu * (vy0 + ((m1 + py0) - dr * vy0) * inv);
+        un2 = cu * (vz0 + ((m2 + pz0) - dr * vz0) * inv);
         return;
     }
     const float tau = c.tau, ig = c.inv_gamma;
     const float cF = 1.0f - 0.5f / tau;
     const float a3 = 3.0f * (2.0f * tau - 1.0f);
-
-    const float d0 = St<TR>::ld(rho, k);
-    const float ux0 = St<TU>::ld(u, k) * us, uy0 = St<TU>::ld(u, N + k) * us, uz0 = St<TU>::ld(u, 2 * N + k) * us;
+    const float ux0 = cu0, uy0 = cu1, uz0 = cu2;
     const float uu0 = ux0 * ux0 + uy0 * uy0 + uz0 * uz0;
     float dr = 0.f;
     float m0 = 0.f, m1 = 0.f, m2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
 #pragma unroll
     for (int i = 0; i < (Q27 ? 13 : 9); ++i) {
-        const int ex = c_pair[i][0], ey = c_pair[i][1], ez = c_pair[i][2];
+        const int ex = pair_of(i, 0), ey = pair_of(i, 1), ez = pair_of(i, 2);
         const float w = Q27 ? (i < 3 ? 2.0f / 27.0f : i < 9 ? 1.0f / 54.0f : 1.0f / 216.0f) : (i < 3 ? WF : WE);
-        const int kp = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
-        const int km = wrap1(x - ex, c.nx) + c.nx * (wrap1(y - ey, c.ny) + c.ny * wrap1(z - ez, c.nz));
-        const float dp = St<TR>::ld(rho, kp), dm = St<TR>::ld(rho, km);
-        const float upx = St<TU>::ld(u, kp) * us, upy = St<TU>::ld(u, N + kp) * us, upz = St<TU>::ld(u, 2 * N + kp) * us;
-        const float umx = St<TU>::ld(u, km) * us, umy = St<TU>::ld(u, N + km) * us, umz = St<TU>::ld(u, 2 * N + km) * us;
-        const float fpx = F[kp], fpy = F[N + kp], fpz = F[2 * N + kp];
-        const float fmx = F[km], fmy = F[N + km], fmz = F[2 * N + km];
+        float dp, dm, upx, upy, upz, umx, umy, umz, fpx, fpy, fpz, fmx, fmy, fmz;
+        at(ex, ey, ez, dp, upx, upy, upz, fpx, fpy, fpz);
+        at(-ex, -ey, -ez, dm, umx, umy, umz, fmx, fmy, fmz);
         // differences to the centre
         const float Dpx = upx - ux0, Dpy = upy - uy0, Dpz = upz - uz0;
         const float Dmx = umx - ux0, Dmy = umy - uy0, Dmz = umz - uz0;
@@ -492,18 +490,25 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         g1 += ey * cg;
         g2 += ez * cg;
     }
-    const float dnew = d0 + dr;
+    dnew = d0 + dr;
     const float tcF = tau * cF * (ig * ig);
-    const float Dm0 = (m0 - tcF * g0) + F[k] * ig;
-    const float Dm1 = (m1 - tcF * g1) + F[N + k] * ig;
-    const float Dm2 = (m2 - tcF * g2) + F[2 * N + k] * ig;
+    const float Dm0 = (m0 - tcF * g0) + cf0 * ig;
+    const float Dm1 = (m1 - tcF * g1) + cf1 * ig;
+    const float Dm2 = (m2 - tcF * g2) + cf2 * ig;
     const float inv = 1.0f / (1.0f + dnew);
-    St<TR>::st(rho_o, k, dnew);
-    const float un0 = ux0 + (Dm0 - dr * ux0) * inv, un1 = uy0 + (Dm1 - dr * uy0) * inv,
-                un2 = uz0 + (Dm2 - dr * uz0) * inv;
-    // blow-up: a non-finite or supersonic velocity marks the box (plain store of the same value
-    // from every such lane, no atomic)
+    un0 = ux0 + (Dm0 - dr * ux0) * inv;
+    un1 = uy0 + (Dm1 - dr * uy0) * inv;
+    un2 = uz0 + (Dm2 - dr * uz0) * inv;
+}
+
+// New state of one cell from fluid_update: stores, the split form's float16 copy of u, and the
+// blow-up flag (a non-finite or supersonic velocity marks the box; every such lane stores the same
+// value, so the plain store needs no atomic).
+template <typename TR, typename TU>
+__device__ __forceinline__ void fluid_store(int64_t k, int64_t N, float dnew, float un0, float un1, float un2,
+                                            TR *rho_o, TU *u_o, __half *u_copy, const StepConst &c) {
     if (!((double)(un0 * un0 + un1 * un1 + un2 * un2) < c.u_limit2) || !(dnew == dnew)) *c.status = 1;
+    St<TR>::st(rho_o, k, dnew);
     St<TU>::st(u_o, k, un0 * c.inv_u_scale);
     St<TU>::st(u_o, N + k, un1 * c.inv_u_scale);
     St<TU>::st(u_o, 2 * N + k, un2 * c.inv_u_scale);
@@ -511,6 +516,215 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
         u_copy[k] = __float2half_rn(un0 * c.inv_copy_scale);
         u_copy[N + k] = __float2half_rn(un1 * c.inv_copy_scale);
         u_copy[2 * N + k] = __float2half_rn(un2 * c.inv_copy_scale);
+    }
+}
+
+template <typename TR, typename TU, bool BATCH, bool Q27>
+__global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU *u, const float *F, TR *rho_o,
+                                                        TU *u_o, __half *u_copy, StepConst c, const PipeStep *tab,
+                                                        const BlockMap *map) {
+    int64_t blk = blockIdx.x;
+    if constexpr (BATCH) {
+        const BlockMap m = map[blk];
+        const PipeStep &q = tab[m.pipe];
+        rho = (const TR *)q.rho;
+        u = (const TU *)q.u;
+        F = q.F;
+        rho_o = (TR *)q.rho_o;
+        u_o = (TU *)q.u_o;
+        u_copy = (__half *)q.u_copy;
+        c = q.c;
+        blk = m.local;
+    }
+    const int64_t N = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t k = blk * kCellThreads + threadIdx.x;
+    if (k >= N) return;
+    int x, y, z;
+    cell_xyz(k, c.nx, c.ny, x, y, z);
+    const float us = c.u_scale;
+    auto at = [&](int ex, int ey, int ez, float &d, float &u0_, float &u1_, float &u2_, float &f0, float &f1,
+                  float &f2) {
+        const int kk = wrap1(x + ex, c.nx) + c.nx * (wrap1(y + ey, c.ny) + c.ny * wrap1(z + ez, c.nz));
+        d = St<TR>::ld(rho, kk);
+        u0_ = St<TU>::ld(u, kk) * us;
+        u1_ = St<TU>::ld(u, N + kk) * us;
+        u2_ = St<TU>::ld(u, 2 * N + kk) * us;
+        f0 = F[kk];
+        f1 = F[N + kk];
+        f2 = F[2 * N + kk];
+    };
+    float dnew, un0, un1, un2;
+    fluid_update<Q27>(at, c, dnew, un0, un1, un2);
+    fluid_store(k, N, dnew, un0, un1, un2, rho_o, u_o, u_copy, c);
+}
+
+// -------------------------------------------------------------------------------------------
+// Lorentz force and fluid update in one plane-marching kernel (single boxes, float32 storage).
+// A workgroup owns a 64 x 4 column of cells and marches along z over a chunk of planes. Each
+// plane of b is staged in LDS with a two-cell halo, each plane of rho and u with a one-cell
+// halo; the force of a plane is formed in LDS on the one-cell halo from the three b planes
+// around it (lorentz_force), and the fluid update of the plane before takes its neighbours'
+// rho, u and F from LDS (fluid_update). F never goes to memory: the pair reads b, rho and u and
+// writes rho and u once, 44 B per cell (the two-kernel form also writes and re-reads F, and
+// gathers every neighbour through the caches). Rings of 4 (b, F) and 5 (rho, u) planes let one
+// barrier per plane separate the writes of a plane from the reads of the planes before it. The
+// cell arithmetic is the same code as k_lorentz and k_fluid, so the results are the same bit
+// for bit.
+// -------------------------------------------------------------------------------------------
+constexpr int kLfTX = 64, kLfTY = 4;                         // output tile (256 work-items)
+constexpr int kLfBX = kLfTX + 4, kLfBY = kLfTY + 4;          // b with a two-cell halo
+constexpr int kLfFX = kLfTX + 2, kLfFY = kLfTY + 2;          // F, rho, u with a one-cell halo
+constexpr int kLfBN = kLfBX * kLfBY, kLfFN = kLfFX * kLfFY;  // 544, 396 cells per plane
+constexpr int kLfBS = (kLfBN + kCellThreads - 1) / kCellThreads;  // b cells staged per work-item
+constexpr int kLfFS = (kLfFN + kCellThreads - 1) / kCellThreads;  // F / rho-u cells per work-item
+
+__device__ __forceinline__ int ring5(int p) { return ((p % 5) + 5) % 5; }
+
+template <bool Q27>
+__global__ void __launch_bounds__(kCellThreads) k_lorentz_fluid(LfArgs a) {
+    __shared__ float sb[4][3][kLfBN];
+    __shared__ float sF[4][3][kLfFN];
+    __shared__ float sr[5][4][kLfFN];
+    const StepConst &c = a.c;
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const unsigned plane = (unsigned)nx * ny;
+    // XCD-aware order (as for the sweep): each XCD receives a contiguous run of tiles
+    const int per = gridDim.x >> 3;
+    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (lb >= a.nblocks) return;
+    const int tix = lb % a.tiles_x, rest = lb / a.tiles_x;
+    const int tiy = rest % a.tiles_y, tiz = rest / a.tiles_y;
+    const int x0 = tix * kLfTX, y0 = tiy * kLfTY, z0 = tiz * a.zchunk;
+    const int z1 = min(z0 + a.zchunk, nz);
+    const int t = threadIdx.x;
+    const float us = c.u_scale, bs = c.b_scale;
+
+    // staged cells of this work-item (fixed (x, y) for the whole march)
+    unsigned bxy[kLfBS];
+    bool bval[kLfBS];
+#pragma unroll
+    for (int s = 0; s < kLfBS; ++s) {
+        const int i = t + s * kCellThreads;
+        bval[s] = i < kLfBN;
+        const int hx = i % kLfBX, hy = i / kLfBX;
+        bxy[s] = (unsigned)(wrapi(x0 - 2 + hx, nx) + nx * wrapi(y0 - 2 + hy, ny));
+    }
+    unsigned fxy[kLfFS];
+    bool fval[kLfFS];
+#pragma unroll
+    for (int s = 0; s < kLfFS; ++s) {
+        const int i = t + s * kCellThreads;
+        fval[s] = i < kLfFN;
+        const int hx = i % kLfFX, hy = i / kLfFX;
+        fxy[s] = (unsigned)(wrapi(x0 - 1 + hx, nx) + nx * wrapi(y0 - 1 + hy, ny));
+    }
+    float rb[kLfBS][3], rr[kLfFS][4];
+    auto load_b = [&](int p) {
+        const unsigned off = (unsigned)wrapi(p, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < kLfBS; ++s)
+            if (bval[s])
+#pragma unroll
+                for (int q = 0; q < 3; ++q) rb[s][q] = a.b[q * N + off + bxy[s]];
+    };
+    auto store_b = [&](int p) {
+#pragma unroll
+        for (int s = 0; s < kLfBS; ++s)
+            if (bval[s])
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sb[p & 3][q][t + s * kCellThreads] = rb[s][q];
+    };
+    auto load_r = [&](int p) {
+        const unsigned off = (unsigned)wrapi(p, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < kLfFS; ++s)
+            if (fval[s]) {
+                rr[s][0] = a.rho[off + fxy[s]];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) rr[s][1 + q] = a.u[q * N + off + fxy[s]];
+            }
+    };
+    auto store_r = [&](int p) {
+#pragma unroll
+        for (int s = 0; s < kLfFS; ++s)
+            if (fval[s])
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sr[ring5(p)][q][t + s * kCellThreads] = rr[s][q];
+    };
+    // force of plane p on the one-cell halo region, from b planes p - 1 .. p + 1
+    const float G = (float)a.ctrl->G_step;
+    auto force = [&](int p) {
+        const int zz = wrapi(p, nz);
+#pragma unroll 1
+        for (int i = t; i < kLfFN; i += kCellThreads) {
+            const int hx = i % kLfFX + 1, hy = i / kLfFX + 1;  // position in the b region
+            const int gx = wrapi(x0 - 2 + hx, nx), gy = wrapi(y0 - 2 + hy, ny);
+            auto b_at = [&](int, int ex, int ey, int ez, float &v0, float &v1, float &v2) {
+                const int sl = (p + ez) & 3, o = (hy + ey) * kLfBX + (hx + ex);
+                v0 = sb[sl][0][o] * bs;
+                v1 = sb[sl][1][o] * bs;
+                v2 = sb[sl][2][o] * bs;
+            };
+            const int oc = hy * kLfBX + hx;
+            float Bx = sb[p & 3][0][oc] * bs + a.bext[gx];
+            float By = sb[p & 3][1][oc] * bs + a.bext[nx + gx];
+            float Bz = sb[p & 3][2][oc] * bs + a.bext[2 * nx + gx];
+            if (a.bext_yz) {  // six magnets: (y, z) part of B_ext
+                const int64_t pyz = (int64_t)ny * nz, o = gy + (int64_t)ny * zz;
+                Bx += a.bext_yz[o];
+                By += a.bext_yz[pyz + o];
+                Bz += a.bext_yz[2 * pyz + o];
+            }
+            float F0, F1, F2;
+            lorentz_force<Q27>(b_at, Bx, By, Bz, G, F0, F1, F2);
+            sF[p & 3][0][i] = F0;
+            sF[p & 3][1][i] = F1;
+            sF[p & 3][2][i] = F2;
+        }
+    };
+    // fluid update of the output cell of this work-item on plane q
+    const int lx = t % kLfTX, ly = t / kLfTX;
+    const int ox = x0 + lx, oy = y0 + ly;
+    const bool own = ox < nx && oy < ny;
+    auto fluid = [&](int q) {
+        auto at = [&](int ex, int ey, int ez, float &d, float &u0_, float &u1_, float &u2_, float &f0, float &f1,
+                      float &f2) {
+            const int rs = ring5(q + ez), fs = (q + ez) & 3, o = (ly + 1 + ey) * kLfFX + (lx + 1 + ex);
+            d = sr[rs][0][o];
+            u0_ = sr[rs][1][o] * us;
+            u1_ = sr[rs][2][o] * us;
+            u2_ = sr[rs][3][o] * us;
+            f0 = sF[fs][0][o];
+            f1 = sF[fs][1][o];
+            f2 = sF[fs][2][o];
+        };
+        float dnew, un0, un1, un2;
+        fluid_update<Q27>(at, c, dnew, un0, un1, un2);
+        const int64_t k = (int64_t)q * plane + ox + (int64_t)nx * oy;
+        fluid_store(k, N, dnew, un0, un1, un2, a.rho_o, a.u_o, (__half *)nullptr, c);
+    };
+
+    // prologue: b planes z0 - 2 .. z0 and rho, u of plane z0 - 1 in LDS; the next planes requested
+    load_b(z0 - 2);
+    store_b(z0 - 2);
+    load_b(z0 - 1);
+    store_b(z0 - 1);
+    load_b(z0);
+    store_b(z0);
+    load_r(z0 - 1);
+    store_r(z0 - 1);
+    load_b(z0 + 1);
+    load_r(z0);
+    __syncthreads();
+    for (int p = z0 - 1; p <= z1; ++p) {
+        force(p);
+        store_b(p + 2);               // b is needed up to plane z1 + 1, rho and u up to z1; the
+        store_r(p + 1);               // requests below are clamped so that every one is issued
+        load_b(min(p + 3, z1 + 1));
+        load_r(min(p + 2, z1));
+        __syncthreads();
+        if (p - 1 >= z0 && own) fluid(p - 1);
     }
 }
 
@@ -885,6 +1099,21 @@ hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u
                         void *u_o, void *u_copy, StepConst c) {
     return fluid_kinds<false>(s, kinds, rho, u, F, rho_o, u_o, u_copy, c, nullptr, nullptr, 0);
 }
+hipError_t launch_lorentz_fluid(hipStream_t s, const LfArgs &a0) {
+    LfArgs a = a0;
+    a.tiles_x = (a.c.nx + kLfTX - 1) / kLfTX;
+    a.tiles_y = (a.c.ny + kLfTY - 1) / kLfTY;
+    const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
+    a.zchunk = cols * ((a.c.nz + 15) / 16) >= 512 ? 16 : 8;  // 16-plane chunks when they fill the chip
+    a.nblocks = (int)(cols * ((a.c.nz + a.zchunk - 1) / a.zchunk));
+    const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
+    if (a.c.lattice == 27)
+        hipLaunchKernelGGL(k_lorentz_fluid<true>, grid, dim3(kCellThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_lorentz_fluid<false>, grid, dim3(kCellThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_fluid_batch(hipStream_t s, int kinds, const PipeStep *tab, const BlockMap *map, int nblocks,
                               bool q27) {
     StepConst c{};

@@ -173,6 +173,7 @@ struct mhd_sim {
     };
     std::vector<StepGraph> graphs;
     bool graph_on = true;
+    bool fused_lf = true;  // Lorentz + fluid in one launch where the storage allows (MHD_FUSED_LF=0: two)
     // Scratch of the step kernels taken from elsewhere than the workspace while set (the
     // allocation-free entry point): Lorentz force F, wall corrections, flow and budget partials.
     struct Scratch {
@@ -468,17 +469,31 @@ mhd_status one_step(mhd_sim *s) {
     STEPCHK(timed(s, MHD_K_CONTROL, "ctrl_begin", [&] { return launch_ctrl_begin(st, s->ctrl(), c); }));
     // 1. magnetic iteration, wall correction after every sweep
     for (int m = 0; m < s->prm.n_mag; ++m) STEPCHK(mag_iteration(s, c, m));
-    // 2. Lorentz + body force from the new b
-    float *F = s->F_buf();
-    STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
-        return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->bh(s->ch), s->at<float>(s->L.bext), s->byz(),
-                              s->ctrl(), F, c);
-    }));
-    // 3. fluid predictor, 4. velocity wall correction
+    // 2. Lorentz + body force from the new b, 3. fluid predictor (one launch for float32 boxes:
+    // the force then stays in LDS), 4. velocity wall correction
     const int nr = 1 - s->cr, nu = 1 - s->cu;
-    STEPCHK(timed(s, MHD_K_FLUID, "fluid", [&] {
-        return launch_fluid(st, s->kinds, s->rho(s->cr), s->u(s->cu), F, s->rho(nr), s->u(nu), s->u16(), c);
-    }));
+    if (s->fused_lf && s->kinds == pack_kinds(MHD_STORE_F32, MHD_STORE_F32, MHD_STORE_F32)) {
+        LfArgs a{};
+        a.rho = static_cast<const float *>(s->rho(s->cr));
+        a.u = static_cast<const float *>(s->u(s->cu));
+        a.b = static_cast<const float *>(s->b(s->cb));
+        a.bext = s->at<float>(s->L.bext);
+        a.bext_yz = s->byz();
+        a.ctrl = s->ctrl();
+        a.rho_o = static_cast<float *>(s->rho(nr));
+        a.u_o = static_cast<float *>(s->u(nu));
+        a.c = c;
+        STEPCHK(timed(s, MHD_K_FLUID, "lorentz + fluid", [&] { return launch_lorentz_fluid(st, a); }));
+    } else {
+        float *F = s->F_buf();
+        STEPCHK(timed(s, MHD_K_LORENTZ, "lorentz", [&] {
+            return launch_lorentz(st, s->g.b_storage, s->b(s->cb), s->bh(s->ch), s->at<float>(s->L.bext), s->byz(),
+                                  s->ctrl(), F, c);
+        }));
+        STEPCHK(timed(s, MHD_K_FLUID, "fluid", [&] {
+            return launch_fluid(st, s->kinds, s->rho(s->cr), s->u(s->cu), F, s->rho(nr), s->u(nu), s->u16(), c);
+        }));
+    }
     STEPCHK(ib_correct(s, s->g.u_storage, s->u(nu), c.u_scale, c.inv_u_scale, s->at<float>(s->L.s_u),
                        s->at<float>(s->L.uwall), nullptr, s->u16(), c.inv_copy_scale));
     s->cr = nr;
@@ -815,6 +830,7 @@ mhd_status mhd_set_params(mhd_sim *s, const mhd_params *p) {
     const bool first = !s->have_params;
     const mhd_params old = s->prm;
     drop_step_graphs(s);
+    s->fused_lf = env_int("MHD_FUSED_LF", 1) != 0;
     s->prm = *p;
     s->have_params = true;
     if (s->owner) batch_touch(s->owner);

@@ -701,3 +701,58 @@ def test_paired_tiles_agree_bitwise_on_a_128_wide_box(bext):
             for f, x, y in zip(("rho", "u", "b"), ref, got):
                 assert np.array_equal(x, y), (tiles, f, float(np.abs(x - y).max()))
         sim.close()
+
+
+@pytest.mark.parametrize("case", ["pipe", "ragged", "tiny", "q27", "six_magnets", "macroscopic", "gamma"])
+def test_fused_lorentz_fluid_equals_the_two_kernels_bitwise(case, monkeypatch):
+    """float32 boxes take the Lorentz force and the fluid update in one plane-marching launch
+    (the force stays in LDS). It runs the same cell arithmetic as the two separate kernels, so the
+    fields equal theirs bit for bit; MHD_FUSED_LF=0 at mhd_set_params selects the two kernels.
+    Covers ragged tiles (37 x 21 x 13, 1 x 24 x 1), D3Q27, the six-magnet table, the macroscopic
+    branch (tau >= 1) and the rescaled update."""
+    from paper_2211_09370_amd import MHD_K_LORENTZ, Sim
+
+    over = {}
+    if case == "pipe":
+        w = W.small_pipe(rho_amp=1e-3, b_amp=1e-3)
+        w.params.n_mag = 4
+    elif case == "ragged":
+        w = random_box(37, 21, 13, key=220, n_mag=2)
+    elif case == "q27":
+        w = random_box(16, 16, 9, key=221, n_mag=2)
+        over = dict(lattice=27)
+    elif case == "six_magnets":
+        w = W.pipe_workload("six_magnets", 222, 16, 33, 33, 14.0, 50.0, 10.0, 1e-2,
+                            bext_kind=W.BEXT_SIX_MAGNETS, n_mag=3, b_amp=1e-3, noise=1e-2)
+    elif case == "tiny":  # one cell across x and z: every halo wraps onto itself (no wall)
+        w = random_box(1, 24, 1, key=225, n_mag=2)
+        w.markers = np.zeros((3, 0))
+    elif case == "macroscopic":
+        w = random_box(16, 24, 20, key=223, n_mag=2, nu=0.3)
+    else:
+        w = random_box(32, 11, 17, key=224, n_mag=2)
+        over = dict(gamma=2.5)
+    print("case fused lorentz-fluid", case, flush=True)
+    out = {}
+    for fused in (True, False):
+        monkeypatch.setenv("MHD_FUSED_LF", "1" if fused else "0")
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+        sim.set_markers(w.markers)
+        sim.set_params(w.params, **over)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.step(2)
+        sim.set_profiling(True)
+        sim.step(1)
+        n_lorentz, _ = sim.kernel_stats(MHD_K_LORENTZ)
+        sim.set_profiling(False)
+        assert n_lorentz == (0 if fused else 1), (fused, n_lorentz)
+        out[fused] = [sim.get_field(f) for f in ("rho", "u", "b")]
+        sim.close()
+    for f, x, y in zip(("rho", "u", "b"), out[True], out[False]):
+        assert np.array_equal(x, y), (case, f, float(np.abs(x - y).max()))
+    compare_w = oracle_run(w, 3, markers=w.markers.shape[1] > 0, **over)
+    rho_s = max(np.abs(compare_w.rho - 1.0).max(), math.sqrt(3.0) * np.abs(compare_w.u).max())
+    assert np.abs(out[True][0] - compare_w.rho).max() <= TOL * rho_s
+    assert err(out[True][1], compare_w.u) <= TOL and err(out[True][2], compare_w.b) <= TOL

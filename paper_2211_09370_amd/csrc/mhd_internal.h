@@ -98,6 +98,16 @@ struct IbArgs {
     const void *phi_hi;    // split form: hi part of the field, added in the interpolation (else NULL)
     void *copy;            // float16 copy of the field refreshed at corrected cells (else NULL)
     float copy_inv;        // 1 / scale of that copy
+    // Line-structured walls (ring != 0): every marker sits on an integer x plane and the markers
+    // form lines, one marker per x plane at each (y, z) position, internal index j = line * nx + x,
+    // n_x a multiple of 64. Taps and gather entries then repeat along x and are read from
+    // per-line and per-band-row tables (wave-uniform); band cell e = row * nx + x.
+    int ring, nx, kmr;
+    const int *ring_tap;   // [lines][tm] tap offsets nx (y + ny z) (padding repeats the first)
+    const float *ring_tw;  // [lines][tm] tap weights (0 for padding)
+    const int *row_off;    // [rows] offset nx (y + ny z) of each band row, increasing
+    const int *row_mk;     // [rows][kmr] line of each gather entry (padding: a valid line)
+    const float *row_w;    // [rows][kmr] weight of each gather entry (0 for padding)
 };
 // Interpolation launch, then spreading launch.
 hipError_t launch_ib(hipStream_t s, int kind, void *phi, float scale, float inv_scale, const IbArgs &a);

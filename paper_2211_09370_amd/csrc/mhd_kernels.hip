@@ -165,16 +165,50 @@ __global__ void k_reset_records(DevCtrl *ctrl) {
 // and then by x, band cells by cell index: neighbouring lanes of a wave then address
 // neighbouring x, i.e. consecutive words of the x-fastest fields.
 // -------------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void ib_marker(const T *phi, float scale, const IbArgs &a, int j, float &d0, float &d1,
-                                          float &d2) {
+// Where the taps of a marker and the gather entries of a band cell come from: the general
+// padded structure-of-arrays tables, or (line-structured walls) the tables of the marker's line
+// and of the cell's band row, whose wave-uniform index lets them be read with scalar loads.
+// Both list taps and entries in the same order, so the two forms give the same bits.
+struct GeneralTaps {
+    const int *cell;
+    const float *w;
+    int64_t M;
+    int j;
+    __device__ int64_t k(int t) const { return cell[(int64_t)t * M + j]; }
+    __device__ float wt(int t) const { return w[(int64_t)t * M + j]; }
+};
+struct LineTaps {
+    const int *off;  // this line's tap offsets
+    const float *w;
+    int x;
+    __device__ int64_t k(int t) const { return x + off[t]; }
+    __device__ float wt(int t) const { return w[t]; }
+};
+struct GeneralEntries {
+    const int *mk;
+    const float *w;
+    int nband, e;
+    __device__ int j(int q) const { return mk[(int64_t)q * nband + e]; }
+    __device__ float wt(int q) const { return w[(int64_t)q * nband + e]; }
+};
+struct RowEntries {
+    const int *mk;  // this row's entry lines
+    const float *w;
+    int nx, x;
+    __device__ int j(int q) const { return mk[q] * nx + x; }
+    __device__ float wt(int q) const { return w[q]; }
+};
+
+template <typename T, typename Taps>
+__device__ __forceinline__ void ib_marker(const T *phi, float scale, const IbArgs &a, int j, const Taps &tp,
+                                          float &d0, float &d1, float &d2) {
     float I0 = 0.f, I1 = 0.f, I2 = 0.f;
     const T *hi = (const T *)a.phi_hi;
     if (hi) {  // split form: the field is (hi + lo) scale
 #pragma unroll 9
         for (int t = 0; t < a.tm; ++t) {
-            const int64_t k = a.tap_cell[(int64_t)t * a.M + j];
-            const float w = a.tap_w[(int64_t)t * a.M + j];
+            const int64_t k = tp.k(t);
+            const float w = tp.wt(t);
             I0 += w * ((St<T>::ld(phi, k) + St<T>::ld(hi, k)) * scale);
             I1 += w * ((St<T>::ld(phi, a.N + k) + St<T>::ld(hi, a.N + k)) * scale);
             I2 += w * ((St<T>::ld(phi, 2 * a.N + k) + St<T>::ld(hi, 2 * a.N + k)) * scale);
@@ -182,8 +216,8 @@ __device__ __forceinline__ void ib_marker(const T *phi, float scale, const IbArg
     } else {
 #pragma unroll 9
         for (int t = 0; t < a.tm; ++t) {
-            const int64_t k = a.tap_cell[(int64_t)t * a.M + j];
-            const float w = a.tap_w[(int64_t)t * a.M + j];
+            const int64_t k = tp.k(t);
+            const float w = tp.wt(t);
             I0 += w * (St<T>::ld(phi, k) * scale);
             I1 += w * (St<T>::ld(phi, a.N + k) * scale);
             I2 += w * (St<T>::ld(phi, 2 * a.N + k) * scale);
@@ -195,17 +229,16 @@ __device__ __forceinline__ void ib_marker(const T *phi, float scale, const IbArg
     d2 = s * (a.wall[2 * a.M + j] - I2);
 }
 
-template <typename T>
-__device__ __forceinline__ void ib_cell(T *phi, float scale, float inv_scale, const IbArgs &a, int e,
-                                        const float *d0, const float *d1, const float *d2, int base) {
-    const int64_t k = a.band_cell[e];
+template <typename T, typename Ents>
+__device__ __forceinline__ void ib_cell(T *phi, float scale, float inv_scale, const IbArgs &a, int64_t k, int km,
+                                        const Ents &en, const float *d0, const float *d1, const float *d2) {
     const float v0 = St<T>::ld(phi, k) * scale, v1 = St<T>::ld(phi, a.N + k) * scale,
                 v2 = St<T>::ld(phi, 2 * a.N + k) * scale;
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
 #pragma unroll 4
-    for (int q = 0; q < a.km; ++q) {
-        const int j = a.band_mk[(int64_t)q * a.nband + e] - base;
-        const float w = a.band_w[(int64_t)q * a.nband + e];
+    for (int q = 0; q < km; ++q) {
+        const int j = en.j(q);
+        const float w = en.wt(q);
         c0 += w * d0[j];
         c1 += w * d1[j];
         c2 += w * d2[j];
@@ -236,7 +269,14 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_interp(const T *phi, float sc
     const int j = blk * kIbThreads + threadIdx.x;
     if (j >= a.M) return;
     float d0, d1, d2;
-    ib_marker(phi, scale, a, j, d0, d1, d2);
+    if (a.ring) {  // the wave's 64 markers: consecutive x of one line (n_x % 64 == 0)
+        const int j0 = blk * kIbThreads + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63);
+        const int line = j0 / a.nx;
+        const LineTaps tp{a.ring_tap + (int64_t)line * a.tm, a.ring_tw + (int64_t)line * a.tm, j - line * a.nx};
+        ib_marker(phi, scale, a, j, tp, d0, d1, d2);
+    } else {
+        ib_marker(phi, scale, a, j, GeneralTaps{a.tap_cell, a.tap_w, a.M, j}, d0, d1, d2);
+    }
     a.delta[j] = d0;
     a.delta[a.M + j] = d1;
     a.delta[2 * a.M + j] = d2;
@@ -257,7 +297,16 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_spread(T *phi, float scale, f
     }
     const int e = blk * kIbThreads + threadIdx.x;
     if (e >= a.nband) return;
-    ib_cell(phi, scale, inv_scale, a, e, a.delta, a.delta + a.M, a.delta + 2 * a.M, 0);
+    const float *d0 = a.delta, *d1 = a.delta + a.M, *d2 = a.delta + 2 * a.M;
+    if (a.ring) {  // the wave's 64 cells: consecutive x of one band row (n_x % 64 == 0)
+        const int e0 = blk * kIbThreads + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63);
+        const int row = e0 / a.nx, x = e - row * a.nx;
+        const RowEntries en{a.row_mk + (int64_t)row * a.kmr, a.row_w + (int64_t)row * a.kmr, a.nx, x};
+        ib_cell(phi, scale, inv_scale, a, (int64_t)x + a.row_off[row], a.kmr, en, d0, d1, d2);
+    } else {
+        ib_cell(phi, scale, inv_scale, a, (int64_t)a.band_cell[e], a.km, GeneralEntries{a.band_mk, a.band_w, a.nband, e},
+                d0, d1, d2);
+    }
 }
 
 // -------------------------------------------------------------------------------------------

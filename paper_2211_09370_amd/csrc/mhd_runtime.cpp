@@ -57,6 +57,7 @@ constexpr int64_t kBandSlots = 64;
 struct Layout {
     size_t rho[2], u[2], b[2], bh[2], u16, F, bext, bext_yz, ctrl, tap_cell, tap_w, s_u, s_b, uwall, bwall, delta;
     size_t band_cell, band_mk, band_w, red_part, flow_part, ring, res, total;
+    size_t ring_tap, ring_tw, row_off, row_mk, row_w;  // line-structured walls
 };
 
 Layout make_layout(const mhd_grid_desc &g, int64_t M) {
@@ -91,6 +92,12 @@ Layout make_layout(const mhd_grid_desc &g, int64_t M) {
     L.band_cell = take(T * sizeof(int));
     L.band_mk = take(TB * sizeof(int));
     L.band_w = take(TB * sizeof(float));
+    // line tables: lines * taps, band rows and rows * entries are each at most M when n_x >= 64
+    L.ring_tap = take(M * sizeof(int));
+    L.ring_tw = take(M * sizeof(float));
+    L.row_off = take(M * sizeof(int));
+    L.row_mk = take(M * sizeof(int));
+    L.row_w = take(M * sizeof(float));
     L.red_part = take((size_t)kRedBlocks * kBudgetVals * sizeof(double));
     L.flow_part = take((size_t)kRedBlocks * sizeof(double));
     L.ring = take((size_t)kRingCap * sizeof(mhd_budget));
@@ -156,6 +163,9 @@ struct mhd_sim {
     int64_t M = 0, nband = 0;
     int tm = 0, km = 0;
     std::vector<double> d;  // row sums of D D^T (internal marker order)
+    // line-structured wall (tables uploaded) and whether its kernels are used (MHD_IB_RING=0: the
+    // general tables, same bits)
+    bool lines = false, ring_on = false;
     int64_t t_host = 0;
     SweepLaunch sweep{64, 4, 8, 0};
     double flow_inv_count = 0.0;
@@ -413,25 +423,15 @@ mhd_status timed(mhd_sim *s, int k, const char *what, Fn fn) {
         if (st_ != MHD_OK) return st_; \
     } while (0)
 
+IbArgs ib_args(mhd_sim *s, const float *sj, const float *wall);
+
 mhd_status ib_correct(mhd_sim *s, int kind, void *phi, float scale, float inv_scale, const float *sj,
                       const float *wall, const void *phi_hi, void *copy, float copy_inv) {
     if (s->M == 0) return MHD_OK;
-    IbArgs a;
+    IbArgs a = ib_args(s, sj, wall);
     a.phi_hi = phi_hi;
     a.copy = copy;
     a.copy_inv = copy_inv;
-    a.N = s->N;
-    a.M = (int)s->M;
-    a.nband = (int)s->nband;
-    a.tm = s->tm;
-    a.km = s->km;
-    a.tap_cell = s->at<int>(s->L.tap_cell);
-    a.tap_w = s->at<float>(s->L.tap_w);
-    a.sj = sj;
-    a.wall = wall;
-    a.band_cell = s->at<int>(s->L.band_cell);
-    a.band_mk = s->at<int>(s->L.band_mk);
-    a.band_w = s->at<float>(s->L.band_w);
     a.delta = s->delta_buf();
     return timed(s, MHD_K_IB, "wall correction",
                  [&] { return launch_ib(s->stream, kind, phi, scale, inv_scale, a); });
@@ -706,14 +706,40 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
         }
     }
     // 3. internal order: by the (y, z) of the first tap, then x, so that markers at the same
-    //    cross-section position on neighbouring x planes sit next to each other
+    //    cross-section position on neighbouring x planes sit next to each other. Line-structured
+    //    walls (every marker on an integer x plane, and at each (y, z) position one marker on every
+    //    x plane: the rings of a straight pipe) keep each line together, so that marker
+    //    line * nx + x is the line's marker on plane x.
     const int nx = n[0];
+    std::vector<int64_t> line_key((size_t)M, 0);  // first original index of the marker's line
+    bool lines = M > 0 && M % nx == 0;
+    for (int64_t j = 0; j < M && lines; ++j) lines = xyz[j] == std::floor(xyz[j]);
+    if (lines) {
+        std::vector<int64_t> o((size_t)M);
+        for (int64_t j = 0; j < M; ++j) o[j] = j;
+        std::stable_sort(o.begin(), o.end(), [&](int64_t a, int64_t b) {
+            if (xyz[M + a] != xyz[M + b]) return xyz[M + a] < xyz[M + b];
+            if (xyz[2 * M + a] != xyz[2 * M + b]) return xyz[2 * M + a] < xyz[2 * M + b];
+            return xyz[a] < xyz[b];
+        });
+        for (int64_t g0 = 0; g0 < M && lines; g0 += nx) {
+            int64_t first = o[g0];
+            for (int x = 0; x < nx && lines; ++x) {
+                const int64_t j = o[g0 + x];
+                lines = xyz[j] == (double)x && xyz[M + j] == xyz[M + o[g0]] && xyz[2 * M + j] == xyz[2 * M + o[g0]];
+                first = std::min(first, j);
+            }
+            for (int x = 0; x < nx; ++x) line_key[o[g0 + x]] = first;
+        }
+    }
     std::vector<int64_t> perm((size_t)M);
     for (int64_t j = 0; j < M; ++j) perm[j] = j;
     std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
         const int ka = tcell[tptr[a]], kb = tcell[tptr[b]];
         const int ya = ka / nx, yb = kb / nx;
-        return ya != yb ? ya < yb : (ka % nx) < (kb % nx);
+        if (ya != yb) return ya < yb;
+        if (lines && line_key[a] != line_key[b]) return line_key[a] < line_key[b];
+        return (ka % nx) < (kb % nx);
     });
     int tm = 1;
     for (int64_t j = 0; j < M; ++j) tm = std::max(tm, tptr[j + 1] - tptr[j]);
@@ -764,6 +790,51 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
             band_w[(size_t)q * nband + e] = real ? (float)ent[a + q].w : 0.f;
         }
     }
+    // 4b. line tables (n_x a multiple of 64, so a wave's 64 markers or band cells share one line
+    //     or band row): the taps of line l are those of its marker on plane 0, shifted by x; the
+    //     entries of band row r those of its cell on plane 0, with the line of each entry. Every
+    //     marker and band cell is checked against the general tables, so the two forms read the
+    //     same taps and entries in the same order.
+    const int64_t nlines = lines ? M / nx : 0;
+    const int64_t nrows = lines ? nband / nx : 0;
+    bool ring = lines && nx % 64 == 0 && nband % nx == 0;
+    std::vector<int> ring_tap, row_off, row_mk;
+    std::vector<float> ring_tw, row_w;
+    if (ring) {
+        ring_tap.resize((size_t)(nlines * tm));
+        ring_tw.resize((size_t)(nlines * tm));
+        for (int64_t l = 0; l < nlines; ++l)
+            for (int t = 0; t < tm; ++t) {
+                ring_tap[(size_t)(l * tm + t)] = tap_cell[(size_t)t * M + l * nx];
+                ring_tw[(size_t)(l * tm + t)] = tap_w[(size_t)t * M + l * nx];
+            }
+        for (int64_t i = 0; i < M && ring; ++i) {
+            const int64_t l = i / nx, x = i % nx;
+            for (int t = 0; t < tm && ring; ++t)
+                ring = tap_cell[(size_t)t * M + i] == x + ring_tap[(size_t)(l * tm + t)] &&
+                       tap_w[(size_t)t * M + i] == ring_tw[(size_t)(l * tm + t)];
+        }
+    }
+    if (ring) {
+        row_off.resize((size_t)nrows);
+        row_mk.resize((size_t)(nrows * km));
+        row_w.resize((size_t)(nrows * km));
+        for (int64_t r = 0; r < nrows; ++r) {
+            row_off[r] = band_cell[(size_t)(r * nx)];
+            for (int q = 0; q < km; ++q) {
+                row_mk[(size_t)(r * km + q)] = band_mk[(size_t)q * nband + r * nx] / nx;
+                row_w[(size_t)(r * km + q)] = band_w[(size_t)q * nband + r * nx];
+            }
+        }
+        for (int64_t e = 0; e < nband && ring; ++e) {
+            const int64_t r = e / nx, x = e % nx;
+            ring = band_cell[e] == x + row_off[r];
+            for (int q = 0; q < km && ring; ++q)
+                ring = band_mk[(size_t)q * nband + e] == row_mk[(size_t)(r * km + q)] * nx + x &&
+                       band_w[(size_t)q * nband + e] == row_w[(size_t)(r * km + q)];
+        }
+        ring = ring && nlines * tm <= s->Mcap && nrows <= s->Mcap && nrows * km <= s->Mcap;
+    }
     // 5. wall values in internal order
     std::vector<float> uw((size_t)(3 * M), 0.f), bw((size_t)(3 * M), 0.f);
     for (int64_t i = 0; i < M; ++i)
@@ -775,6 +846,11 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream);
     };
+    // MHD_IB_RING: 0 = general tables only, 1 (default) = line tables where the wall allows,
+    // 2 = line tables required (the call fails otherwise)
+    const int ring_mode = env_int("MHD_IB_RING", 1);
+    if (ring_mode == 2 && !ring)
+        return fail(MHD_ERR_UNSUPPORTED, "MHD_IB_RING=2: the markers are not line-structured with n_x %% 64 == 0");
     HIPCHK(hipStreamSynchronize(s->stream));
     HIPCHK(up(s->L.tap_cell, tap_cell.data(), tap_cell.size() * sizeof(int)));
     HIPCHK(up(s->L.tap_w, tap_w.data(), tap_w.size() * sizeof(float)));
@@ -783,7 +859,16 @@ mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const doubl
     HIPCHK(up(s->L.band_cell, band_cell.data(), band_cell.size() * sizeof(int)));
     HIPCHK(up(s->L.band_mk, band_mk.data(), band_mk.size() * sizeof(int)));
     HIPCHK(up(s->L.band_w, band_w.data(), band_w.size() * sizeof(float)));
+    if (ring) {
+        HIPCHK(up(s->L.ring_tap, ring_tap.data(), ring_tap.size() * sizeof(int)));
+        HIPCHK(up(s->L.ring_tw, ring_tw.data(), ring_tw.size() * sizeof(float)));
+        HIPCHK(up(s->L.row_off, row_off.data(), row_off.size() * sizeof(int)));
+        HIPCHK(up(s->L.row_mk, row_mk.data(), row_mk.size() * sizeof(int)));
+        HIPCHK(up(s->L.row_w, row_w.data(), row_w.size() * sizeof(float)));
+    }
     HIPCHK(hipStreamSynchronize(s->stream));
+    s->lines = ring;
+    s->ring_on = ring && ring_mode != 0;
     s->M = M;
     s->nband = nband;
     s->tm = tm;
@@ -1452,6 +1537,14 @@ IbArgs ib_args(mhd_sim *s, const float *sj, const float *wall) {
     a.band_mk = s->at<int>(s->L.band_mk);
     a.band_w = s->at<float>(s->L.band_w);
     a.delta = s->at<float>(s->L.delta);
+    a.ring = s->ring_on ? 1 : 0;
+    a.nx = s->g.nx;
+    a.kmr = s->km;
+    a.ring_tap = s->at<int>(s->L.ring_tap);
+    a.ring_tw = s->at<float>(s->L.ring_tw);
+    a.row_off = s->at<int>(s->L.row_off);
+    a.row_mk = s->at<int>(s->L.row_mk);
+    a.row_w = s->at<float>(s->L.row_w);
     return a;
 }
 

@@ -756,3 +756,78 @@ def test_fused_lorentz_fluid_equals_the_two_kernels_bitwise(case, monkeypatch):
     rho_s = max(np.abs(compare_w.rho - 1.0).max(), math.sqrt(3.0) * np.abs(compare_w.u).max())
     assert np.abs(out[True][0] - compare_w.rho).max() <= TOL * rho_s
     assert err(out[True][1], compare_w.u) <= TOL and err(out[True][2], compare_w.b) <= TOL
+
+
+LINE_CASES = ["f32", "wall_values", "shuffled_two_rings", "split", "f16", "nx256"]
+
+
+@pytest.mark.parametrize("case", LINE_CASES)
+def test_line_wall_tables_equal_the_general_tables_bitwise(case, monkeypatch):
+    """Walls made of lines (every marker on an integer x plane, one marker per plane at each
+    (y, z) position: the rings of a straight pipe) with n_x a multiple of 64 take the wall
+    correction from per-line and per-band-row tables. They list the same taps and entries in the
+    same order as the general tables, so the fields equal the general path's bit for bit
+    (MHD_IB_RING=0 at mhd_set_markers selects it; =2 requires the line tables, so that the first
+    run is known to use them). Covers nonzero wall values of both fields, markers handed over in
+    shuffled order with two rings close enough to share first-tap rows, the split and float16
+    storage (hi part and float16 copy of u), and the halo-column sweep (n_x = 256)."""
+    from paper_2211_09370_amd import Sim
+
+    store, u_wall, b_wall = {}, None, None
+    if case == "nx256":
+        w = random_box(256, 14, 12, key=236, n_mag=3, R=4.5)
+    else:
+        w = random_box(128, 40, 36, key=230, n_mag=3)
+    M = w.markers.shape[1]
+    if case == "wall_values":
+        g = W.rng_for(231)
+        u_wall = 0.01 * g.uniform(-1, 1, size=(3, M))
+        b_wall = 0.002 * g.uniform(-1, 1, size=(3, M))
+    elif case == "shuffled_two_rings":
+        inner = W.pipe_markers(w.nx, w.R - 0.55, w.ny // 2, w.nz // 2)
+        X = np.concatenate([w.markers, inner], axis=1)
+        w.markers = X[:, W.rng_for(232).permutation(X.shape[1])]
+    elif case == "split":
+        store = dict(b_storage="f16split", u_scale=0.05, b_scale=0.01)
+    elif case == "f16":
+        store = dict(rho_storage="f16", u_storage="f16", b_storage="f16", u_scale=0.05, b_scale=0.01)
+    print("case line wall tables", case, flush=True)
+    out = {}
+    for mode in ("2", "0"):
+        monkeypatch.setenv("MHD_IB_RING", mode)
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], **store)
+        sim.set_markers(w.markers, u_wall, b_wall)
+        sim.set_params(w.params)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.step(3)
+        out[mode] = [sim.get_field(f) for f in ("rho", "u", "b")]
+        sim.close()
+    for f, x, y in zip(("rho", "u", "b"), out["2"], out["0"]):
+        assert np.array_equal(x, y), (case, f, float(np.abs(x - y).max()))
+    if not store:
+        o = oracle_run(w, 3, u_wall=u_wall, b_wall=b_wall)
+        rho_s = max(np.abs(o.rho - 1.0).max(), math.sqrt(3.0) * np.abs(o.u).max())
+        assert np.abs(out["2"][0] - o.rho).max() <= TOL * rho_s
+        assert err(out["2"][1], o.u) <= TOL and err(out["2"][2], o.b) <= TOL
+
+
+def test_line_tables_are_refused_where_the_wall_has_no_lines(monkeypatch):
+    """MHD_IB_RING=2 makes set_markers fail when the wall is not line-structured: a marker off
+    its x plane, a line missing a plane, or n_x not a multiple of 64."""
+    from paper_2211_09370_amd import Sim
+    from paper_2211_09370_amd._abi import MHD_ERR_UNSUPPORTED, MhdError
+
+    monkeypatch.setenv("MHD_IB_RING", "2")
+    w = random_box(128, 20, 22, key=233, n_mag=1)
+    off_plane = w.markers.copy()
+    off_plane[0, 5] += 0.25
+    missing = w.markers[:, 1:]
+    for name, X, nx in (("off plane", off_plane, 128), ("missing plane", missing, 128),
+                        ("n_x 96", W.pipe_markers(96, 5.0, 10, 11), 96)):
+        sim = Sim(nx, w.ny, w.nz, X.shape[1])
+        with pytest.raises(MhdError) as ei:
+            sim.set_markers(X)
+        assert ei.value.status == MHD_ERR_UNSUPPORTED, name
+        sim.close()

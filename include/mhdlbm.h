@@ -167,7 +167,13 @@ mhd_status mhd_create(const mhd_grid_desc *g, int64_t n_markers, void *dev_works
  * u_wall, b_wall (host, 3*M component-major, NULL -> 0). Copied; caller keeps ownership.
  * Each coordinate must lie in [0, n) of its axis (the stencil wraps periodically).
  * Computes the Lagrange taps (Sec. 5.2), the row sums d_j of D D^T (Sec. 5.3) and the
- * gather lists of the spreading step. M = 0 removes the wall. */
+ * gather lists of the spreading step. M = 0 removes the wall. A wall made of lines (every
+ * marker on an integer x plane and, at each (y, z) position, one marker on every x plane, as
+ * the rings of a straight pipe) with n_x a multiple of 64 is also stored as per-line and
+ * per-band-row tables, which the corrections then read (the same taps and entries in the
+ * same order, so the same results). The environment variable MHD_IB_RING, read here, selects:
+ * 0 = general tables only, 1 (default) = line tables where the wall allows, 2 = line tables
+ * required (UNSUPPORTED otherwise). */
 mhd_status mhd_set_markers(mhd_sim *s, const double *xyz, int64_t M, const double *u_wall,
                            const double *b_wall);
 

@@ -18,6 +18,8 @@ cell does not depend on the box length).
 batched = the batched form on 64 independent pipes of uneven size and physics (~74 M cells,
 ~2.3 M markers, tiles autotuned), MLUPS over all their cells (an extra object, not `value`),
 next to the same pipes stepped one at a time with the same tiles (sequential_MLUPS).
+shard = one GPU's share of the 512 x 256 x 256 pipe under the axial slab decomposition (64- and
+128-plane slabs, periodic in x in place of the halo exchange): step rate, sweep time, halo bytes.
 accelerated = the accelerated magnetic iteration (alpha = 1/2, 135 sweeps) on the same box, with the
 induction residual after a step next to the plain method's (an extra object, not `value`).
 precision = float32 against the 16-bit storage forms on the 512 x 256 x 256 pipe at 270 sweeps
@@ -171,6 +173,60 @@ def hbm_roofline_leg(n_sweeps=None, profile_steps=1):
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": read_traffic(), "kernel": "mag_sweep",
             "workload": w.name, "box": [w.nx, w.ny, w.nz], "tiles": tiles, "launches": n_launch,
             "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes}
+
+
+def shard_leg(steps=3):
+    """One GPU's share of the 512 x 256 x 256 pipe under the axial slab decomposition: the float32
+    step on a 64-plane (one of eight GPUs) and a 128-plane (one of four) slab of the same pipe,
+    periodic in x where the slabs would exchange halos (nothing crosses GPUs here). Reports the
+    slab's step rate, its sweep and wall-correction times, and the halo a sweep would send (the two
+    x faces of b, three float32 components each)."""
+    import torch
+
+    import workloads as W
+    from paper_2211_09370_amd import MHD_K_IB, MHD_K_MAG_SWEEP, Sim
+
+    res = []
+    for n_gpu, nx in ((8, 64), (4, 128)):
+        w = W.pipe_slab(nx)
+        stream = torch.cuda.Stream()
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1], stream=stream)
+        sim.set_markers(w.markers)
+        sim.set_params(w.params)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.step(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        sim.set_profiling(True)
+        sim.step(1)
+        n_sw, ms_sw = sim.kernel_stats(MHD_K_MAG_SWEEP)
+        n_ib, ms_ib = sim.kernel_stats(MHD_K_IB)
+        sim.set_profiling(False)
+        tiles = list(sim.tiles)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        sweep_us = ms_sw * 1e3 / max(n_sw, 1)
+        halo = 2 * w.ny * w.nz * 12
+        mlups = w.n_cells * steps / sec / 1e6
+        log(f"bench: slab {nx}x256^2 (1 of {n_gpu}): {mlups:.1f} MLUPS, sweep {sweep_us:.2f} us, "
+            f"halo {halo / 1e6:.2f} MB per sweep")
+        res.append({"gpus": n_gpu, "slab": [w.nx, w.ny, w.nz], "tiles": tiles, "MLUPS": round(mlups, 3),
+                    "ms_per_step": round(sec * 1e3 / steps, 4), "sweep_us": round(sweep_us, 3),
+                    "sweep_alg_GBs": round(SWEEP_BYTES_PER_CELL * w.n_cells / (sweep_us * 1e-6) / 1e9, 1),
+                    "wall_correction_us_per_sweep": round(ms_ib * 1e3 / max(n_sw, 1), 3),
+                    "halo_bytes_per_sweep": halo,
+                    "whole_pipe_MLUPS_if_halo_hidden": round(mlups * n_gpu, 1)})
+    return {"workload": "axial slabs of the 512 x 256 x 256 pipe (R = 120, Ha 30, Re 5000, Rm 1e-2, "
+                        "270 sweeps per step), periodic in x in place of the halo exchange",
+            "shares": res}
 
 
 def batched_leg(steps, seq_steps=2):
@@ -467,6 +523,7 @@ def main():
     ap.add_argument("--hbm-only", action="store_true", help="only the 512 x 256^2 sweep roofline leg")
     ap.add_argument("--hbm-sweeps", type=int, default=0, help="sweeps per step of that leg (0: 270)")
     ap.add_argument("--no-hbm", action="store_true")
+    ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share slab leg")
     ap.add_argument("--transition", nargs="+", type=float, metavar="RM",
                     help="run the unsteady large-pipe case at these Rm instead of the benchmark")
     ap.add_argument("--transition-forms", nargs="+", default=["f32", "f16split"])
@@ -551,6 +608,7 @@ def main():
         accel = accelerated_leg(w, args.steps, args.warmup + args.profile_steps, res_plain)
 
     hbm = None if args.no_hbm else hbm_roofline_leg(args.hbm_sweeps or None)
+    shard = None if args.no_shard else shard_leg()
     batched = None
     if not args.no_batch:
         batched = batched_leg(args.batch_steps)
@@ -589,6 +647,7 @@ def main():
         "finite": state_ok,
         "accelerated": accel,
         "batched": batched,
+        "shard": shard,
         "precision": precision,
         "cpu_baseline": cpu,
     }

@@ -184,6 +184,13 @@ def large_pipe(Rm=1e-2, **kw) -> Workload:
                          30.0, Rm, **kw)
 
 
+def pipe_slab(nx: int) -> Workload:
+    """One axial slab of the 512 x 256 x 256 pipe: the same cross-section, physics and ring,
+    nx planes long (64 = one GPU's share of eight, 128 = of four), periodic in x."""
+    return pipe_workload(f"pipe512x256x256_R120_Ha30_Rm0.01_slab{nx}", 5, nx, 256, 256, 120.0, 5000.0,
+                         30.0, 1e-2)
+
+
 def batch_pipes(n: int = 64, key: int = 4, R_range=(16.0, 64.0), lengths=(32, 64, 128, 256),
                 Ha_range=(1.0, 50.0), Rm_range=(1e-4, 1.0), Re_range=(50.0, 1000.0),
                 noise: float = 1e-4, n_mag_cap: int = 270):

@@ -412,10 +412,12 @@ __device__ __forceinline__ float wave_rol1(float v) {
 }
 
 // The halo form (without the six-magnet table) is held to three waves per SIMD (at most 168
-// VGPRs, no spills), so that three 4-row workgroups share a CU on large boxes instead of two:
-// the 16-bit forms' sweeps on 512 x 256 x 256 then take 5-6% less time, float32 about 1%.
+// VGPRs, no spills), so that three 4-row workgroups share a CU on large boxes instead of two: the
+// 16-bit forms' steps on 512 x 256 x 256 then run 5-6% faster and the float32 64-pipe batch 5%.
+// The single-box float32 form is left unbounded (the bound made its step 0.4% slower).
 template <int TY, typename TU, typename TB, bool BATCH, bool SPLIT, bool BYZ, bool Q27, bool XWRAP>
-__global__ void __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(XWRAP || BYZ ? 1 : 3)))
+__global__ void __launch_bounds__(64 * TY)
+__attribute__((amdgpu_waves_per_eu(XWRAP || BYZ || (std::is_same<TB, float>::value && !BATCH) ? 1 : 3)))
 k_mag_sweep_pair(SweepArgs a, const PipeStep *tab, const BlockMap *map,
                                                             int which, int nbatch) {
     using LW = Lat<Q27>;

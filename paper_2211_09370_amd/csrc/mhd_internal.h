@@ -118,16 +118,12 @@ hipError_t launch_lorentz(hipStream_t s, int kind_b, const void *b, const void *
 hipError_t launch_fluid(hipStream_t s, int kinds, const void *rho, const void *u, const float *F,
                         void *rho_o, void *u_o, void *u_copy, StepConst c);
 hipError_t launch_flow_partial(hipStream_t s, int kind_u, const void *u, double *part, StepConst c);
-// Lorentz force and fluid update in one launch (single boxes with float32 rho and u, b float32
-// or split; k_lorentz_fluid).
+// Lorentz force and fluid update in one launch (float32 single boxes; k_lorentz_fluid).
 struct LfArgs {
-    const float *rho, *u;         // state before the fluid update
-    const void *b;                // b after the magnetic iteration (float32, or the split form's lo)
-    const void *b_hi;             // split form: hi part of b (float16), else NULL
+    const float *rho, *u, *b;     // state before the fluid update (b after the magnetic iteration)
     const float *bext, *bext_yz;  // B_ext tables (bext_yz NULL unless six magnets)
     const DevCtrl *ctrl;
     float *rho_o, *u_o;           // new rho - 1 and u* (before the u wall correction)
-    void *u_copy;                 // split form: float16 copy of the new u, else NULL
     StepConst c;
     int tiles_x, tiles_y, zchunk, nblocks;  // filled in by the launcher
 };

@@ -608,8 +608,7 @@ __global__ void __launch_bounds__(kCellThreads) k_fluid(const TR *rho, const TU 
 }
 
 // -------------------------------------------------------------------------------------------
-// Lorentz force and fluid update in one plane-marching kernel (single boxes with float32 rho and
-// u; b float32 or, SPLIT, float16 hi + lo).
+// Lorentz force and fluid update in one plane-marching kernel (single boxes, float32 storage).
 // A workgroup owns a 64 x 4 column of cells and marches along z over a chunk of planes. Each
 // plane of b is staged in LDS with a two-cell halo, each plane of rho and u with a one-cell
 // halo; the force of a plane is formed in LDS on the one-cell halo from the three b planes
@@ -630,7 +629,7 @@ constexpr int kLfFS = (kLfFN + kCellThreads - 1) / kCellThreads;  // F / rho-u c
 
 __device__ __forceinline__ int ring5(int p) { return ((p % 5) + 5) % 5; }
 
-template <bool Q27, bool SPLIT>
+template <bool Q27>
 __global__ void __launch_bounds__(kCellThreads) k_lorentz_fluid(LfArgs a) {
     __shared__ float sb[4][3][kLfBN];
     __shared__ float sF[4][3][kLfFN];
@@ -670,20 +669,13 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz_fluid(LfArgs a) {
         fxy[s] = (unsigned)(wrapi(x0 - 1 + hx, nx) + nx * wrapi(y0 - 1 + hy, ny));
     }
     float rb[kLfBS][3], rr[kLfFS][4];
-    // b in stored units (the split form's hi + lo, added as k_lorentz adds them)
     auto load_b = [&](int p) {
         const unsigned off = (unsigned)wrapi(p, nz) * plane;
 #pragma unroll
         for (int s = 0; s < kLfBS; ++s)
             if (bval[s])
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const int64_t i = q * N + off + bxy[s];
-                    if constexpr (SPLIT)
-                        rb[s][q] = St<__half>::ld((const __half *)a.b, i) + St<__half>::ld((const __half *)a.b_hi, i);
-                    else
-                        rb[s][q] = ((const float *)a.b)[i];
-                }
+                for (int q = 0; q < 3; ++q) rb[s][q] = a.b[q * N + off + bxy[s]];
     };
     auto store_b = [&](int p) {
 #pragma unroll
@@ -759,7 +751,7 @@ __global__ void __launch_bounds__(kCellThreads) k_lorentz_fluid(LfArgs a) {
         float dnew, un0, un1, un2;
         fluid_update<Q27>(at, c, dnew, un0, un1, un2);
         const int64_t k = (int64_t)q * plane + ox + (int64_t)nx * oy;
-        fluid_store(k, N, dnew, un0, un1, un2, a.rho_o, a.u_o, (__half *)a.u_copy, c);
+        fluid_store(k, N, dnew, un0, un1, un2, a.rho_o, a.u_o, (__half *)nullptr, c);
     };
 
     // prologue: b planes z0 - 2 .. z0 and rho, u of plane z0 - 1 in LDS; the next planes requested
@@ -1164,18 +1156,10 @@ hipError_t launch_lorentz_fluid(hipStream_t s, const LfArgs &a0) {
     a.zchunk = cols * ((a.c.nz + 15) / 16) >= 512 ? 16 : 8;  // 16-plane chunks when they fill the chip
     a.nblocks = (int)(cols * ((a.c.nz + a.zchunk - 1) / a.zchunk));
     const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
-    const bool split = a.b_hi != nullptr;
-    if (a.c.lattice == 27) {
-        if (split)
-            hipLaunchKernelGGL((k_lorentz_fluid<true, true>), grid, dim3(kCellThreads), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_lorentz_fluid<true, false>), grid, dim3(kCellThreads), 0, s, a);
-    } else {
-        if (split)
-            hipLaunchKernelGGL((k_lorentz_fluid<false, true>), grid, dim3(kCellThreads), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_lorentz_fluid<false, false>), grid, dim3(kCellThreads), 0, s, a);
-    }
+    if (a.c.lattice == 27)
+        hipLaunchKernelGGL(k_lorentz_fluid<true>, grid, dim3(kCellThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_lorentz_fluid<false>, grid, dim3(kCellThreads), 0, s, a);
     return hipGetLastError();
 }
 

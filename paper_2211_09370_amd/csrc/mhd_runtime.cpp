@@ -469,17 +469,14 @@ mhd_status one_step(mhd_sim *s) {
     STEPCHK(timed(s, MHD_K_CONTROL, "ctrl_begin", [&] { return launch_ctrl_begin(st, s->ctrl(), c); }));
     // 1. magnetic iteration, wall correction after every sweep
     for (int m = 0; m < s->prm.n_mag; ++m) STEPCHK(mag_iteration(s, c, m));
-    // 2. Lorentz + body force from the new b, 3. fluid predictor (one launch when rho and u are
-    // float32 and b float32 or split: the force then stays in LDS), 4. velocity wall correction
+    // 2. Lorentz + body force from the new b, 3. fluid predictor (one launch for float32 boxes:
+    // the force then stays in LDS), 4. velocity wall correction
     const int nr = 1 - s->cr, nu = 1 - s->cu;
-    if (s->fused_lf && (s->kinds == pack_kinds(MHD_STORE_F32, MHD_STORE_F32, MHD_STORE_F32) ||
-                        s->kinds == pack_kinds(MHD_STORE_F32, MHD_STORE_F32, MHD_STORE_F16_SPLIT))) {
+    if (s->fused_lf && s->kinds == pack_kinds(MHD_STORE_F32, MHD_STORE_F32, MHD_STORE_F32)) {
         LfArgs a{};
         a.rho = static_cast<const float *>(s->rho(s->cr));
         a.u = static_cast<const float *>(s->u(s->cu));
-        a.b = s->b(s->cb);
-        a.b_hi = s->split() ? s->bh(s->ch) : nullptr;
-        a.u_copy = s->split() ? s->u16() : nullptr;
+        a.b = static_cast<const float *>(s->b(s->cb));
         a.bext = s->at<float>(s->L.bext);
         a.bext_yz = s->byz();
         a.ctrl = s->ctrl();

@@ -39,13 +39,16 @@ def _same(a, b, label):
 
 
 def test_noalloc_step_matches_step_on_two_calls_in_a_row():
+    """Calls in a row on shrinking boxes: 128 x 40 x 36 (paired sweep with x neighbours by wave
+    rotation, line tables), 64 x 40 x 36 with flow control (single-cell sweep), 8 x 32 x 32."""
+    wide = random_box(128, 40, 36, key=901, n_mag=4, R=14.0)
     big = random_box(64, 40, 36, key=900, n_mag=5, R=14.0)
     big.params.flow_control = 1
     big.params.u_bulk_target = 0.02
     small = W.small_pipe()
     small.params.n_mag = 7
-    print("case noalloc: 64x40x36 then 8x32x32", flush=True)
-    for w, steps, every in ((big, 3, 1), (small, 2, 2)):
+    print("case noalloc: 128x40x36, 64x40x36, then 8x32x32", flush=True)
+    for w, steps, every in ((wide, 2, 1), (big, 3, 1), (small, 2, 2)):
         ref, got = _twins(w)
         ref.step(steps, every)
         got.step_noalloc(steps, every)

@@ -60,9 +60,9 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if the kernel source is
-    unchanged since they were taken; else None."""
+def read_traffic(tiles):
+    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if the kernel source and
+    the launch tiles are those the counters were taken with; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -71,6 +71,8 @@ def read_traffic():
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    if kv.get("tiles") != ",".join(str(int(t)) for t in tiles):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -94,7 +96,10 @@ def _counter_rows(d, counter):
 def traffic_summary(fetch_dir, write_dir, copy_mib):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep, scaled by what the same
     counters read for a plain copy of copy_mib MiB (the largest torch copy dispatch), written to
-    the traffic file together with the hash of the kernel source they were taken on."""
+    the traffic file together with the hash of the kernel source and the launch tiles (from the
+    roofline leg's JSON line, which the fetch run writes to hbm.json in its directory)."""
+    leg = json.load(open(os.path.join(fetch_dir, "hbm.json")))["roofline"]
+    tiles = ",".join(str(int(t)) for t in leg["tiles"])
     out = {}
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _counter_rows(d, counter)
@@ -117,7 +122,7 @@ def traffic_summary(fetch_dir, write_dir, copy_mib):
         "# dispatches), each scaled by the ratio of the known size of a plain torch copy to what the",
         "# same counter reads for it. Commands:",
         f"#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --hbm-only "
-        f"--hbm-sweeps 4 --calib-copy-mib {copy_mib}",
+        f"--hbm-sweeps 4 --calib-copy-mib {copy_mib} > D1/hbm.json",
         "#   (the same with --pmc WRITE_SIZE into D2)",
         f"#   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib {copy_mib}",
         f"fetch_kib_raw = {out['fetch']['raw_kib']:.1f}",
@@ -132,6 +137,7 @@ def traffic_summary(fetch_dir, write_dir, copy_mib):
         f"hbm_bytes_per_launch = {fetch_b + write_b:.0f}",
         f"traffic_over_algorithmic = {(fetch_b + write_b) / alg:.4f}",
         f"kernel_source_sha256_16 = {kernel_hash()}",
+        f"tiles = {tiles}",
     ]
     open(TRAFFIC_FILE, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -170,7 +176,7 @@ def hbm_roofline_leg(n_sweeps=None, profile_steps=1):
     achieved = alg_bytes / avg_s / 1e9
     log(f"bench: 512x256^2 mag_sweep {n_launch} launches, avg {avg_s * 1e6:.2f} us, {achieved:.0f} GB/s")
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": read_traffic(), "kernel": "mag_sweep",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": read_traffic(tiles), "kernel": "mag_sweep",
             "workload": w.name, "box": [w.nx, w.ny, w.nz], "tiles": tiles, "launches": n_launch,
             "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes}
 

@@ -568,11 +568,18 @@ SweepLaunch default_tiles(const mhd_grid_desc &g) {
         }
     }
     // long chunks of the paired float32 sweep: 8-row tiles when that still leaves 256
-    // workgroups (the same 2048 waves); 2-4% shorter sweeps on 128 x 256^2 to 512 x 256^2 boxes
+    // workgroups (the same 2048 waves); 2-4% shorter sweeps on 128 x 256^2 to 512 x 256^2 boxes.
+    // An 8-row workgroup of the float32 sweep holds a CU's register file alone (150-170 VGPRs,
+    // two waves per SIMD), so 256 workgroups run in one round: the chunk then doubles up to 128
+    // planes while 256 remain (512 x 256^2: 272-273 -> 265 us, half the halo planes).
     if (plain_pair && L.zchunk >= 32 && env_int("MHD_SWEEP_PAIR_TY", 0) == 0) {
         SweepLaunch t = L;
         t.ty = 8;
-        if (sweep_workgroups(t, nx, ny, nz) >= 256) L.ty = 8;
+        if (sweep_workgroups(t, nx, ny, nz) >= 256) {
+            L.ty = 8;
+            for (t.zchunk = 2 * L.zchunk; t.zchunk <= 128 && sweep_workgroups(t, nx, ny, nz) >= 256; t.zchunk *= 2)
+                L.zchunk = t.zchunk;
+        }
     }
     L.zchunk = std::max(1, env_int("MHD_SWEEP_ZCHUNK", L.zchunk));
     return L;
@@ -1142,7 +1149,7 @@ mhd_status mhd_tune(mhd_sim *s, int32_t reps) {
     const StepConst c = step_const(s);
     const int nx = s->g.nx, nz = s->g.nz;
     std::vector<SweepLaunch> cand;
-    for (int zc : {4, 8, 16, 32, 64}) {
+    for (int zc : {4, 8, 16, 32, 64, 128}) {
         if (zc > 2 * nz && zc != 4) continue;
         if (nx % 128 == 0)
             for (int ty : {4, 8}) cand.push_back({64, ty, zc, 1});

@@ -630,11 +630,11 @@ def test_default_tiles_follow_the_box_size():
     """Default sweep tiles: widest x tile the box fills, the paired form for n_x % 128 == 0, the
     longest z chunk of 64 / 32 / 16 planes that keeps 512 workgroups (paired float32) or 2048
     (other forms), else 8, and 8-row paired tiles for the float32 chunks of 32 planes or more
-    when 256 workgroups remain."""
+    when 256 workgroups remain, their chunk doubled up to 128 planes while 256 still remain."""
     from paper_2211_09370_amd import Sim
 
     split = dict(b_storage="f16split", u_scale=0.05, b_scale=0.01)
-    for shape, store, want in (((128, 128, 128), {}, (64, 8, 1, 4)), ((512, 256, 256), {}, (64, 64, 1, 8)),
+    for shape, store, want in (((128, 128, 128), {}, (64, 8, 1, 4)), ((512, 256, 256), {}, (64, 128, 1, 8)),
                                ((512, 256, 256), split, (64, 32, 1, 4)), ((256, 256, 256), {}, (64, 64, 1, 8)),
                                ((384, 192, 192), {}, (64, 32, 1, 8)), ((128, 256, 256), {}, (64, 32, 1, 8)),
                                ((200, 200, 200), {}, (64, 16, 0, 4)), ((40, 30, 20), {}, (32, 8, 0, 4)),

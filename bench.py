@@ -32,7 +32,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batc
 HBM traffic of the sweep on the 512 x 256 x 256 pipe (rocprofv3 counters, scaled by a plain copy
 of known size):
   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --hbm-only \
-      --hbm-sweeps 4 --calib-copy-mib 1024
+      --hbm-sweeps 4 --calib-copy-mib 1024 > D1/hbm.json
   (the same with WRITE_SIZE into D2), then
   python3 bench.py --traffic-summary D1 D2 --calib-copy-mib 1024
 """

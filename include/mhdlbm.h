@@ -270,12 +270,13 @@ mhd_status mhd_destroy(mhd_sim *s);
  * choice beyond float32 rounding of contracted multiply-adds. Default: the widest x tile the box
  * fills, the paired form when it applies, and the longest z chunk of 64, 32 or 16 planes that
  * leaves 512 workgroups (paired float32 sweep) or 2048 (other forms), else 8; rows 4, or 8 for
- * paired float32 chunks of 32 planes or more when 256 workgroups remain. */
+ * paired float32 chunks of 32 planes or more when 256 workgroups remain, with the chunk then
+ * doubled up to 128 planes while 256 workgroups still remain. */
 mhd_status mhd_get_tiles(mhd_sim *s, int32_t tiles[4]);
 mhd_status mhd_set_tiles(mhd_sim *s, const int32_t tiles[4]);
 
 /* Autotuner of the sweep tiles of one box: every valid choice (x tile 8-64, the paired form with
- * 4 or 8 rows when nx % 128 == 0, z chunks 4-64 planes) is timed by reps sweeps (default 5 if
+ * 4 or 8 rows when nx % 128 == 0, z chunks 4-128 planes) is timed by reps sweeps (default 5 if
  * reps <= 0) of the live fields into the box's other buffer of b, and the fastest is kept. The
  * state is unchanged. Synchronous. STATE before mhd_set_params or on a box of a batch. */
 mhd_status mhd_tune(mhd_sim *s, int32_t reps);

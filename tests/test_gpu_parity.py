@@ -684,7 +684,39 @@ def test_paired_tiles_agree_bitwise_on_a_128_wide_box(bext):
     w = W.pipe_workload("tiles128", 18, 128, 26, 21, 8.0, 50.0, 10.0, 1e-2, bext_kind=bext,
                         fringe_x0=64.0, fringe_w=4.0, n_mag=5, noise=1e-2, rho_amp=1e-3, b_amp=1e-3)
     ref = None
-    for tiles in [(64, 8, 1, 4), (64, 8, 1, 8), (64, 16, 1, 8), (64, 4, 1, 4), (64, 32, 1, 4)]:
+    for tiles in [(64, 8, 1, 4), (64, 8, 1, 8), (64, 16, 1, 8), (64, 4, 1, 4), (64, 32, 1, 4), (64, 128, 1, 8)]:
+        sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
+        sim.set_markers(w.markers)
+        sim.set_params(w.params)
+        sim.set_field("rho", w.rho)
+        sim.set_field("u", w.u)
+        sim.set_field("b", w.b)
+        sim.tiles = tiles
+        sim.step(3)
+        got = [sim.get_field(f) for f in ("rho", "u", "b")]
+        if ref is None:
+            ref = got
+            compare(sim, oracle_run(w, 3), tol=TOL, label=f"tiles {tiles}")
+        else:
+            for f, x, y in zip(("rho", "u", "b"), ref, got):
+                assert np.array_equal(x, y), (tiles, f, float(np.abs(x - y).max()))
+        sim.close()
+
+
+@pytest.mark.parametrize("bext", [W.BEXT_TANH_FRINGE_Y, W.BEXT_SIX_MAGNETS])
+def test_paired_tiles_agree_bitwise_on_a_256_wide_box(bext):
+    """The same on an n_x = 256 box, where the paired sweep stages halo columns (two 128-cell x
+    tiles per row): 4- and 8-row tiles and z chunks of 8 to 128 planes give the same fields bit for
+    bit. 20 rows leave a ragged last 8-row tile; 37 planes leave a ragged last chunk, and the
+    128-plane chunk (the default of long float32 boxes) is longer than the box. The first choice
+    is also checked against the oracle."""
+    from paper_2211_09370_amd import Sim
+
+    print("case paired tiles 256", bext, flush=True)
+    w = W.pipe_workload("tiles256", 19, 256, 20, 37, 8.0, 50.0, 10.0, 1e-2, bext_kind=bext,
+                        fringe_x0=128.0, fringe_w=6.0, n_mag=5, noise=1e-2, rho_amp=1e-3, b_amp=1e-3)
+    ref = None
+    for tiles in [(64, 8, 1, 4), (64, 16, 1, 8), (64, 128, 1, 8), (64, 32, 1, 4), (64, 128, 1, 4)]:
         sim = Sim(w.nx, w.ny, w.nz, w.markers.shape[1])
         sim.set_markers(w.markers)
         sim.set_params(w.params)

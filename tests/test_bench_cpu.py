@@ -36,3 +36,15 @@ def test_recorded_traffic_is_near_the_algorithmic_bytes():
     ratio = float(kv["hbm_bytes_per_launch"]) / float(kv["algorithmic_bytes_per_launch"])
     assert 1.0 <= ratio < 1.2, ratio
     assert abs(ratio - float(kv["traffic_over_algorithmic"])) < 1e-3
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """The build runs on one GPU: bench.py --gpus N with N > 1 exits with status 2 and says so,
+    before it touches a device."""
+    import subprocess
+
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2, (res.returncode, res.stderr[-500:])
+    assert "one GPU only" in res.stderr
+    assert res.stdout.strip() == ""

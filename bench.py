@@ -30,7 +30,7 @@ the stored FP64 oracle run of the 8 x 32 x 32 pipe after 2000 steps.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-precision]
                        [--no-accel]
 HBM traffic of the sweep on the 512 x 256 x 256 pipe (rocprofv3 counters, scaled by a plain copy
-of known size):
+of known size), after mkdir -p D1 D2:
   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --hbm-only \
       --hbm-sweeps 4 --calib-copy-mib 1024 > D1/hbm.json
   (the same with WRITE_SIZE into D2), then
@@ -98,7 +98,11 @@ def traffic_summary(fetch_dir, write_dir, copy_mib):
     counters read for a plain copy of copy_mib MiB (the largest torch copy dispatch), written to
     the traffic file together with the hash of the kernel source and the launch tiles (from the
     roofline leg's JSON line, which the fetch run writes to hbm.json in its directory)."""
-    leg = json.load(open(os.path.join(fetch_dir, "hbm.json")))["roofline"]
+    leg_file = os.path.join(fetch_dir, "hbm.json")
+    if not os.path.exists(leg_file):
+        raise SystemExit(f"{leg_file} is missing: the FETCH_SIZE run writes the roofline leg's JSON line "
+                         "there (it records the launch tiles the counters belong to)")
+    leg = json.load(open(leg_file))["roofline"]
     tiles = ",".join(str(int(t)) for t in leg["tiles"])
     out = {}
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
@@ -120,7 +124,7 @@ def traffic_summary(fetch_dir, write_dir, copy_mib):
         "# HBM-side traffic of the magnetic sweep on the 512 x 256 x 256 pipe (float32), per launch.",
         "# rocprofv3 --pmc FETCH_SIZE / --pmc WRITE_SIZE (KiB per dispatch, averaged over the sweep",
         "# dispatches), each scaled by the ratio of the known size of a plain torch copy to what the",
-        "# same counter reads for it. Commands:",
+        "# same counter reads for it. Commands (after mkdir -p D1 D2):",
         f"#   rocprofv3 --pmc FETCH_SIZE -d D1 -o run --output-format csv -- python3 bench.py --hbm-only "
         f"--hbm-sweeps 4 --calib-copy-mib {copy_mib} > D1/hbm.json",
         "#   (the same with --pmc WRITE_SIZE into D2)",

@@ -243,9 +243,17 @@ __device__ __forceinline__ void ib_cell(T *phi, float scale, float inv_scale, co
         c1 += w * d1[j];
         c2 += w * d2[j];
     }
-    St<T>::st(phi, k, (v0 + c0) * inv_scale);
-    St<T>::st(phi, a.N + k, (v1 + c1) * inv_scale);
-    St<T>::st(phi, 2 * a.N + k, (v2 + c2) * inv_scale);
+    if constexpr (std::is_same<T, float>::value) {
+        // float32 cells go out as agent-scope relaxed atomic stores, which write through the L2
+        // (the same values; the next sweep reads them on every XCD): 128^3 step 6.77 -> 6.71 ms
+        __hip_atomic_store(phi + k, (v0 + c0) * inv_scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(phi + a.N + k, (v1 + c1) * inv_scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(phi + 2 * a.N + k, (v2 + c2) * inv_scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        St<T>::st(phi, k, (v0 + c0) * inv_scale);
+        St<T>::st(phi, a.N + k, (v1 + c1) * inv_scale);
+        St<T>::st(phi, 2 * a.N + k, (v2 + c2) * inv_scale);
+    }
     if (a.copy) {  // float16 copy of the corrected field (the split form's u for the sweeps)
         __half *cp = (__half *)a.copy;
         cp[k] = __float2half_rn((v0 + c0) * a.copy_inv);
@@ -277,9 +285,10 @@ __global__ void __launch_bounds__(kIbThreads) k_ib_interp(const T *phi, float sc
     } else {
         ib_marker(phi, scale, a, j, GeneralTaps{a.tap_cell, a.tap_w, a.M, j}, d0, d1, d2);
     }
-    a.delta[j] = d0;
-    a.delta[a.M + j] = d1;
-    a.delta[2 * a.M + j] = d2;
+    // corrections written through the L2 as well (agent-scope relaxed atomic stores)
+    __hip_atomic_store(a.delta + j, d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.delta + a.M + j, d1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.delta + 2 * a.M + j, d2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T, bool BATCH>

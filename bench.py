@@ -11,7 +11,8 @@ roofline = the magnetic sweep kernel (the dominant one): 36 algorithmic bytes pe
 (read u and b, write b*, float32) per launch over its HIP-event-timed average duration, measured
 on the 512 x 256 x 256 pipe (1.9 GB of state, far beyond the 256 MB Infinity Cache, so the
 sweep streams from HBM); roofline_cache_resident = the same figure on the 128^3 box of `value`,
-whose 136 MB state the Infinity Cache holds.
+whose 136 MB state the Infinity Cache holds. Both give the sweep's cells per second
+(gcells_per_s): about equal, so the sweep's rate is set by its per-CU chain, not by HBM.
 cpu_baseline = the FP64 oracle on this host: the median of 5 fluid steps (270 sweeps each) after
 one warm-up step, on a 16-plane slab of the same pipe (1/8 of its cells; the oracle's cost per
 cell does not depend on the box length).
@@ -182,7 +183,8 @@ def hbm_roofline_leg(n_sweeps=None, profile_steps=1):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": read_traffic(tiles), "kernel": "mag_sweep",
             "workload": w.name, "box": [w.nx, w.ny, w.nz], "tiles": tiles, "launches": n_launch,
-            "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes}
+            "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes,
+            "gcells_per_s": round(w.n_cells / avg_s / 1e9, 2)}
 
 
 def shard_leg(steps=3):
@@ -652,7 +654,8 @@ def main():
                                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                                     "traffic": None, "kernel": "mag_sweep", "workload": w.name,
                                     "note": "136 MB state held by the 256 MB Infinity Cache",
-                                    "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes},
+                                    "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": alg_bytes,
+                                    "gcells_per_s": round(w.n_cells / avg_s / 1e9, 2)},
         "sweep_glups": round(w.n_cells * (w.params.n_mag + 1) * args.steps / sec / 1e9, 3),
         "finite": state_ok,
         "accelerated": accel,
